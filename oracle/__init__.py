@@ -1,0 +1,285 @@
+"""CPU oracle for the sparse-octree Barnes-Hut tree-code (Bedorf, Gaburov &
+Portegies Zwart, arXiv:1106.1900): a plain single-threaded float64 C library
+(``bh_oracle.c``) and this ctypes wrapper.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package.  It shares no code with the HIP
+library; the two meet only through the arrays of the ``workloads`` generators.
+
+What each function follows in the paper:
+
+* ``domain``/``keys``/``interleave`` - App. B (integer map and Morton key).
+* ``argsort`` - App. A (stable radix sort = stable ascending order of keys).
+* ``Tree`` - Sect. 2.1 (level-by-level cells, links), Sect. 2.2 (groups),
+  Sect. 3.2 (float64 monopole and quadrupole moments).
+* ``Tree.rcrit``/``Tree.mac_accept`` - Sect. 3.3, Eq. (1).
+* ``Tree.walk_counts``/``Tree.group_lists``/``Tree.forces`` - Sect. 2.2
+  breadth-first group walk with float64 evaluation.
+* ``direct`` - the direct-summation reference of Sect. 4.2.1 (Eq. (2)).
+* ``kdk_step`` - Sect. 3.1 leapfrog; ``energy`` - Eq. (3) ingredients.
+"""
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bh_oracle.c")
+_LIB = os.path.join(_HERE, "_bh_oracle.so")
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle with gcc (no fused multiply-add)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], cwd=_HERE)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _P(t):
+    return ctypes.POINTER(t)
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    L = ctypes.CDLL(_LIB)
+    d, f, i64, u64, u32, u8, i32 = (ctypes.c_double, ctypes.c_float, ctypes.c_int64,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint8,
+                                    ctypes.c_int32)
+    vp = ctypes.c_void_p
+    sig = {
+        "orc_interleave": (u64, [u32, u32, u32]),
+        "orc_domain": (ctypes.c_int, [vp, i64, vp, vp, vp]),
+        "orc_keys": (None, [vp, i64, vp, d, vp, vp]),
+        "orc_argsort": (ctypes.c_int, [vp, i64, vp]),
+        "orc_build": (vp, [vp, vp, i64, ctypes.c_int, ctypes.c_int]),
+        "orc_free": (None, [vp]),
+        "orc_n": (i64, [vp]),
+        "orc_ncells": (i64, [vp]),
+        "orc_ngroups": (i64, [vp]),
+        "orc_depth": (ctypes.c_int, [vp]),
+        "orc_get_domain": (None, [vp, vp, vp, vp]),
+        "orc_get_order": (None, [vp, vp, vp]),
+        "orc_get_cells": (None, [vp] + [vp] * 8),
+        "orc_get_groups": (None, [vp, vp, vp, vp, vp]),
+        "orc_get_moments": (None, [vp, vp, vp, vp]),
+        "orc_rcrit": (None, [vp, f, vp, vp]),
+        "orc_mac_accept": (ctypes.c_int, [vp, i64, i64, f]),
+        "orc_walk_counts": (ctypes.c_int, [vp, f, vp, vp]),
+        "orc_group_lists": (i64, [vp, f, i64, vp, i64, vp, i64, vp]),
+        "orc_forces": (ctypes.c_int, [vp, f, f, vp, i64, vp, vp, vp, vp]),
+        "orc_direct": (None, [vp, vp, i64, f, vp, i64, vp, vp]),
+        "orc_kdk_step": (ctypes.c_int, [vp, vp, vp, i64, vp, vp, d, f, f,
+                                        ctypes.c_int, ctypes.c_int]),
+        "orc_energy": (None, [vp, vp, vp, i64, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    del i32, u8
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        raise ValueError("expected shape %s, got %s" % (shape, a.shape))
+    return a
+
+
+def interleave(qx, qy, qz):
+    return int(lib().orc_interleave(qx, qy, qz))
+
+
+def domain(pos):
+    pos = _f64(pos)
+    lo = np.zeros(3)
+    L = ctypes.c_double()
+    scale = ctypes.c_double()
+    st = lib().orc_domain(_ptr(pos), pos.shape[0], _ptr(lo), ctypes.byref(L), ctypes.byref(scale))
+    if st:
+        raise ValueError("non-finite coordinate")
+    return lo, L.value, scale.value
+
+
+def keys(pos):
+    """Keys and integer coordinates of every point, input order."""
+    pos = _f64(pos)
+    lo, L, scale = domain(pos)
+    n = pos.shape[0]
+    key = np.zeros(n, dtype=np.uint64)
+    q = np.zeros((n, 3), dtype=np.uint32)
+    lib().orc_keys(_ptr(pos), n, _ptr(lo), scale, _ptr(key), _ptr(q))
+    return key, q
+
+
+def argsort(key):
+    key = np.ascontiguousarray(key, dtype=np.uint64)
+    perm = np.zeros(key.shape[0], dtype=np.int64)
+    if lib().orc_argsort(_ptr(key), key.shape[0], _ptr(perm)):
+        raise MemoryError
+    return perm
+
+
+class Tree:
+    """The canonical tree of a particle set (Sect. 2.1-2.2, 3.2)."""
+
+    def __init__(self, pos, mass, nleaf=16, ncrit=64):
+        self.pos = _f64(pos)
+        self.mass = _f64(mass)
+        n = self.pos.shape[0]
+        if self.pos.shape != (n, 3) or self.mass.shape != (n,):
+            raise ValueError("pos must be (n, 3), mass (n,)")
+        self.n = n
+        self.nleaf = nleaf
+        self.ncrit = ncrit
+        h = lib().orc_build(_ptr(self.pos), _ptr(self.mass), n, nleaf, ncrit)
+        if not h:
+            raise ValueError("oracle build failed (bad input or out of memory)")
+        self._h = ctypes.c_void_p(h)
+        L = lib()
+        self.ncells = int(L.orc_ncells(self._h))
+        self.ngroups = int(L.orc_ngroups(self._h))
+        self.depth = int(L.orc_depth(self._h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_free(h)
+            self._h = None
+
+    def domain(self):
+        lo = np.zeros(3)
+        L = ctypes.c_double()
+        s = ctypes.c_double()
+        lib().orc_get_domain(self._h, _ptr(lo), ctypes.byref(L), ctypes.byref(s))
+        return lo, L.value, s.value
+
+    def order(self):
+        perm = np.zeros(self.n, dtype=np.int64)
+        key = np.zeros(self.n, dtype=np.uint64)
+        lib().orc_get_order(self._h, _ptr(perm), _ptr(key))
+        return perm, key
+
+    def cells(self):
+        c = self.ncells
+        out = dict(
+            level=np.zeros(c, np.uint8), prefix=np.zeros(c, np.uint64),
+            first=np.zeros(c, np.int64), count=np.zeros(c, np.int64),
+            is_leaf=np.zeros(c, np.uint8), parent=np.zeros(c, np.int64),
+            child=np.zeros(c, np.int64), nchild=np.zeros(c, np.int32))
+        lib().orc_get_cells(self._h, *[_ptr(out[k]) for k in
+                                       ("level", "prefix", "first", "count", "is_leaf",
+                                        "parent", "child", "nchild")])
+        return out
+
+    def groups(self):
+        g = self.ngroups
+        out = dict(first=np.zeros(g, np.int64), count=np.zeros(g, np.int64),
+                   centre=np.zeros((g, 3)), half=np.zeros((g, 3), np.float32))
+        lib().orc_get_groups(self._h, _ptr(out["first"]), _ptr(out["count"]),
+                             _ptr(out["centre"]), _ptr(out["half"]))
+        return out
+
+    def moments(self):
+        c = self.ncells
+        out = dict(mass=np.zeros(c), com=np.zeros((c, 3)), S=np.zeros((c, 6)))
+        lib().orc_get_moments(self._h, _ptr(out["mass"]), _ptr(out["com"]), _ptr(out["S"]))
+        return out
+
+    def rcrit(self, theta):
+        r2 = np.zeros(self.ncells, np.float32)
+        centre = np.zeros((self.ncells, 3))
+        lib().orc_rcrit(self._h, float(theta), _ptr(r2), _ptr(centre))
+        return r2, centre
+
+    def mac_accept(self, g, c, rcrit2_c):
+        return bool(lib().orc_mac_accept(self._h, int(g), int(c), float(rcrit2_c)))
+
+    def walk_counts(self, theta):
+        npp = np.zeros(self.ngroups, np.int64)
+        npc = np.zeros(self.ngroups, np.int64)
+        if lib().orc_walk_counts(self._h, float(theta), _ptr(npp), _ptr(npc)):
+            raise MemoryError
+        return npp, npc
+
+    def group_lists(self, theta, g):
+        cap = self.ncells
+        pc = np.zeros(cap, np.int64)
+        pp = np.zeros(cap, np.int64)
+        npl = ctypes.c_int64()
+        r = lib().orc_group_lists(self._h, float(theta), int(g), _ptr(pc), cap, _ptr(pp), cap,
+                                  ctypes.byref(npl))
+        if r < 0:
+            raise RuntimeError("group_lists failed")
+        return pc[:r].copy(), pp[:npl.value].copy()
+
+    def forces(self, theta, eps, groups=None):
+        """float64 tree forces, input order; rows of unselected groups are NaN."""
+        n = self.n
+        acc = np.full((n, 3), np.nan)
+        pot = np.full(n, np.nan)
+        aabs = np.full(n, np.nan)
+        pabs = np.full(n, np.nan)
+        if groups is None:
+            gp, ng = None, 0
+        else:
+            garr = np.ascontiguousarray(groups, dtype=np.int64)
+            gp, ng = _ptr(garr), garr.shape[0]
+        st = lib().orc_forces(self._h, float(theta), float(eps), gp, ng, _ptr(acc), _ptr(pot),
+                              _ptr(aabs), _ptr(pabs))
+        if st:
+            raise RuntimeError("oracle forces failed (%d)" % st)
+        return acc, pot, aabs, pabs
+
+
+def direct(pos, mass, eps, targets=None):
+    """float64 direct summation on the given targets (all if None)."""
+    pos = _f64(pos)
+    mass = _f64(mass)
+    n = pos.shape[0]
+    tgt = np.arange(n, dtype=np.int64) if targets is None else np.ascontiguousarray(
+        targets, dtype=np.int64)
+    acc = np.zeros((tgt.shape[0], 3))
+    pot = np.zeros(tgt.shape[0])
+    lib().orc_direct(_ptr(pos), _ptr(mass), n, float(eps), _ptr(tgt), tgt.shape[0],
+                     _ptr(acc), _ptr(pot))
+    return acc, pot
+
+
+def kdk_step(pos, vel, mass, acc, pot, dt, theta, eps, nleaf=16, ncrit=64):
+    """One kick-drift-kick step in place (float64 arrays, input order)."""
+    for a in (pos, vel, acc, pot):
+        if a.dtype != np.float64 or not a.flags.c_contiguous:
+            raise ValueError("state arrays must be contiguous float64")
+    mass = _f64(mass)
+    st = lib().orc_kdk_step(_ptr(pos), _ptr(vel), _ptr(mass), pos.shape[0], _ptr(acc),
+                            _ptr(pot), float(dt), float(theta), float(eps), nleaf, ncrit)
+    if st:
+        raise RuntimeError("oracle kdk failed (%d)" % st)
+
+
+def energy(vel, mass, pot):
+    vel = _f64(vel)
+    mass = _f64(mass)
+    pot = _f64(pot)
+    out = np.zeros(6)
+    lib().orc_energy(_ptr(vel), _ptr(mass), _ptr(pot), mass.shape[0], _ptr(out))
+    return out

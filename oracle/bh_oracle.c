@@ -1,0 +1,684 @@
+/*
+ * bh_oracle.c - CPU oracle for the sparse-octree Barnes-Hut tree-code of Bedorf,
+ * Gaburov & Portegies Zwart (arXiv:1106.1900).  TEST INFRASTRUCTURE ONLY; see
+ * bh_oracle.h for the contract.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math (no fused multiply-add,
+ * no reassociation).  Every loop below runs in the order written.
+ */
+#include "bh_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define QMAX 1048575u            /* 2^20 - 1 */
+#define QSPAN 1048576.0          /* 2^20 */
+
+struct orc_tree {
+    int64_t n;
+    int nleaf, ncrit;
+    double lo[3], L, scale;
+    /* particles in sorted order */
+    int64_t *perm;
+    uint64_t *key;
+    uint32_t *q;        /* [n][3] */
+    double *x;          /* [n][3] */
+    double *m;          /* [n] */
+    /* cells */
+    int64_t ncells, cap;
+    uint8_t *level;
+    uint64_t *prefix;
+    int64_t *first, *count, *parent, *child;
+    uint8_t *leaf;
+    int32_t *nchild;
+    double *M, *com, *S; /* [c], [c][3], [c][6] */
+    /* groups */
+    int64_t ngroups;
+    int64_t *gfirst, *gcount;
+    double *gc;         /* [g][3] */
+    float *gh;          /* [g][3] */
+    int depth;
+};
+
+/* ------------------------------------------------------------------------- */
+/* App. B: integer coordinates and Morton keys.                              */
+
+uint64_t orc_interleave(uint32_t qx, uint32_t qy, uint32_t qz)
+{
+    uint64_t k = 0;
+    for (int b = 0; b < ORC_MAX_LEVEL; ++b) {
+        k |= (uint64_t)((qx >> b) & 1u) << (3 * b);
+        k |= (uint64_t)((qy >> b) & 1u) << (3 * b + 1);
+        k |= (uint64_t)((qz >> b) & 1u) << (3 * b + 2);
+    }
+    return k;
+}
+
+int orc_domain(const double *pos, int64_t n, double lo[3], double *L, double *scale)
+{
+    double hi[3];
+    for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            double v = pos[3 * i + k];
+            if (!isfinite(v)) return -1;
+            if (v < lo[k]) lo[k] = v;
+            if (v > hi[k]) hi[k] = v;
+        }
+    double side = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double e = hi[k] - lo[k];
+        if (e > side) side = e;
+    }
+    if (side == 0.0) side = 1.0;
+    *L = side;
+    *scale = QSPAN / side;
+    return 0;
+}
+
+static uint32_t coord_to_int(double x, double lo, double scale)
+{
+    double d = x - lo;
+    double f = d * scale;
+    if (f >= (double)QMAX) return QMAX;
+    return (uint32_t)floor(f);
+}
+
+void orc_keys(const double *pos, int64_t n, const double lo[3], double scale,
+              uint64_t *key, uint32_t *q)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t c[3];
+        for (int k = 0; k < 3; ++k) c[k] = coord_to_int(pos[3 * i + k], lo[k], scale);
+        key[i] = orc_interleave(c[0], c[1], c[2]);
+        if (q) { q[3 * i] = c[0]; q[3 * i + 1] = c[1]; q[3 * i + 2] = c[2]; }
+    }
+}
+
+/* Stable merge sort of indices by key. */
+int orc_argsort(const uint64_t *key, int64_t n, int64_t *perm)
+{
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!tmp) return -2;
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    int64_t *src = perm, *dst = tmp;
+    for (int64_t w = 1; w < n; w *= 2) {
+        for (int64_t s = 0; s < n; s += 2 * w) {
+            int64_t a = s, am = s + w < n ? s + w : n;
+            int64_t b = am, bm = s + 2 * w < n ? s + 2 * w : n;
+            int64_t o = s;
+            while (a < am && b < bm) {
+                /* take from the left run on ties: keeps input order */
+                if (key[src[b]] < key[src[a]]) dst[o++] = src[b++];
+                else dst[o++] = src[a++];
+            }
+            while (a < am) dst[o++] = src[a++];
+            while (b < bm) dst[o++] = src[b++];
+        }
+        int64_t *t = src; src = dst; dst = t;
+    }
+    if (src != perm) memcpy(perm, src, sizeof(int64_t) * (size_t)n);
+    free(tmp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sect. 2.1: level-by-level cell construction and linking.                  */
+
+static int grow_cells(orc_tree *t)
+{
+    int64_t cap = t->cap ? 2 * t->cap : 64;
+#define GROW(field, type) do {                                        \
+        type *p = (type *)realloc(t->field, sizeof(type) * (size_t)cap);  \
+        if (!p) return -2;                                                \
+        t->field = p;                                                     \
+    } while (0)
+    GROW(level, uint8_t);
+    GROW(prefix, uint64_t);
+    GROW(first, int64_t);
+    GROW(count, int64_t);
+    GROW(parent, int64_t);
+    GROW(child, int64_t);
+    GROW(leaf, uint8_t);
+    GROW(nchild, int32_t);
+#undef GROW
+    t->cap = cap;
+    return 0;
+}
+
+static int64_t add_cell(orc_tree *t, int lev, uint64_t prefix, int64_t first,
+                        int64_t count, int64_t parent)
+{
+    if (t->ncells == t->cap && grow_cells(t)) return -1;
+    int64_t c = t->ncells++;
+    t->level[c] = (uint8_t)lev;
+    t->prefix[c] = prefix;
+    t->first[c] = first;
+    t->count[c] = count;
+    t->parent[c] = parent;
+    t->leaf[c] = (uint8_t)(count <= t->nleaf || lev == ORC_MAX_LEVEL);
+    t->child[c] = -1;
+    t->nchild[c] = 0;
+    return c;
+}
+
+/* Open nodes of level l-1 are split, in array order, into maximal runs of equal
+ * level-l key prefix; each run becomes a child cell, leaf if it holds at most
+ * nleaf particles or sits at the deepest level (the key has no more bits). */
+static int build_cells(orc_tree *t)
+{
+    int64_t n = t->n;
+    int64_t *open = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!open || !next) { free(open); free(next); return -2; }
+    int64_t nopen = 0;
+    if (add_cell(t, 0, 0, 0, n, -1) < 0) { free(open); free(next); return -2; }
+    if (!t->leaf[0]) open[nopen++] = 0;
+    t->depth = 0;
+    for (int l = 1; l <= ORC_MAX_LEVEL && nopen > 0; ++l) {
+        int shift = 3 * (ORC_MAX_LEVEL - l);
+        int64_t nnext = 0;
+        for (int64_t k = 0; k < nopen; ++k) {
+            int64_t node = open[k];
+            int64_t s = t->first[node], e = s + t->count[node];
+            int64_t c0 = t->ncells;
+            int64_t i = s;
+            while (i < e) {
+                uint64_t p = t->key[i] >> shift;
+                int64_t j = i + 1;
+                while (j < e && (t->key[j] >> shift) == p) ++j;
+                int64_t c = add_cell(t, l, p, i, j - i, node);
+                if (c < 0) { free(open); free(next); return -2; }
+                if (!t->leaf[c]) next[nnext++] = c;
+                i = j;
+            }
+            t->child[node] = c0;
+            t->nchild[node] = (int32_t)(t->ncells - c0);
+        }
+        t->depth = l;
+        int64_t *sw = open; open = next; next = sw;
+        nopen = nnext;
+    }
+    free(open);
+    free(next);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sect. 2.2: groups.  A cell is a group if it holds at most ncrit particles   */
+/* and its parent holds more (or it is the root); a leaf that still holds more */
+/* than ncrit particles is cut into runs of ncrit consecutive particles.       */
+
+static int build_groups(orc_tree *t)
+{
+    int64_t n = t->n;
+    uint8_t *start = (uint8_t *)calloc((size_t)n + 1, 1);
+    if (!start) return -2;
+    for (int64_t c = 0; c < t->ncells; ++c) {
+        int64_t cnt = t->count[c];
+        int top = (c == 0) || (t->count[t->parent[c]] > t->ncrit);
+        if (cnt <= t->ncrit && top) start[t->first[c]] = 1;
+        else if (t->leaf[c] && cnt > t->ncrit) {
+            for (int64_t o = 0; o < cnt; o += t->ncrit) start[t->first[c] + o] = 1;
+        }
+    }
+    int64_t ng = 0;
+    for (int64_t i = 0; i < n; ++i) ng += start[i];
+    t->ngroups = ng;
+    t->gfirst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ng + 1));
+    t->gcount = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ng + 1));
+    t->gc = (double *)malloc(sizeof(double) * 3 * (size_t)(ng + 1));
+    t->gh = (float *)malloc(sizeof(float) * 3 * (size_t)(ng + 1));
+    if (!t->gfirst || !t->gcount || !t->gc || !t->gh) { free(start); return -2; }
+    int64_t g = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (start[i]) { ++g; t->gfirst[g] = i; t->gcount[g] = 0; }
+        t->gcount[g] += 1;
+    }
+    free(start);
+    for (g = 0; g < ng; ++g) {
+        double bmin[3], bmax[3];
+        for (int k = 0; k < 3; ++k) { bmin[k] = INFINITY; bmax[k] = -INFINITY; }
+        for (int64_t i = t->gfirst[g]; i < t->gfirst[g] + t->gcount[g]; ++i)
+            for (int k = 0; k < 3; ++k) {
+                double v = t->x[3 * i + k];
+                if (v < bmin[k]) bmin[k] = v;
+                if (v > bmax[k]) bmax[k] = v;
+            }
+        for (int k = 0; k < 3; ++k) {
+            t->gc[3 * g + k] = 0.5 * (bmin[k] + bmax[k]);
+            t->gh[3 * g + k] = (float)(0.5 * (bmax[k] - bmin[k]));
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sect. 3.2: monopole and quadrupole moments in float64, leaves from their    */
+/* particles, nodes from their children, deepest cells first.                  */
+
+static void build_moments(orc_tree *t)
+{
+    for (int64_t c = t->ncells - 1; c >= 0; --c) {
+        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        double *com = t->com + 3 * c, *S = t->S + 6 * c;
+        if (t->leaf[c]) {
+            int64_t s = t->first[c], e = s + t->count[c];
+            for (int64_t j = s; j < e; ++j) M = M + t->m[j];
+            for (int64_t j = s; j < e; ++j) {
+                sx = sx + t->m[j] * t->x[3 * j];
+                sy = sy + t->m[j] * t->x[3 * j + 1];
+                sz = sz + t->m[j] * t->x[3 * j + 2];
+            }
+            com[0] = sx / M; com[1] = sy / M; com[2] = sz / M;
+            for (int a = 0; a < 6; ++a) S[a] = 0.0;
+            for (int64_t j = s; j < e; ++j) {
+                double dx = t->x[3 * j] - com[0];
+                double dy = t->x[3 * j + 1] - com[1];
+                double dz = t->x[3 * j + 2] - com[2];
+                double mj = t->m[j];
+                S[0] += mj * dx * dx; S[1] += mj * dy * dy; S[2] += mj * dz * dz;
+                S[3] += mj * dx * dy; S[4] += mj * dx * dz; S[5] += mj * dy * dz;
+            }
+        } else {
+            int64_t s = t->child[c], e = s + t->nchild[c];
+            for (int64_t k = s; k < e; ++k) M = M + t->M[k];
+            for (int64_t k = s; k < e; ++k) {
+                sx = sx + t->M[k] * t->com[3 * k];
+                sy = sy + t->M[k] * t->com[3 * k + 1];
+                sz = sz + t->M[k] * t->com[3 * k + 2];
+            }
+            com[0] = sx / M; com[1] = sy / M; com[2] = sz / M;
+            for (int a = 0; a < 6; ++a) S[a] = 0.0;
+            for (int64_t k = s; k < e; ++k) {
+                double ex = t->com[3 * k] - com[0];
+                double ey = t->com[3 * k + 1] - com[1];
+                double ez = t->com[3 * k + 2] - com[2];
+                double Mk = t->M[k];
+                const double *Sk = t->S + 6 * k;
+                S[0] += Sk[0] + Mk * ex * ex; S[1] += Sk[1] + Mk * ey * ey;
+                S[2] += Sk[2] + Mk * ez * ez; S[3] += Sk[3] + Mk * ex * ey;
+                S[4] += Sk[4] + Mk * ex * ez; S[5] += Sk[5] + Mk * ey * ez;
+            }
+        }
+        t->M[c] = M;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+
+void orc_free(orc_tree *t)
+{
+    if (!t) return;
+    free(t->perm); free(t->key); free(t->q); free(t->x); free(t->m);
+    free(t->level); free(t->prefix); free(t->first); free(t->count);
+    free(t->parent); free(t->child); free(t->leaf); free(t->nchild);
+    free(t->M); free(t->com); free(t->S);
+    free(t->gfirst); free(t->gcount); free(t->gc); free(t->gh);
+    free(t);
+}
+
+orc_tree *orc_build(const double *pos, const double *mass, int64_t n, int nleaf, int ncrit)
+{
+    if (!pos || !mass || n < 1 || nleaf < 1 || ncrit < 1) return NULL;
+    orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
+    if (!t) return NULL;
+    t->n = n; t->nleaf = nleaf; t->ncrit = ncrit;
+    if (orc_domain(pos, n, t->lo, &t->L, &t->scale)) { orc_free(t); return NULL; }
+    uint64_t *key_in = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    uint32_t *q_in = (uint32_t *)malloc(sizeof(uint32_t) * 3 * (size_t)n);
+    t->perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    t->key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    t->q = (uint32_t *)malloc(sizeof(uint32_t) * 3 * (size_t)n);
+    t->x = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    t->m = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!key_in || !q_in || !t->perm || !t->key || !t->q || !t->x || !t->m) goto fail;
+    orc_keys(pos, n, t->lo, t->scale, key_in, q_in);
+    if (orc_argsort(key_in, n, t->perm)) goto fail;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t p = t->perm[i];
+        t->key[i] = key_in[p];
+        t->m[i] = mass[p];
+        for (int k = 0; k < 3; ++k) {
+            t->q[3 * i + k] = q_in[3 * p + k];
+            t->x[3 * i + k] = pos[3 * p + k];
+        }
+    }
+    free(key_in); key_in = NULL;
+    free(q_in); q_in = NULL;
+    if (build_cells(t)) goto fail;
+    t->M = (double *)malloc(sizeof(double) * (size_t)t->ncells);
+    t->com = (double *)malloc(sizeof(double) * 3 * (size_t)t->ncells);
+    t->S = (double *)malloc(sizeof(double) * 6 * (size_t)t->ncells);
+    if (!t->M || !t->com || !t->S) goto fail;
+    build_moments(t);
+    if (build_groups(t)) goto fail;
+    return t;
+fail:
+    free(key_in);
+    free(q_in);
+    orc_free(t);
+    return NULL;
+}
+
+int64_t orc_n(const orc_tree *t) { return t->n; }
+int64_t orc_ncells(const orc_tree *t) { return t->ncells; }
+int64_t orc_ngroups(const orc_tree *t) { return t->ngroups; }
+int orc_depth(const orc_tree *t) { return t->depth; }
+
+void orc_get_domain(const orc_tree *t, double lo[3], double *L, double *scale)
+{
+    for (int k = 0; k < 3; ++k) lo[k] = t->lo[k];
+    *L = t->L;
+    *scale = t->scale;
+}
+
+void orc_get_order(const orc_tree *t, int64_t *perm, uint64_t *key)
+{
+    if (perm) memcpy(perm, t->perm, sizeof(int64_t) * (size_t)t->n);
+    if (key) memcpy(key, t->key, sizeof(uint64_t) * (size_t)t->n);
+}
+
+void orc_get_cells(const orc_tree *t, uint8_t *level, uint64_t *prefix,
+                   int64_t *first, int64_t *count, uint8_t *is_leaf,
+                   int64_t *parent, int64_t *child, int32_t *nchild)
+{
+    size_t c = (size_t)t->ncells;
+    if (level) memcpy(level, t->level, c);
+    if (prefix) memcpy(prefix, t->prefix, 8 * c);
+    if (first) memcpy(first, t->first, 8 * c);
+    if (count) memcpy(count, t->count, 8 * c);
+    if (is_leaf) memcpy(is_leaf, t->leaf, c);
+    if (parent) memcpy(parent, t->parent, 8 * c);
+    if (child) memcpy(child, t->child, 8 * c);
+    if (nchild) memcpy(nchild, t->nchild, 4 * c);
+}
+
+void orc_get_groups(const orc_tree *t, int64_t *gfirst, int64_t *gcount,
+                    double *centre, float *half)
+{
+    size_t g = (size_t)t->ngroups;
+    if (gfirst) memcpy(gfirst, t->gfirst, 8 * g);
+    if (gcount) memcpy(gcount, t->gcount, 8 * g);
+    if (centre) memcpy(centre, t->gc, 24 * g);
+    if (half) memcpy(half, t->gh, 12 * g);
+}
+
+void orc_get_moments(const orc_tree *t, double *mass, double *com, double *S)
+{
+    size_t c = (size_t)t->ncells;
+    if (mass) memcpy(mass, t->M, 8 * c);
+    if (com) memcpy(com, t->com, 24 * c);
+    if (S) memcpy(S, t->S, 48 * c);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sect. 3.3, Eq. (1): d > l/theta + delta.                                    */
+
+void orc_rcrit(const orc_tree *t, float theta, float *rcrit2, double *centre)
+{
+    for (int64_t c = 0; c < t->ncells; ++c) {
+        int lev = t->level[c];
+        double l = ldexp(t->L, -lev);
+        const uint32_t *q = t->q + 3 * t->first[c];
+        double g[3];
+        for (int k = 0; k < 3; ++k) {
+            uint32_t p = q[k] >> (ORC_MAX_LEVEL - lev);
+            g[k] = t->lo[k] + ((double)p + 0.5) * l;
+        }
+        double dx = t->com[3 * c] - g[0];
+        double dy = t->com[3 * c + 1] - g[1];
+        double dz = t->com[3 * c + 2] - g[2];
+        double delta = sqrt((dx * dx + dy * dy) + dz * dz);
+        double r = l / (double)theta + delta;
+        if (rcrit2) rcrit2[c] = (float)(r * r);
+        if (centre) { centre[3 * c] = g[0]; centre[3 * c + 1] = g[1]; centre[3 * c + 2] = g[2]; }
+    }
+}
+
+/* d is the distance from the cell's centre of mass to the group's box, taken in
+ * float32 on offsets from the group centre; accept when d^2 > r_crit^2. */
+int orc_mac_accept(const orc_tree *t, int64_t g, int64_t c, float rcrit2_c)
+{
+    float u[3];
+    for (int k = 0; k < 3; ++k) {
+        float o = (float)(t->com[3 * c + k] - t->gc[3 * g + k]);
+        float d = fabsf(o) - t->gh[3 * g + k];
+        u[k] = d > 0.0f ? d : 0.0f;
+    }
+    float d2 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+    return d2 > rcrit2_c;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sect. 2.2: breadth-first walk of one group.                                 */
+
+typedef struct { int64_t *v; int64_t n, cap; } ivec;
+
+static int ivec_push(ivec *a, int64_t x)
+{
+    if (a->n == a->cap) {
+        int64_t cap = a->cap ? 2 * a->cap : 256;
+        int64_t *p = (int64_t *)realloc(a->v, sizeof(int64_t) * (size_t)cap);
+        if (!p) return -1;
+        a->v = p; a->cap = cap;
+    }
+    a->v[a->n++] = x;
+    return 0;
+}
+
+/* Fills pc (accepted cells) and ppl (opened leaves) for group g. */
+static int walk_group(const orc_tree *t, const float *rc2, int64_t g, ivec *pc, ivec *ppl,
+                      ivec *cur, ivec *nxt)
+{
+    pc->n = 0; ppl->n = 0; cur->n = 0; nxt->n = 0;
+    if (ivec_push(cur, 0)) return -2;
+    while (cur->n > 0) {
+        nxt->n = 0;
+        for (int64_t k = 0; k < cur->n; ++k) {
+            int64_t c = cur->v[k];
+            if (orc_mac_accept(t, g, c, rc2[c])) {
+                if (ivec_push(pc, c)) return -2;
+            } else if (t->leaf[c]) {
+                if (ivec_push(ppl, c)) return -2;
+            } else {
+                for (int64_t ch = t->child[c]; ch < t->child[c] + t->nchild[c]; ++ch)
+                    if (ivec_push(nxt, ch)) return -2;
+            }
+        }
+        ivec sw = *cur; *cur = *nxt; *nxt = sw;
+    }
+    return 0;
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+int orc_walk_counts(const orc_tree *t, float theta, int64_t *npp, int64_t *npc)
+{
+    float *rc2 = (float *)malloc(sizeof(float) * (size_t)t->ncells);
+    if (!rc2) return -2;
+    orc_rcrit(t, theta, rc2, NULL);
+    ivec pc = {0}, ppl = {0}, cur = {0}, nxt = {0};
+    int st = 0;
+    for (int64_t g = 0; g < t->ngroups && !st; ++g) {
+        st = walk_group(t, rc2, g, &pc, &ppl, &cur, &nxt);
+        int64_t s = 0;
+        for (int64_t k = 0; k < ppl.n; ++k) s += t->count[ppl.v[k]];
+        npp[g] = s;
+        npc[g] = pc.n;
+    }
+    free(pc.v); free(ppl.v); free(cur.v); free(nxt.v); free(rc2);
+    return st;
+}
+
+int64_t orc_group_lists(const orc_tree *t, float theta, int64_t g,
+                        int64_t *pc_out, int64_t pc_cap,
+                        int64_t *pp_out, int64_t pp_cap, int64_t *npp_leaves)
+{
+    if (g < 0 || g >= t->ngroups) return -1;
+    float *rc2 = (float *)malloc(sizeof(float) * (size_t)t->ncells);
+    if (!rc2) return -2;
+    orc_rcrit(t, theta, rc2, NULL);
+    ivec pc = {0}, ppl = {0}, cur = {0}, nxt = {0};
+    int64_t ret = walk_group(t, rc2, g, &pc, &ppl, &cur, &nxt);
+    if (ret == 0) {
+        if (pc.n > pc_cap || ppl.n > pp_cap) ret = -1;
+        else {
+            qsort(pc.v, (size_t)pc.n, sizeof(int64_t), cmp_i64);
+            qsort(ppl.v, (size_t)ppl.n, sizeof(int64_t), cmp_i64);
+            memcpy(pc_out, pc.v, sizeof(int64_t) * (size_t)pc.n);
+            memcpy(pp_out, ppl.v, sizeof(int64_t) * (size_t)ppl.n);
+            *npp_leaves = ppl.n;
+            ret = pc.n;
+        }
+    }
+    free(pc.v); free(ppl.v); free(cur.v); free(nxt.v); free(rc2);
+    return ret;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Force evaluation in float64.                                                */
+
+/* Particle j on particle i: a += m r s^(-3/2), phi -= m s^(-1/2), r = x_j - x_i,
+ * s = |r|^2 + eps^2 (Plummer softening). */
+static void pp_term(const double *xi, const double *xj, double mj, double eps2,
+                    double a[3], double *phi, double *aabs, double *pabs)
+{
+    double rx = xj[0] - xi[0], ry = xj[1] - xi[1], rz = xj[2] - xi[2];
+    double s = ((rx * rx + ry * ry) + rz * rz) + eps2;
+    if (s == 0.0) return;
+    double rinv = 1.0 / sqrt(s);
+    double f = mj * rinv * rinv * rinv;
+    a[0] += f * rx; a[1] += f * ry; a[2] += f * rz;
+    *phi -= mj * rinv;
+    *aabs += f * sqrt((rx * rx + ry * ry) + rz * rz);
+    *pabs += mj * rinv;
+}
+
+/* Cell (mass M, centre of mass com, second moment S about com) on particle i,
+ * monopole plus quadrupole with Plummer-softened inverse distance rho:
+ *   phi = -M rho - 3/2 (r.S.r) rho^5 + 1/2 tr(S) rho^3
+ *   a   = -M rho^3 r + 3 rho^5 S.r + 3/2 tr(S) rho^5 r - 15/2 (r.S.r) rho^7 r
+ * with r = x_i - com; a = -grad phi.  Unsoftened this is the traceless
+ * quadrupole Q = 3S - tr(S) I of the textbook expansion. */
+static void pc_term(const double *xi, const double *com, double M, const double *S,
+                    double eps2, double a[3], double *phi, double *aabs, double *pabs)
+{
+    double rx = xi[0] - com[0], ry = xi[1] - com[1], rz = xi[2] - com[2];
+    double s = ((rx * rx + ry * ry) + rz * rz) + eps2;
+    if (s == 0.0) return;
+    double rho = 1.0 / sqrt(s);
+    double rho2 = rho * rho, rho3 = rho2 * rho, rho5 = rho3 * rho2, rho7 = rho5 * rho2;
+    double Srx = S[0] * rx + S[3] * ry + S[4] * rz;
+    double Sry = S[3] * rx + S[1] * ry + S[5] * rz;
+    double Srz = S[4] * rx + S[5] * ry + S[2] * rz;
+    double rSr = rx * Srx + ry * Sry + rz * Srz;
+    double tr = S[0] + S[1] + S[2];
+    double radial = -M * rho3 + 1.5 * tr * rho5 - 7.5 * rSr * rho7;
+    double ax = radial * rx + 3.0 * rho5 * Srx;
+    double ay = radial * ry + 3.0 * rho5 * Sry;
+    double az = radial * rz + 3.0 * rho5 * Srz;
+    a[0] += ax; a[1] += ay; a[2] += az;
+    double p = -M * rho - 1.5 * rSr * rho5 + 0.5 * tr * rho3;
+    *phi += p;
+    *aabs += sqrt((ax * ax + ay * ay) + az * az);
+    *pabs += fabs(p);
+}
+
+int orc_forces(const orc_tree *t, float theta, float eps,
+               const int64_t *groups, int64_t ng,
+               double *acc, double *pot, double *absacc, double *abspot)
+{
+    float *rc2 = (float *)malloc(sizeof(float) * (size_t)t->ncells);
+    if (!rc2) return -2;
+    orc_rcrit(t, theta, rc2, NULL);
+    double eps2 = (double)eps * (double)eps;
+    ivec pc = {0}, ppl = {0}, cur = {0}, nxt = {0};
+    int st = 0;
+    int64_t count = groups ? ng : t->ngroups;
+    for (int64_t k = 0; k < count && !st; ++k) {
+        int64_t g = groups ? groups[k] : k;
+        if (g < 0 || g >= t->ngroups) { st = -1; break; }
+        st = walk_group(t, rc2, g, &pc, &ppl, &cur, &nxt);
+        if (st) break;
+        for (int64_t i = t->gfirst[g]; i < t->gfirst[g] + t->gcount[g]; ++i) {
+            const double *xi = t->x + 3 * i;
+            double a[3] = {0.0, 0.0, 0.0}, phi = 0.0, aabs = 0.0, pabs = 0.0;
+            for (int64_t u = 0; u < ppl.n; ++u) {
+                int64_t leaf = ppl.v[u];
+                for (int64_t j = t->first[leaf]; j < t->first[leaf] + t->count[leaf]; ++j) {
+                    if (j == i) continue;
+                    pp_term(xi, t->x + 3 * j, t->m[j], eps2, a, &phi, &aabs, &pabs);
+                }
+            }
+            for (int64_t u = 0; u < pc.n; ++u) {
+                int64_t c = pc.v[u];
+                pc_term(xi, t->com + 3 * c, t->M[c], t->S + 6 * c, eps2, a, &phi, &aabs, &pabs);
+            }
+            int64_t o = t->perm[i];
+            acc[3 * o] = a[0]; acc[3 * o + 1] = a[1]; acc[3 * o + 2] = a[2];
+            pot[o] = phi;
+            if (absacc) absacc[o] = aabs;
+            if (abspot) abspot[o] = pabs;
+        }
+    }
+    free(pc.v); free(ppl.v); free(cur.v); free(nxt.v); free(rc2);
+    return st;
+}
+
+void orc_direct(const double *pos, const double *mass, int64_t n, float eps,
+                const int64_t *tgt, int64_t nt, double *acc, double *pot)
+{
+    double eps2 = (double)eps * (double)eps;
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tgt[k];
+        double a[3] = {0.0, 0.0, 0.0}, phi = 0.0, aabs = 0.0, pabs = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            pp_term(pos + 3 * i, pos + 3 * j, mass[j], eps2, a, &phi, &aabs, &pabs);
+        }
+        acc[3 * k] = a[0]; acc[3 * k + 1] = a[1]; acc[3 * k + 2] = a[2];
+        pot[k] = phi;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sect. 3.1: leapfrog.  Predicting x with the old acceleration and correcting  */
+/* v with the mean of old and new is the same map as kick-drift-kick.           */
+
+int orc_kdk_step(double *pos, double *vel, const double *mass, int64_t n,
+                 double *acc, double *pot, double dt, float theta, float eps,
+                 int nleaf, int ncrit)
+{
+    double h = 0.5 * dt;
+    for (int64_t i = 0; i < 3 * n; ++i) vel[i] = vel[i] + acc[i] * h;
+    for (int64_t i = 0; i < 3 * n; ++i) pos[i] = pos[i] + vel[i] * dt;
+    orc_tree *t = orc_build(pos, mass, n, nleaf, ncrit);
+    if (!t) return -2;
+    int st = orc_forces(t, theta, eps, NULL, 0, acc, pot, NULL, NULL);
+    orc_free(t);
+    if (st) return st;
+    for (int64_t i = 0; i < 3 * n; ++i) vel[i] = vel[i] + acc[i] * h;
+    return 0;
+}
+
+void orc_energy(const double *vel, const double *mass, const double *pot, int64_t n,
+                double out[6])
+{
+    double T = 0.0, W = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *v = vel + 3 * i;
+        T += 0.5 * mass[i] * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+        W += 0.5 * mass[i] * pot[i];
+        px += mass[i] * v[0];
+        py += mass[i] * v[1];
+        pz += mass[i] * v[2];
+    }
+    out[0] = T; out[1] = W; out[2] = T + W;
+    out[3] = px; out[4] = py; out[5] = pz;
+}

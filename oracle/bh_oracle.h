@@ -1,0 +1,137 @@
+/*
+ * bh_oracle.h - plain, slow, single-threaded CPU oracle for the sparse-octree
+ * gravitational tree-code of Bedorf, Gaburov & Portegies Zwart, "A sparse octree
+ * gravitational N-body code that runs entirely on the GPU processor" (J. Comput.
+ * Phys. 231 (2012); arXiv:1106.1900).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this code.  The product library shares
+ * no source, header, table or helper with it.
+ *
+ * Everything here is float64 arithmetic in the order the comments state, built
+ * with -ffp-contract=off so that no multiply-add is fused.  Decisions that the
+ * paper takes in single precision (the opening test of Eq. (1)) are taken in
+ * float32 here as well, so that the tree, the groups and the interaction lists
+ * have one exact answer that the GPU path must reproduce bit for bit.
+ *
+ * Conventions: positions are [n][3] row-major float64, masses [n] float64.
+ * "Sorted order" is the Morton (Z) order of App. B; "input order" is the
+ * caller's.  All index outputs are int64.  Functions that allocate return NULL
+ * or a negative status on failure; nothing aborts.
+ */
+#ifndef BH_ORACLE_H
+#define BH_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_LEVEL 20      /* 60-bit keys: 20 levels of 3 bits (App. B) */
+
+/* Integer coordinates and the 60-bit Morton key of one point (App. B).
+ * The domain is the cube with lower corner lo and side L; each coordinate is
+ * mapped to floor((x - lo) * 2^20 / L), clamped to [0, 2^20 - 1].  Bit b of the
+ * x, y, z integers goes to key bit 3b, 3b+1, 3b+2 respectively. */
+uint64_t orc_interleave(uint32_t qx, uint32_t qy, uint32_t qz);
+
+/* Domain of a point set: per-axis minimum lo[3], cube side L (the largest
+ * extent, 1 if every extent is zero) and scale = 2^20 / L.  Returns 0, or -1
+ * if a coordinate is not finite. */
+int orc_domain(const double *pos, int64_t n, double lo[3], double *L, double *scale);
+
+/* Keys of all points in input order; q (optional, [n][3]) receives the integer
+ * coordinates. */
+void orc_keys(const double *pos, int64_t n, const double lo[3], double scale,
+              uint64_t *key, uint32_t *q);
+
+/* Stable ascending argsort of keys: perm[i] is the input index of the i-th
+ * smallest key; equal keys keep input order (App. A: the split primitive keeps
+ * order, so the radix sort built from it is stable). */
+int orc_argsort(const uint64_t *key, int64_t n, int64_t *perm);
+
+typedef struct orc_tree orc_tree;
+
+/* Build keys, sorted order, the level-by-level cell array (Sect. 2.1), links,
+ * groups (Sect. 2.2) and float64 multipole moments (Sect. 3.2).
+ * nleaf >= 1, ncrit >= 1.  Returns NULL on bad arguments or allocation failure. */
+orc_tree *orc_build(const double *pos, const double *mass, int64_t n, int nleaf, int ncrit);
+void orc_free(orc_tree *t);
+
+int64_t orc_n(const orc_tree *t);
+int64_t orc_ncells(const orc_tree *t);
+int64_t orc_ngroups(const orc_tree *t);
+int     orc_depth(const orc_tree *t);   /* deepest level that holds a cell */
+
+void orc_get_domain(const orc_tree *t, double lo[3], double *L, double *scale);
+/* perm[i] = input index of sorted particle i; key[i] its key. */
+void orc_get_order(const orc_tree *t, int64_t *perm, uint64_t *key);
+/* Cell table in (level, key prefix) order.  For a node, child/nchild give its
+ * contiguous children; for a leaf child = -1, nchild = 0.  parent = -1 at the
+ * root.  first/count give the contiguous range of sorted particles. */
+void orc_get_cells(const orc_tree *t, uint8_t *level, uint64_t *prefix,
+                   int64_t *first, int64_t *count, uint8_t *is_leaf,
+                   int64_t *parent, int64_t *child, int32_t *nchild);
+/* Groups ordered by first particle; centre = float64 box centre, half = float32
+ * box half-size (tight box of the group's particles). */
+void orc_get_groups(const orc_tree *t, int64_t *gfirst, int64_t *gcount,
+                    double *centre, float *half);
+/* Per-cell mass, centre of mass [c][3] and second moment about the centre of
+ * mass S [c][6] = xx, yy, zz, xy, xz, yz. */
+void orc_get_moments(const orc_tree *t, double *mass, double *com, double *S);
+
+/* Opening radius of Eq. (1): r_crit = l / theta + delta, with l = L 2^-level the
+ * cell side and delta the distance between the geometric centre and the centre
+ * of mass.  Outputs (each optional): rcrit2[c] = (float)(r_crit^2), centre
+ * [c][3] = geometric centre. */
+void orc_rcrit(const orc_tree *t, float theta, float *rcrit2, double *centre);
+
+/* Opening test of Eq. (1) between group g and cell c, given rcrit2 of the cell.
+ * Returns 1 if the cell is accepted (its multipole is used), 0 if it is opened. */
+int orc_mac_accept(const orc_tree *t, int64_t g, int64_t c, float rcrit2_c);
+
+/* Interaction counts per group for opening angle theta (Sect. 2.2): npp = number
+ * of particles in opened leaves (the group's own included), npc = number of
+ * accepted cells.  Returns 0 or a negative status. */
+int orc_walk_counts(const orc_tree *t, float theta, int64_t *npp, int64_t *npc);
+
+/* Interaction lists of one group: the accepted cells (pc, ascending) and the
+ * opened leaves (pp_leaves, ascending).  Capacities are in entries; the
+ * function returns the number of accepted cells and stores the number of opened
+ * leaves in *npp_leaves; -1 if a capacity is too small. */
+int64_t orc_group_lists(const orc_tree *t, float theta, int64_t g,
+                        int64_t *pc, int64_t pc_cap,
+                        int64_t *pp_leaves, int64_t pp_cap, int64_t *npp_leaves);
+
+/* Barnes-Hut accelerations and potentials in float64 for the groups listed in
+ * groups[0..ng) (all groups if groups == NULL).  Outputs are in input order and
+ * only written for particles of the selected groups: acc [n][3], pot [n];
+ * absacc[i] = sum over interactions of |a_ij|, abspot[i] = sum of |phi_ij|
+ * (both optional).  G = 1.  Pairs whose softened distance is zero (a particle
+ * with itself, or coincident particles when eps = 0) contribute nothing. */
+int orc_forces(const orc_tree *t, float theta, float eps,
+               const int64_t *groups, int64_t ng,
+               double *acc, double *pot, double *absacc, double *abspot);
+
+/* Direct summation for the targets tgt[0..nt) (input indices); outputs are
+ * [nt][3] and [nt] in target order.  Same pair rule as orc_forces. */
+void orc_direct(const double *pos, const double *mass, int64_t n, float eps,
+                const int64_t *tgt, int64_t nt, double *acc, double *pot);
+
+/* One kick-drift-kick step (Sect. 3.1) of the Barnes-Hut system in input order:
+ * v += a dt/2; x += v dt; rebuild; new a, phi; v += a dt/2.  acc/pot hold the
+ * forces at the incoming positions and are overwritten with the new ones. */
+int orc_kdk_step(double *pos, double *vel, const double *mass, int64_t n,
+                 double *acc, double *pot, double dt, float theta, float eps,
+                 int nleaf, int ncrit);
+
+/* out = {T, W, E, Px, Py, Pz}: kinetic energy, potential energy (half the
+ * mass-weighted sum of phi), their sum, and the linear momentum. */
+void orc_energy(const double *vel, const double *mass, const double *pot, int64_t n,
+                double out[6]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

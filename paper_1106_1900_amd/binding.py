@@ -1,0 +1,243 @@
+"""ctypes binding of libbh (include/bh.h).  Argument marshalling only: every step
+of the method runs in the HIP kernels of the library.  Tensors passed in must be
+contiguous CUDA (HIP) tensors of the stated dtype on the context's device; work is
+enqueued on the current torch stream at context creation.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+HEADER = os.path.join(_ROOT, "include", "bh.h")
+
+BH_OK, BH_EINVAL, BH_ENOMEM, BH_EDEVICE, BH_ESTATE = 0, -1, -2, -3, -4
+_NAMES = {BH_EINVAL: "EINVAL", BH_ENOMEM: "ENOMEM", BH_EDEVICE: "EDEVICE", BH_ESTATE: "ESTATE"}
+
+
+class BHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
+                ("max_n", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ncells", ctypes.c_int64), ("nleaves", ctypes.c_int64),
+                ("ngroups", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("lanes_per_group_max", ctypes.c_int32), ("sum_npp", ctypes.c_int64),
+                ("sum_npc", ctypes.c_int64), ("ms_keys", ctypes.c_double),
+                ("ms_sort", ctypes.c_double), ("ms_move", ctypes.c_double),
+                ("ms_tree", ctypes.c_double), ("ms_moments", ctypes.c_double),
+                ("ms_walk", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+
+
+class TreeHost(ctypes.Structure):
+    _fields_ = [(k, _vp) for k in ("key", "perm", "level", "prefix", "first", "count", "is_leaf",
+                                   "parent", "child", "nchild", "mass", "com", "S", "rcrit2",
+                                   "gfirst", "gcount", "gcentre", "ghalf", "npp", "npc")]
+
+
+_lib = None
+
+
+def library_path():
+    return os.environ.get("BH_LIBRARY", os.path.join(_HERE, "libbh.so"))
+
+
+def declared_functions():
+    """Names of the functions include/bh.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(bh_\w+)\s*\(", text, re.M)))
+
+
+def load_library():
+    """Load libbh.so (built by ``python -m paper_1106_1900_amd.build``).  Raises if
+    it is missing: there is no other implementation to fall back on."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError("libbh.so not built (%s); run python -m paper_1106_1900_amd.build" % path)
+    L = ctypes.CDLL(path)
+    i32, i64, f32, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+    sig = {
+        "bh_default_params": (i32, [ctypes.POINTER(Params)]),
+        "bh_create": (i32, [ctypes.POINTER(_vp), ctypes.POINTER(Params), _vp]),
+        "bh_destroy": (i32, [_vp]),
+        "bh_build_tree": (i32, [_vp, _vp, _vp, i64]),
+        "bh_set_velocities": (i32, [_vp, _vp]),
+        "bh_compute_forces": (i32, [_vp, f32, f32, _vp, _vp]),
+        "bh_leapfrog_step": (i32, [_vp, f64]),
+        "bh_get_state": (i32, [_vp, _vp, _vp, _vp, _vp]),
+        "bh_set_state": (i32, [_vp, _vp, _vp]),
+        "bh_energy": (i32, [_vp, _vp]),
+        "bh_stats_get": (i32, [_vp, ctypes.POINTER(Stats)]),
+        "bh_export_tree": (i32, [_vp, ctypes.POINTER(TreeHost)]),
+        "bh_last_error": (ctypes.c_char_p, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _dev_ptr(t, dtype, shape=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, shape, tuple(t.shape)))
+    return _vp(t.data_ptr())
+
+
+class Context:
+    """One particle system on the device (bh_ctx)."""
+
+    def __init__(self, nleaf=16, ncrit=64, max_n=0, hbm_budget_bytes=0, stream=None):
+        import torch
+        self._L = load_library()
+        p = Params(nleaf, ncrit, max_n, hbm_budget_bytes)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _vp()
+        st = self._L.bh_create(ctypes.byref(h), ctypes.byref(p), _vp(stream.cuda_stream))
+        if st:
+            raise BHError(st, "bh_create failed")
+        self._h = h
+        self.n = 0
+        self.nleaf = nleaf
+        self.ncrit = ncrit
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.bh_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st):
+        if st:
+            raise BHError(st, self._L.bh_last_error(self._h).decode())
+
+    # --- the method -------------------------------------------------------
+    def build_tree(self, pos, mass):
+        import torch
+        n = int(pos.shape[0]) if pos.dim() == 2 else 0
+        pp = _dev_ptr(pos, torch.float64, (n, 3), "pos")
+        mp = _dev_ptr(mass, torch.float64, (n,), "mass")
+        self._keep = (pos, mass)
+        self._check(self._L.bh_build_tree(self._h, pp, mp, n))
+        self._keep = None
+        self.n = n
+
+    def set_velocities(self, vel):
+        import torch
+        self._check(self._L.bh_set_velocities(self._h, _dev_ptr(vel, torch.float64, (self.n, 3),
+                                                                "vel")))
+
+    def compute_forces(self, theta, eps, acc=None, pot=None, want=True):
+        """Accelerations [n,3] and potentials [n] (float32, caller order)."""
+        import torch
+        if want and acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float32, device=self._device())
+        if want and pot is None:
+            pot = torch.empty((self.n,), dtype=torch.float32, device=self._device())
+        ap = _dev_ptr(acc, torch.float32, (self.n, 3), "acc")
+        pp = _dev_ptr(pot, torch.float32, (self.n,), "pot")
+        self._check(self._L.bh_compute_forces(self._h, float(theta), float(eps), ap, pp))
+        return acc, pot
+
+    def leapfrog_step(self, dt):
+        self._check(self._L.bh_leapfrog_step(self._h, float(dt)))
+
+    def get_state(self):
+        import torch
+        dev = self._device()
+        pos = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        vel = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        acc = torch.empty((self.n, 3), dtype=torch.float32, device=dev)
+        pot = torch.empty((self.n,), dtype=torch.float32, device=dev)
+        self._check(self._L.bh_get_state(self._h, _vp(pos.data_ptr()), _vp(vel.data_ptr()),
+                                         _vp(acc.data_ptr()), _vp(pot.data_ptr())))
+        return pos, vel, acc, pot
+
+    def get_positions(self):
+        import torch
+        dev = self._device()
+        pos = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        vel = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        self._check(self._L.bh_get_state(self._h, _vp(pos.data_ptr()), _vp(vel.data_ptr()),
+                                         None, None))
+        return pos, vel
+
+    def set_state(self, pos, vel):
+        import torch
+        self._check(self._L.bh_set_state(self._h, _dev_ptr(pos, torch.float64, (self.n, 3), "pos"),
+                                         _dev_ptr(vel, torch.float64, (self.n, 3), "vel")))
+
+    def energy(self):
+        out = np.zeros(7)
+        self._check(self._L.bh_energy(self._h, out.ctypes.data_as(_vp)))
+        return out
+
+    def stats(self):
+        s = Stats()
+        self._check(self._L.bh_stats_get(self._h, ctypes.byref(s)))
+        return s
+
+    def export_tree(self):
+        """Host copies of keys, sorted order, cells, moments, groups and counts."""
+        s = self.stats()
+        n, nc, ng = s.n, s.ncells, s.ngroups
+        out = dict(
+            key=np.zeros(n, np.uint64), perm=np.zeros(n, np.int64),
+            level=np.zeros(nc, np.uint8), prefix=np.zeros(nc, np.uint64),
+            first=np.zeros(nc, np.int64), count=np.zeros(nc, np.int64),
+            is_leaf=np.zeros(nc, np.uint8), parent=np.zeros(nc, np.int64),
+            child=np.zeros(nc, np.int64), nchild=np.zeros(nc, np.int32),
+            mass=np.zeros(nc), com=np.zeros((nc, 3)), S=np.zeros((nc, 6)),
+            rcrit2=np.zeros(nc, np.float32),
+            gfirst=np.zeros(ng, np.int64), gcount=np.zeros(ng, np.int64),
+            gcentre=np.zeros((ng, 3)), ghalf=np.zeros((ng, 3), np.float32),
+            npp=np.zeros(ng, np.int64), npc=np.zeros(ng, np.int64))
+        th = TreeHost(**{k: v.ctypes.data_as(_vp) for k, v in out.items()})
+        self._check(self._L.bh_export_tree(self._h, ctypes.byref(th)))
+        return out
+
+    def _device(self):
+        import torch
+        return torch.device("cuda", torch.cuda.current_device())

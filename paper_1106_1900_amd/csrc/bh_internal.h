@@ -1,0 +1,249 @@
+// bh_internal.h - shared declarations of the libbh HIP sources: the context,
+// device buffers, wavefront primitives for gfx950 (wave64) and the host-side
+// launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/bh.h"
+
+namespace bh {
+
+constexpr int kMaxLevel = 20;          // 60-bit keys: 20 levels of 3 bits (App. B)
+constexpr int kLevels = kMaxLevel + 1;  // levels 0..20
+constexpr uint32_t kQMax = (1u << 20) - 1u;
+constexpr uint32_t kNone = 0xffffffffu;
+constexpr int kWave = 64;
+
+// Sort tiling: 256 threads x 8 keys per block.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// Tree-level tiling: one block of 256 threads handles 256 particles.
+constexpr int kTreeTile = 256;
+
+// Walk: one group per wavefront, 4 wavefronts per block.
+constexpr int kWalkWaves = 4;
+constexpr int kStackCap = 1408;        // >= 21 levels x 64 ranges (see walk.hip)
+
+// Small device-side scalars shared by the build and walk kernels.
+struct DevMisc {
+    unsigned long long bb_min[3];      // order-preserving images of the minima
+    unsigned long long bb_max[3];
+    uint32_t nonfinite;
+    uint32_t pad0;
+    double lo[3];
+    double L;
+    double scale;
+    uint32_t level_count[kLevels];
+    uint32_t level_offset[kLevels + 1];
+    uint32_t ncells;
+    uint32_t nleaves;
+    uint32_t ngroups;
+    uint32_t depth;
+    uint32_t walk_next;                // group work counter
+    uint32_t walk_overflow;            // set if a per-wave list would overflow
+    unsigned long long sum_npp;
+    unsigned long long sum_npc;
+};
+
+}  // namespace bh
+
+struct bh_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bh_params p{};
+    std::string err;
+
+    int64_t n = 0;          // particles in the current system
+    int64_t cap_n = 0;      // particle capacity of the buffers
+    int64_t cap_c = 0;      // cell capacity
+    int64_t bytes = 0;      // device bytes held
+    int cur = 0;            // which particle buffer holds the current state
+    bool built = false;
+    bool have_forces = false;
+    bool have_e0 = false;
+    double e0 = 0.0;
+    float theta = 0.75f;
+    float eps = 0.0f;
+
+    // host copies of counts after a build
+    int64_t ncells = 0, ngroups = 0, nleaves = 0;
+    int depth = 0;
+
+    // ---- particle buffers (sorted order) ----
+    double4 *p4[2] = {nullptr, nullptr};     // x, y, z, mass
+    double4 *v4[2] = {nullptr, nullptr};     // vx, vy, vz, unused
+    uint32_t *pid[2] = {nullptr, nullptr};   // caller index
+    float4 *acc4 = nullptr;                  // ax, ay, az, pot (sorted order)
+    uint64_t *key[2] = {nullptr, nullptr};   // sort ping-pong
+    uint32_t *val[2] = {nullptr, nullptr};
+    uint8_t *split = nullptr;                // level at which particle i leaves i-1's cell
+    uint8_t *lam = nullptr;                  // level of the leaf holding particle i
+    uint8_t *gflag = nullptr;                // group start flags
+    uint32_t *blk = nullptr;                 // per-block counters (levels, sort digits, scans)
+    int64_t blk_len = 0;
+    uint32_t *scan_tmp = nullptr;
+    int64_t scan_len = 0;
+
+    // ---- cells (level-major, key order within a level) ----
+    uint32_t *c_first = nullptr, *c_count = nullptr, *c_child = nullptr, *c_nchild = nullptr;
+    uint32_t *c_parent = nullptr, *c_arrive = nullptr;
+    uint8_t *c_level = nullptr, *c_leaf = nullptr;
+    double4 *c_com = nullptr;                // centre of mass, mass (float64)
+    double *c_S = nullptr;                   // [c][6] float64 second moment
+    float4 *c_q0 = nullptr, *c_q1 = nullptr; // float32 walk multipoles
+    float *c_rcrit2 = nullptr;
+    uint4 *c_walk = nullptr;                 // per-cell walk record (walk.hip)
+
+    // ---- groups ----
+    uint32_t *g_first = nullptr, *g_count = nullptr, *g_npp = nullptr, *g_npc = nullptr;
+    double4 *g_centre = nullptr;
+    float4 *g_half = nullptr;
+
+    // ---- scalars ----
+    bh::DevMisc *misc = nullptr;             // device
+    bh::DevMisc *misc_h = nullptr;           // pinned host mirror
+    double *red = nullptr;                   // energy partial sums
+    int64_t red_len = 0;
+    double *red_h = nullptr;                 // pinned host copy of the 6 sums
+
+    hipEvent_t ev[8] = {};
+    bh_stats stats{};
+    int lanes_max = 0;
+};
+
+namespace bh {
+
+// ---------------------------------------------------------------------------
+// launchers (each returns hipSuccess or the first HIP error)
+
+// build.hip
+hipError_t launch_bbox(bh_ctx *c, const double *pos_aos, int64_t n);   // pos_aos NULL: use p4[cur]
+hipError_t launch_keys(bh_ctx *c, const double *pos_aos, int64_t n);
+hipError_t launch_reorder_from_caller(bh_ctx *c, const double *pos_aos, const double *mass,
+                                      const uint32_t *perm, int64_t n);
+hipError_t launch_reorder(bh_ctx *c, const uint32_t *perm, int64_t n);
+hipError_t launch_tree(bh_ctx *c, int64_t n);
+hipError_t launch_groups(bh_ctx *c, int64_t n);
+hipError_t launch_group_boxes(bh_ctx *c, int64_t ngroups);
+hipError_t launch_moments(bh_ctx *c, int64_t ncells);
+hipError_t launch_rcrit(bh_ctx *c, int64_t ncells, float theta);
+
+// sort.hip
+hipError_t radix_sort_pairs(bh_ctx *c, int64_t n);      // key[0]/val[0] -> key[0]/val[0]
+hipError_t exclusive_scan_u32(bh_ctx *c, const uint32_t *in, uint32_t *out, int64_t n,
+                              uint32_t *total);          // total: device scalar or NULL
+hipError_t compact_flags(bh_ctx *c, const uint8_t *flags, int64_t n, uint32_t *idx,
+                         uint32_t *count);
+int64_t sort_blk_words(int64_t n);
+int64_t scan_tmp_words(int64_t n);
+
+// walk.hip
+hipError_t launch_walk(bh_ctx *c, float theta, float eps);
+hipError_t launch_scatter(bh_ctx *c, float *acc, float *pot);
+
+// integrate.hip
+hipError_t launch_kick(bh_ctx *c, double h);
+hipError_t launch_drift(bh_ctx *c, double dt);
+hipError_t launch_energy(bh_ctx *c);
+hipError_t launch_set_velocities(bh_ctx *c, const double *vel);
+hipError_t launch_get_state(bh_ctx *c, double *pos, double *vel, float *acc, float *pot);
+hipError_t launch_set_positions(bh_ctx *c, const double *pos, const double *vel);
+
+}  // namespace bh
+
+// ---------------------------------------------------------------------------
+// wavefront primitives (wave64)
+
+namespace bh {
+
+__device__ __forceinline__ int lane_id()
+{
+    return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// number of set bits of mask below this lane
+__device__ __forceinline__ int mask_rank(unsigned long long mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ unsigned long long ballot(bool p)
+{
+    return __ballot(p);
+}
+
+// Orders LDS traffic of one wavefront: writes issued before are visible to reads
+// issued after, and the compiler may not move memory accesses across it.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan_add(T v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T o = __shfl_up(v, d, kWave);
+        if (l >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan_max(int v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int o = __shfl_up(v, d, kWave);
+        if (l >= d) v = v > o ? v : o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t readfirst(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Order-preserving map of a double to an unsigned integer (for atomic min/max).
+__device__ __forceinline__ unsigned long long dbl_order(double x)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double dbl_unorder(unsigned long long b)
+{
+    b = (b >> 63) ? (b & 0x7fffffffffffffffull) : ~b;
+    return __longlong_as_double((long long)b);
+}
+
+}  // namespace bh
+
+#define BH_HIP_TRY(expr)                          \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return e_;          \
+    } while (0)
+
+#define BH_LAUNCH_CHECK() BH_HIP_TRY(hipGetLastError())

@@ -1,0 +1,715 @@
+// build.hip - tree construction on the device: bounding box, integer map and
+// Morton keys (App. B), particle reordering ("moving", Sect. 4.1), the cell array
+// (Sect. 2.1), links, groups (Sect. 2.2), float64 multipole moments (Sect. 3.2)
+// and the opening radius of Eq. (1) (Sect. 3.3).
+//
+// The paper forms cells level by level: it masks the keys of particles not yet in
+// a leaf, groups equal masked keys by compaction, marks cells of at most N_leaf
+// particles as leaves and repeats down to the deepest level, then links parents
+// and children with binary searches and atomics.  The same cell array is built
+// here with a fixed number of launches, independent of the depth:
+//
+//   split(i)  = first level at which sorted particles i-1 and i fall in
+//               different cells (from the common key prefix; 21 if equal keys);
+//   leaf(i)   = the level of the leaf holding particle i: the first level at
+//               which the run of particles sharing i's key prefix is at most
+//               N_leaf long, or 20 (found from split() within +-N_leaf of i);
+//   particle i starts exactly the cells of the levels split(i) .. leaf(i).
+//
+// Counting those starts per level and block, one scan per level gives every
+// cell its position in the (level, key) order, its parent and first child come
+// from the per-level ranks of the same particle, and a cell's end is the first
+// start after it at the same or a shallower level.  The result is the paper's
+// cell array exactly, in its order.
+#include "bh_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace bh {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0xFFFFFu;
+    x = (x | (x << 32)) & 0x001F00000000FFFFull;
+    x = (x | (x << 16)) & 0x001F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint64_t x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10C30C30C30C30C3ull;
+    x = (x ^ (x >> 4)) & 0x100F00F00F00F00Full;
+    x = (x ^ (x >> 8)) & 0x001F0000FF0000FFull;
+    x = (x ^ (x >> 16)) & 0x001F00000000FFFFull;
+    x = (x ^ (x >> 32)) & 0x1FFFFFull;
+    return (uint32_t)x;
+}
+
+__device__ __forceinline__ uint32_t coord_to_int(double x, double lo, double scale)
+{
+    double d = x - lo;
+    double f = d * scale;
+    return f >= (double)kQMax ? kQMax : (uint32_t)f;
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ void misc_reset_kernel(DevMisc *m)
+{
+    const int t = threadIdx.x;
+    if (t < 3) {
+        m->bb_min[t] = ~0ull;
+        m->bb_max[t] = 0ull;
+    }
+    if (t == 0) {
+        m->nonfinite = 0;
+        m->nleaves = 0;
+        m->ngroups = 0;
+        m->ncells = 0;
+    }
+}
+
+struct AosSrc {
+    const double *p;
+    __device__ double get(int64_t i, int k) const { return p[3 * i + k]; }
+};
+struct P4Src {
+    const double4 *p;
+    __device__ double get(int64_t i, int k) const
+    {
+        const double4 v = p[i];
+        return k == 0 ? v.x : (k == 1 ? v.y : v.z);
+    }
+};
+
+template <typename Src>
+__global__ void __launch_bounds__(kBlock) bbox_kernel(Src src, int64_t n, DevMisc *m)
+{
+    double lo[3] = {INFINITY, INFINITY, INFINITY};
+    double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    uint32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double v = src.get(i, k);
+            if (!isfinite(v)) bad = 1;
+            lo[k] = fmin(lo[k], v);
+            hi[k] = fmax(hi[k], v);
+        }
+    }
+    __shared__ double s_lo[3][kBlock / kWave], s_hi[3][kBlock / kWave];
+    __shared__ uint32_t s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    if (bad) atomicOr(&s_bad, 1u);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double a = lo[k], b = hi[k];
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            a = fmin(a, __shfl_xor(a, d, kWave));
+            b = fmax(b, __shfl_xor(b, d, kWave));
+        }
+        if (l == 0) {
+            s_lo[k][w] = a;
+            s_hi[k][w] = b;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        double a = s_lo[k][0], b = s_hi[k][0];
+        for (int i = 1; i < kBlock / kWave; ++i) {
+            a = fmin(a, s_lo[k][i]);
+            b = fmax(b, s_hi[k][i]);
+        }
+        if (a <= b) {  // the block saw at least one finite point on this axis
+            atomicMin(&m->bb_min[k], dbl_order(a));
+            atomicMax(&m->bb_max[k], dbl_order(b));
+        }
+    }
+    if (threadIdx.x == 0 && s_bad) atomicOr(&m->nonfinite, 1u);
+}
+
+// Cube side = largest extent (1 if all extents vanish); scale = 2^20 / side.
+__global__ void domain_kernel(DevMisc *m)
+{
+    if (threadIdx.x != 0) return;
+    double side = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double lo = dbl_unorder(m->bb_min[k]);
+        double hi = dbl_unorder(m->bb_max[k]);
+        m->lo[k] = lo;
+        double e = hi - lo;
+        if (e > side) side = e;
+    }
+    if (side == 0.0) side = 1.0;
+    m->L = side;
+    m->scale = 1048576.0 / side;
+}
+
+template <typename Src>
+__global__ void __launch_bounds__(kBlock)
+keys_kernel(Src src, int64_t n, const DevMisc *__restrict__ m, uint64_t *__restrict__ key,
+            uint32_t *__restrict__ val)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double scale = m->scale;
+    uint32_t qx = coord_to_int(src.get(i, 0), m->lo[0], scale);
+    uint32_t qy = coord_to_int(src.get(i, 1), m->lo[1], scale);
+    uint32_t qz = coord_to_int(src.get(i, 2), m->lo[2], scale);
+    key[i] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+    val[i] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(kBlock)
+reorder_from_caller_kernel(const double *__restrict__ pos, const double *__restrict__ mass,
+                           const uint32_t *__restrict__ perm, int64_t n, double4 *__restrict__ p4,
+                           double4 *__restrict__ v4, uint32_t *__restrict__ pid, DevMisc *m)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t s = perm[i];
+    const double ms = mass[s];
+    if (!(ms > 0.0) || !isfinite(ms)) atomicOr(&m->nonfinite, 2u);
+    p4[i] = make_double4(pos[3 * (int64_t)s], pos[3 * (int64_t)s + 1], pos[3 * (int64_t)s + 2],
+                         ms);
+    v4[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    pid[i] = s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+reorder_kernel(const double4 *__restrict__ p4i, const double4 *__restrict__ v4i,
+               const uint32_t *__restrict__ pidi, const uint32_t *__restrict__ perm, int64_t n,
+               double4 *__restrict__ p4o, double4 *__restrict__ v4o, uint32_t *__restrict__ pido)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t s = perm[i];
+    p4o[i] = p4i[s];
+    v4o[i] = v4i[s];
+    pido[i] = pidi[s];
+}
+
+// ---------------------------------------------------------------------------
+// cells
+
+__device__ __forceinline__ uint8_t split_level(uint64_t a, uint64_t b)
+{
+    uint64_t x = a ^ b;
+    if (x == 0) return (uint8_t)(kMaxLevel + 1);
+    // keys use 60 bits: 4 leading zero bits are not part of the key
+    int lz = __clzll((long long)x) - 4;
+    return (uint8_t)(1 + lz / 3);
+}
+
+// Per particle: split level, leaf level; per block and level: number of cells
+// starting in the block.  blk layout: [level][block].
+__global__ void __launch_bounds__(kTreeTile)
+split_leaf_kernel(const uint64_t *__restrict__ key, int64_t n, int nleaf, uint8_t *__restrict__ split,
+                  uint8_t *__restrict__ lam, uint32_t *__restrict__ blk, int nblk,
+                  DevMisc *__restrict__ m)
+{
+    extern __shared__ uint8_t s_dyn[];
+    const int H = nleaf;                          // halo on each side
+    const int W = kTreeTile + 2 * H;              // split values held in LDS
+    uint8_t *s_split = s_dyn;                     // [W]
+    uint8_t *s_pl = s_dyn + ((W + 15) & ~15);     // [kTreeTile][H] left prefix minima
+    __shared__ uint32_t s_cnt[kLevels];
+    __shared__ uint32_t s_leaves;
+
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kTreeTile;
+    if (t < kLevels) s_cnt[t] = 0;
+    if (t == 0) s_leaves = 0;
+    // split of global index j, with the conventions split(0) = 0 and split(n) = 0
+    for (int u = t; u < W; u += kTreeTile) {
+        int64_t j = base - H + u;
+        uint8_t v;
+        if (j <= 0 || j >= n) v = 0;
+        else v = split_level(key[j - 1], key[j]);
+        s_split[u] = v;
+    }
+    __syncthreads();
+
+    const int64_t i = base + t;
+    const bool valid = i < n;
+    uint8_t sp = 0, lm = 0;
+    if (valid) {
+        sp = s_split[H + t];
+        // left prefix minima PL[a] = min split(i - a'), a' = 0..a
+        uint8_t run = 255;
+        for (int a = 0; a < H; ++a) {
+            uint8_t v = (i - a <= 0) ? (uint8_t)0 : s_split[H + t - a];
+            run = v < run ? v : run;
+            s_pl[t * H + a] = run;
+        }
+        // right prefix minima PR[b] over split(i + b'), b' = 1..b, combined with
+        // PL[H - b]: lam = min_b max(PL[H - b], PR[b])
+        uint8_t best = 255;
+        run = 255;
+        for (int b = 1; b <= H; ++b) {
+            uint8_t v = (i + b >= n) ? (uint8_t)0 : s_split[H + t + b];
+            run = v < run ? v : run;
+            uint8_t pl = s_pl[t * H + (H - b)];
+            uint8_t mx = pl > run ? pl : run;
+            best = mx < best ? mx : best;
+        }
+        lm = best > kMaxLevel ? (uint8_t)kMaxLevel : best;
+        split[i] = sp;
+        lam[i] = lm;
+    }
+    // count starts per level
+    const int l = t % kWave;
+    for (int lev = 0; lev < kLevels; ++lev) {
+        unsigned long long b = ballot(valid && sp <= lev && lev <= lm);
+        if (l == 0 && b) atomicAdd(&s_cnt[lev], (uint32_t)__popcll(b));
+    }
+    {
+        unsigned long long b = ballot(valid && sp <= lm);
+        if (l == 0 && b) atomicAdd(&s_leaves, (uint32_t)__popcll(b));
+    }
+    __syncthreads();
+    if (t < kLevels) blk[(int64_t)t * nblk + blockIdx.x] = s_cnt[t];
+    if (t == 0 && s_leaves) atomicAdd(&m->nleaves, s_leaves);
+}
+
+// level counts -> level offsets (level-major order), total cells, depth.
+__global__ void level_finalize_kernel(const uint32_t *__restrict__ tot, DevMisc *m, int64_t cap_c)
+{
+    if (threadIdx.x != 0) return;
+    uint64_t off = 0;
+    uint32_t depth = 0;
+    for (int l = 0; l < kLevels; ++l) {
+        m->level_offset[l] = (uint32_t)off;
+        m->level_count[l] = tot[l];
+        if (tot[l]) depth = (uint32_t)l;
+        off += tot[l];
+    }
+    if (off > (uint64_t)cap_c) {
+        // cannot happen for a consistent tree; keep every later write in bounds
+        m->nonfinite |= 4u;
+        for (int l = 0; l < kLevels; ++l) m->level_count[l] = 0;
+        off = 0;
+    }
+    m->level_offset[kLevels] = (uint32_t)off;
+    m->ncells = (uint32_t)off;
+    m->depth = depth;
+}
+
+// For every level, the index of the cell of that level holding particle i
+// (valid up to lam(i)): level offset + number of starts at that level up to i,
+// minus one.  Computed with wavefront ballots and the scanned block counts.
+struct Ranks {
+    uint32_t anc[kLevels];
+};
+
+__device__ __forceinline__ void level_ranks(int64_t i, bool valid, uint8_t sp, uint8_t lm,
+                                            const uint32_t *__restrict__ blk_scanned, int nblk,
+                                            const DevMisc *__restrict__ m, uint32_t (*s_wc)[kLevels],
+                                            Ranks &r)
+{
+    const int t = threadIdx.x, w = t / kWave, l = t % kWave;
+    unsigned long long balls[kLevels];
+#pragma unroll
+    for (int lev = 0; lev < kLevels; ++lev) {
+        balls[lev] = ballot(valid && sp <= lev && lev <= lm);
+        if (l == 0) s_wc[w][lev] = (uint32_t)__popcll(balls[lev]);
+    }
+    __syncthreads();
+    const unsigned long long le = (l == kWave - 1) ? ~0ull : ((2ull << l) - 1ull);
+#pragma unroll
+    for (int lev = 0; lev < kLevels; ++lev) {
+        uint32_t off = blk_scanned[(int64_t)lev * nblk + blockIdx.x];
+        for (int ww = 0; ww < w; ++ww) off += s_wc[ww][lev];
+        uint32_t incl = off + (uint32_t)__popcll(balls[lev] & le);
+        r.anc[lev] = m->level_offset[lev] + incl - 1u;
+    }
+}
+
+__global__ void __launch_bounds__(kTreeTile)
+emit_cells_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__ lam, int64_t n,
+                  const uint32_t *__restrict__ blk_scanned, int nblk, const DevMisc *__restrict__ m,
+                  uint32_t *__restrict__ c_first, uint8_t *__restrict__ c_level,
+                  uint8_t *__restrict__ c_leaf, uint32_t *__restrict__ c_parent,
+                  uint32_t *__restrict__ c_child, uint32_t *__restrict__ c_nchild)
+{
+    __shared__ uint32_t s_wc[kTreeTile / kWave][kLevels];
+    const int64_t i = (int64_t)blockIdx.x * kTreeTile + threadIdx.x;
+    const bool valid = i < n;
+    const uint8_t sp = valid ? split[i] : (uint8_t)255;
+    const uint8_t lm = valid ? lam[i] : (uint8_t)0;
+    Ranks r;
+    level_ranks(i, valid, sp, lm, blk_scanned, nblk, m, s_wc, r);
+    if (!valid || sp > lm || m->ncells == 0) return;
+#pragma unroll
+    for (int lev = 0; lev < kLevels; ++lev) {
+        if (lev < sp || lev > lm) continue;
+        const uint32_t c = r.anc[lev];
+        if (c >= m->ncells) continue;
+        c_first[c] = (uint32_t)i;
+        c_level[c] = (uint8_t)lev;
+        c_leaf[c] = (uint8_t)(lev == lm);
+        c_parent[c] = lev > 0 ? r.anc[lev > 0 ? lev - 1 : 0] : kNone;
+        c_child[c] = lev < lm ? r.anc[lev < kMaxLevel ? lev + 1 : kMaxLevel] : kNone;
+        c_nchild[c] = 0;
+    }
+}
+
+// Cell ends (hence counts), numbers of children, and group starts.
+__global__ void __launch_bounds__(kTreeTile)
+cell_ends_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__ lam, int64_t n,
+                 int ncrit, const uint32_t *__restrict__ blk_scanned, int nblk,
+                 const DevMisc *__restrict__ m, const uint32_t *__restrict__ c_first,
+                 const uint32_t *__restrict__ c_parent, const uint32_t *__restrict__ c_child,
+                 uint32_t *__restrict__ c_count, uint32_t *__restrict__ c_nchild,
+                 uint8_t *__restrict__ gflag)
+{
+    __shared__ uint32_t s_wc[kTreeTile / kWave][kLevels];
+    const int64_t i = (int64_t)blockIdx.x * kTreeTile + threadIdx.x;
+    const bool valid = i < n;
+    const uint8_t sp = valid ? split[i] : (uint8_t)255;
+    const uint8_t lm = valid ? lam[i] : (uint8_t)0;
+    Ranks r;
+    level_ranks(i, valid, sp, lm, blk_scanned, nblk, m, s_wc, r);
+    if (!valid || sp > lm || m->ncells == 0) return;
+    uint32_t e = (uint32_t)n;            // running end: min over shallower levels
+    uint32_t prev_count = 0;             // count of the level above (the parent)
+    bool grouped = false;
+#pragma unroll
+    for (int lev = 0; lev < kLevels; ++lev) {
+        if (lev > lm) continue;
+        const uint32_t a = r.anc[lev];
+        const uint32_t lend = m->level_offset[lev] + m->level_count[lev];
+        if (a >= lend) break;
+        const uint32_t nxt = (a + 1u < lend) ? c_first[a + 1u] : (uint32_t)n;
+        e = nxt < e ? nxt : e;
+        const uint32_t first = (lev >= sp) ? (uint32_t)i : c_first[a];
+        const uint32_t cnt = e - first;
+        if (lev >= sp) {
+            c_count[a] = cnt;
+            if (lev > 0) {
+                const uint32_t p = r.anc[lev > 0 ? lev - 1 : 0];
+                const bool last = (a + 1u >= lend) || (c_parent[a + 1u] != p);
+                if (last) c_nchild[p] = a - c_child[p] + 1u;
+            }
+            // group: at most ncrit particles and the parent holds more (or root)
+            if (!grouped && cnt <= (uint32_t)ncrit && (lev == 0 || prev_count > (uint32_t)ncrit)) {
+                gflag[i] = 1;
+                grouped = true;
+            }
+            // a leaf still larger than ncrit is cut into runs of ncrit particles
+            if (lev == lm && cnt > (uint32_t)ncrit) {
+                for (uint32_t o = 0; o < cnt; o += (uint32_t)ncrit) gflag[i + o] = 1;
+            }
+        }
+        prev_count = cnt;
+    }
+}
+
+// group counts and tight boxes
+__global__ void __launch_bounds__(kBlock)
+group_boxes_kernel(const uint32_t *__restrict__ g_first, int64_t ngroups, int64_t n,
+                   const double4 *__restrict__ p4, uint32_t *__restrict__ g_count,
+                   double4 *__restrict__ g_centre, float4 *__restrict__ g_half)
+{
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= ngroups) return;
+    const uint32_t s = g_first[g];
+    const uint32_t e = (g + 1 < ngroups) ? g_first[g + 1] : (uint32_t)n;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t j = s; j < e; ++j) {
+        const double4 p = p4[j];
+        lo[0] = fmin(lo[0], p.x); hi[0] = fmax(hi[0], p.x);
+        lo[1] = fmin(lo[1], p.y); hi[1] = fmax(hi[1], p.y);
+        lo[2] = fmin(lo[2], p.z); hi[2] = fmax(hi[2], p.z);
+    }
+    g_count[g] = e - s;
+    g_centre[g] = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2]),
+                               0.0);
+    g_half[g] = make_float4((float)(0.5 * (hi[0] - lo[0])), (float)(0.5 * (hi[1] - lo[1])),
+                            (float)(0.5 * (hi[2] - lo[2])), 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// moments: float64 monopole and second moment, leaves from particles, nodes from
+// children; the last child to finish computes its parent (children are always
+// read in array order, so the sums do not depend on which thread does it).
+
+__device__ __forceinline__ void store_walk_multipole(uint32_t c, double M, const double *S,
+                                                     float4 *__restrict__ q0, float4 *__restrict__ q1)
+{
+    const double tr = (S[0] + S[1]) + S[2];
+    q0[c] = make_float4((float)(3.0 * S[0]), (float)(3.0 * S[1]), (float)(3.0 * S[2]),
+                        (float)(3.0 * S[3]));
+    q1[c] = make_float4((float)(3.0 * S[4]), (float)(3.0 * S[5]), (float)(0.5 * tr),
+                        (float)(1.5 * tr));
+    (void)M;
+}
+
+__global__ void __launch_bounds__(kBlock)
+moments_kernel(int64_t ncells, const uint8_t *__restrict__ c_leaf,
+               const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
+               const uint32_t *__restrict__ c_parent, const uint32_t *__restrict__ c_child,
+               const uint32_t *__restrict__ c_nchild, uint32_t *__restrict__ arrive,
+               const double4 *__restrict__ p4, double4 *c_com, double *c_S,
+               float4 *__restrict__ q0, float4 *__restrict__ q1)
+{
+    const int64_t c0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c0 >= ncells || !c_leaf[c0]) return;
+    uint32_t c = (uint32_t)c0;
+    {
+        const uint32_t s = c_first[c], e = s + c_count[c];
+        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        for (uint32_t j = s; j < e; ++j) M = M + p4[j].w;
+        for (uint32_t j = s; j < e; ++j) {
+            const double4 p = p4[j];
+            sx = sx + p.w * p.x;
+            sy = sy + p.w * p.y;
+            sz = sz + p.w * p.z;
+        }
+        const double cx = sx / M, cy = sy / M, cz = sz / M;
+        double S[6] = {0, 0, 0, 0, 0, 0};
+        for (uint32_t j = s; j < e; ++j) {
+            const double4 p = p4[j];
+            const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+            S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
+            S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
+        }
+        c_com[c] = make_double4(cx, cy, cz, M);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)c + k] = S[k];
+        store_walk_multipole(c, M, S, q0, q1);
+    }
+    while (c != 0) {
+        const uint32_t p = c_parent[c];
+        if ((int64_t)p >= ncells) return;
+        // release our cell's moments, then count in; the last child carries on
+        const uint32_t old = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u != c_nchild[p]) return;
+        const uint32_t s = c_child[p], e = s + c_nchild[p];
+        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        for (uint32_t k = s; k < e; ++k) M = M + c_com[k].w;
+        for (uint32_t k = s; k < e; ++k) {
+            const double4 q = c_com[k];
+            sx = sx + q.w * q.x;
+            sy = sy + q.w * q.y;
+            sz = sz + q.w * q.z;
+        }
+        const double cx = sx / M, cy = sy / M, cz = sz / M;
+        double S[6] = {0, 0, 0, 0, 0, 0};
+        for (uint32_t k = s; k < e; ++k) {
+            const double4 q = c_com[k];
+            const double ex = q.x - cx, ey = q.y - cy, ez = q.z - cz;
+            const double *Sk = c_S + 6 * (int64_t)k;
+            S[0] += Sk[0] + q.w * ex * ex; S[1] += Sk[1] + q.w * ey * ey;
+            S[2] += Sk[2] + q.w * ez * ez; S[3] += Sk[3] + q.w * ex * ey;
+            S[4] += Sk[4] + q.w * ex * ez; S[5] += Sk[5] + q.w * ey * ez;
+        }
+        c_com[p] = make_double4(cx, cy, cz, M);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)p + k] = S[k];
+        store_walk_multipole(p, M, S, q0, q1);
+        c = p;
+    }
+}
+
+// Eq. (1): r_crit = l/theta + delta with l = L 2^-level and delta the distance of
+// the centre of mass from the cell's geometric centre; stored as float32 r_crit^2.
+__global__ void __launch_bounds__(kBlock)
+rcrit_kernel(int64_t ncells, float theta, const DevMisc *__restrict__ m,
+             const uint8_t *__restrict__ c_level, const uint32_t *__restrict__ c_first,
+             const uint64_t *__restrict__ skey, const double4 *__restrict__ c_com,
+             float *__restrict__ rcrit2)
+{
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncells) return;
+    const int lev = c_level[c];
+    const double l = ldexp(m->L, -lev);
+    const uint64_t pre = skey[c_first[c]] >> (3 * (kMaxLevel - lev));
+    const double gx = m->lo[0] + ((double)compact3(pre) + 0.5) * l;
+    const double gy = m->lo[1] + ((double)compact3(pre >> 1) + 0.5) * l;
+    const double gz = m->lo[2] + ((double)compact3(pre >> 2) + 0.5) * l;
+    const double4 cm = c_com[c];
+    const double dx = cm.x - gx, dy = cm.y - gy, dz = cm.z - gz;
+    const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
+    const double r = l / (double)theta + delta;
+    rcrit2[c] = (float)(r * r);
+}
+
+__global__ void fill_u8_kernel(uint8_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void scan_levels_kernel(uint32_t *__restrict__ blk, int nblk, uint32_t *__restrict__ tot)
+{
+    // one block per level: exclusive scan of the level's block counts in place
+    __shared__ uint32_t s_tmp[4];
+    uint32_t *row = blk + (int64_t)blockIdx.x * nblk;
+    uint32_t run = 0;
+    const int t = threadIdx.x, w = t / kWave, l = t % kWave;
+    for (int b0 = 0; b0 < nblk; b0 += 256) {
+        int b = b0 + t;
+        uint32_t v = b < nblk ? row[b] : 0u;
+        uint32_t inc = wave_incl_scan_add(v);
+        if (l == kWave - 1) s_tmp[w] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot4 = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (k < w) off += s_tmp[k];
+            tot4 += s_tmp[k];
+        }
+        __syncthreads();
+        if (b < nblk) row[b] = run + off + inc - v;
+        run += tot4;
+    }
+    if (t == 0) tot[blockIdx.x] = run;
+}
+
+inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+hipError_t launch_bbox(bh_ctx *c, const double *pos_aos, int64_t n)
+{
+    hipLaunchKernelGGL(misc_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
+    BH_LAUNCH_CHECK();
+    int grid = grid_for(n, kBlock);
+    if (grid > 2048) grid = 2048;
+    if (pos_aos)
+        hipLaunchKernelGGL(bbox_kernel<AosSrc>, dim3(grid), dim3(kBlock), 0, c->stream,
+                           AosSrc{pos_aos}, n, c->misc);
+    else
+        hipLaunchKernelGGL(bbox_kernel<P4Src>, dim3(grid), dim3(kBlock), 0, c->stream,
+                           P4Src{c->p4[c->cur]}, n, c->misc);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(domain_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_keys(bh_ctx *c, const double *pos_aos, int64_t n)
+{
+    if (pos_aos)
+        hipLaunchKernelGGL(keys_kernel<AosSrc>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
+                           c->stream, AosSrc{pos_aos}, n, c->misc, c->key[0], c->val[0]);
+    else
+        hipLaunchKernelGGL(keys_kernel<P4Src>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
+                           c->stream, P4Src{c->p4[c->cur]}, n, c->misc, c->key[0], c->val[0]);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_reorder_from_caller(bh_ctx *c, const double *pos_aos, const double *mass,
+                                      const uint32_t *perm, int64_t n)
+{
+    hipLaunchKernelGGL(reorder_from_caller_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
+                       c->stream, pos_aos, mass, perm, n, c->p4[c->cur], c->v4[c->cur],
+                       c->pid[c->cur], c->misc);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_reorder(bh_ctx *c, const uint32_t *perm, int64_t n)
+{
+    const int s = c->cur, d = c->cur ^ 1;
+    hipLaunchKernelGGL(reorder_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, c->stream,
+                       c->p4[s], c->v4[s], c->pid[s], perm, n, c->p4[d], c->v4[d], c->pid[d]);
+    BH_LAUNCH_CHECK();
+    c->cur = d;
+    return hipSuccess;
+}
+
+hipError_t launch_tree(bh_ctx *c, int64_t n)
+{
+    const int nblk = grid_for(n, kTreeTile);
+    uint32_t *blk = c->blk;                       // [kLevels][nblk]
+    uint32_t *tot = c->blk + (int64_t)kLevels * nblk;
+    const int H = c->p.nleaf;
+    const size_t lds = (size_t)((kTreeTile + 2 * H + 15) & ~15) + (size_t)kTreeTile * H;
+    hipLaunchKernelGGL(split_leaf_kernel, dim3(nblk), dim3(kTreeTile), lds, c->stream, c->key[0],
+                       n, H, c->split, c->lam, blk, nblk, c->misc);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(scan_levels_kernel, dim3(kLevels), dim3(256), 0, c->stream, blk, nblk, tot);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(level_finalize_kernel, dim3(1), dim3(64), 0, c->stream, tot, c->misc,
+                       c->cap_c);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(emit_cells_kernel, dim3(nblk), dim3(kTreeTile), 0, c->stream, c->split,
+                       c->lam, n, blk, nblk, c->misc, c->c_first, c->c_level, c->c_leaf,
+                       c->c_parent, c->c_child, c->c_nchild);
+    BH_LAUNCH_CHECK();
+    int fg = grid_for(n, 256);
+    if (fg > 4096) fg = 4096;
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(fg), dim3(256), 0, c->stream, c->gflag, n);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(cell_ends_kernel, dim3(nblk), dim3(kTreeTile), 0, c->stream, c->split,
+                       c->lam, n, c->p.ncrit, blk, nblk, c->misc, c->c_first, c->c_parent,
+                       c->c_child, c->c_count, c->c_nchild, c->gflag);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_groups(bh_ctx *c, int64_t n)
+{
+    return compact_flags(c, c->gflag, n, c->g_first, &c->misc->ngroups);
+}
+
+hipError_t launch_group_boxes(bh_ctx *c, int64_t ngroups)
+{
+    if (ngroups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(group_boxes_kernel, dim3(grid_for(ngroups, kBlock)), dim3(kBlock), 0,
+                       c->stream, c->g_first, ngroups, c->n, c->p4[c->cur], c->g_count,
+                       c->g_centre, c->g_half);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_moments(bh_ctx *c, int64_t ncells)
+{
+    int fg = grid_for(ncells, 256);
+    if (fg > 4096) fg = 4096;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, c->stream, c->c_arrive, ncells);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(moments_kernel, dim3(grid_for(ncells, kBlock)), dim3(kBlock), 0, c->stream,
+                       ncells, c->c_leaf, c->c_first, c->c_count, c->c_parent, c->c_child,
+                       c->c_nchild, c->c_arrive, c->p4[c->cur], c->c_com, c->c_S, c->c_q0,
+                       c->c_q1);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_rcrit(bh_ctx *c, int64_t ncells, float theta)
+{
+    hipLaunchKernelGGL(rcrit_kernel, dim3(grid_for(ncells, kBlock)), dim3(kBlock), 0, c->stream,
+                       ncells, theta, c->misc, c->c_level, c->c_first, c->key[0], c->c_com,
+                       c->c_rcrit2);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace bh

@@ -69,6 +69,13 @@ typedef struct {
     double ms_moments;      /* multipole moments */
     double ms_walk;         /* opening radii + walk + scatter */
     int64_t device_bytes;   /* device memory held by the context */
+    /* The walk kernel alone, timed with events on the context stream around each
+     * launch: last launch, and totals since the context was created. */
+    double ms_walk_kernel;
+    double walk_kernel_ms_total;
+    int64_t walk_kernel_launches;
+    int64_t total_npp;      /* sum_npp accumulated over all walks */
+    int64_t total_npc;      /* sum_npc accumulated over all walks */
 } bh_stats;
 
 /* Host copies of the tree for checking it element by element.  Every pointer is

@@ -36,7 +36,10 @@ class Stats(ctypes.Structure):
                 ("sum_npc", ctypes.c_int64), ("ms_keys", ctypes.c_double),
                 ("ms_sort", ctypes.c_double), ("ms_move", ctypes.c_double),
                 ("ms_tree", ctypes.c_double), ("ms_moments", ctypes.c_double),
-                ("ms_walk", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("ms_walk", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("ms_walk_kernel", ctypes.c_double), ("walk_kernel_ms_total", ctypes.c_double),
+                ("walk_kernel_launches", ctypes.c_int64), ("total_npp", ctypes.c_int64),
+                ("total_npc", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -74,7 +74,6 @@ void free_buffers(bh_ctx *c)
     dfree(c->c_child);
     dfree(c->c_nchild);
     dfree(c->c_parent);
-    dfree(c->c_arrive);
     dfree(c->c_level);
     dfree(c->c_leaf);
     dfree(c->c_com);
@@ -82,7 +81,9 @@ void free_buffers(bh_ctx *c)
     dfree(c->c_q0);
     dfree(c->c_q1);
     dfree(c->c_rcrit2);
-    dfree(c->c_walk);
+    dfree(c->c_rec);
+    dfree(c->walk_spill);
+    c->walk_spill_waves = 0;
     dfree(c->g_first);
     dfree(c->g_count);
     dfree(c->g_npp);
@@ -106,7 +107,7 @@ int64_t bytes_for(int64_t n, int nleaf)
 {
     const int64_t nc = cell_bound(n, nleaf);
     const int64_t per_p = 2 * 32 + 2 * 32 + 2 * 4 + 16 + 2 * 8 + 2 * 4 + 3 + 64;
-    const int64_t per_c = 6 * 4 + 2 + 32 + 48 + 32 + 4 + 16;
+    const int64_t per_c = 5 * 4 + 2 + 32 + 48 + 32 + 4 + 64;
     const int64_t blk_words = std::max(sort_blk_words(n), (int64_t)kLevels * ((n + kTreeTile - 1) / kTreeTile) + kLevels);
     return n * per_p + nc * per_c + 4 * (blk_words + scan_tmp_words(n)) + 8 * energy_words();
 }
@@ -148,7 +149,6 @@ int ensure_capacity(bh_ctx *c, int64_t n)
     A(c->c_child, nc);
     A(c->c_nchild, nc);
     A(c->c_parent, nc);
-    A(c->c_arrive, nc);
     A(c->c_level, nc);
     A(c->c_leaf, nc);
     A(c->c_com, nc);
@@ -156,7 +156,7 @@ int ensure_capacity(bh_ctx *c, int64_t n)
     A(c->c_q0, nc);
     A(c->c_q1, nc);
     A(c->c_rcrit2, nc);
-    A(c->c_walk, nc);
+    A(c->c_rec, nc);
     A(c->g_first, want);
     A(c->g_count, want);
     A(c->g_npp, want);
@@ -284,10 +284,12 @@ int bh_create(bh_ctx **out, const bh_params *p, void *hip_stream)
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipMalloc((void **)&c->misc, sizeof(DevMisc)) != hipSuccess ||
+        hipMalloc((void **)&c->bb_part, 6 * 1024 * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->misc_h, sizeof(DevMisc), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->red_h, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         if (c->misc) (void)hipFree(c->misc);
+        if (c->bb_part) (void)hipFree(c->bb_part);
         if (c->misc_h) (void)hipHostFree(c->misc_h);
         if (c->red_h) (void)hipHostFree(c->red_h);
         delete c;
@@ -300,7 +302,20 @@ int bh_create(bh_ctx **out, const bh_params *p, void *hip_stream)
             return BH_EDEVICE;
         }
     }
+    for (int i = 0; i < 2 * bh_ctx::kWalkRing; ++i) {
+        if (hipEventCreate(&c->wev[i]) != hipSuccess) {
+            (void)hipGetLastError();
+            bh_destroy(c);
+            return BH_EDEVICE;
+        }
+    }
     memset(c->misc_h, 0, sizeof(DevMisc));
+    if (hipMemsetAsync(c->misc, 0, sizeof(DevMisc), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        bh_destroy(c);
+        return BH_EDEVICE;
+    }
     if (q.max_n > 0) {
         int st = ensure_capacity(c, q.max_n);
         if (st) {
@@ -319,10 +334,13 @@ int bh_destroy(bh_ctx *c)
     else (void)hipDeviceSynchronize();
     free_buffers(c);
     if (c->misc) (void)hipFree(c->misc);
+    if (c->bb_part) (void)hipFree(c->bb_part);
     if (c->misc_h) (void)hipHostFree(c->misc_h);
     if (c->red_h) (void)hipHostFree(c->red_h);
     for (int i = 0; i < 8; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    for (int i = 0; i < 2 * bh_ctx::kWalkRing; ++i)
+        if (c->wev[i]) (void)hipEventDestroy(c->wev[i]);
     delete c;
     return BH_OK;
 }
@@ -373,8 +391,7 @@ int bh_leapfrog_step(bh_ctx *c, double dt)
     if (!std::isfinite(dt)) return fail(c, BH_EINVAL, "dt must be finite");
     if (!c->built || !c->have_forces) return fail(c, BH_ESTATE, "leapfrog_step needs a prior compute_forces");
     const float theta = c->theta, eps = c->eps;
-    TRY_HIP(c, launch_kick(c, 0.5 * dt));
-    TRY_HIP(c, launch_drift(c, dt));
+    TRY_HIP(c, launch_kick_drift(c, 0.5 * dt, dt));
     int st = rebuild(c);
     if (st) return st;
     st = forces(c, theta, eps, nullptr, nullptr);
@@ -454,6 +471,12 @@ int bh_stats_get(bh_ctx *c, bh_stats *out)
     if (c->have_forces && hipEventElapsedTime(&ms, c->ev[6], c->ev[7]) == hipSuccess) s.ms_walk = ms;
     (void)hipGetLastError();
     s.device_bytes = c->bytes;
+    walk_timer_harvest(c, true);
+    s.ms_walk_kernel = c->walk_ms_last;
+    s.walk_kernel_ms_total = c->walk_ms_total;
+    s.walk_kernel_launches = c->walk_launches;
+    s.total_npp = (int64_t)c->misc_h->tot_npp;
+    s.total_npc = (int64_t)c->misc_h->tot_npc;
     *out = s;
     if (c->misc_h->walk_overflow) return fail(c, BH_EDEVICE, "walk list overflow");
     return BH_OK;

@@ -32,10 +32,20 @@ constexpr int kTreeTile = 256;
 constexpr int kWalkWaves = 4;
 constexpr int kStackCap = 1408;        // >= 21 levels x 64 ranges (see walk.hip)
 
+// Per-cell record read by the walk: everything the opening test and a
+// particle-cell interaction need, in one 64-byte line.
+struct alignas(64) WalkCell {
+    double cx, cy, cz;   // centre of mass (float64)
+    float mass;          // cell mass (float32)
+    float rcrit2;        // squared opening radius of Eq. (1) (float32)
+    uint32_t link;       // first child (node) or first particle (leaf)
+    uint32_t info;       // number of children (node) or count | 0x80000000 (leaf)
+    float s3[6];         // 3 S: xx, yy, zz, xy, xz, yz (second moment about the centre of mass)
+};
+static_assert(sizeof(WalkCell) == 64, "walk record must be one 64-byte block");
+
 // Small device-side scalars shared by the build and walk kernels.
 struct DevMisc {
-    unsigned long long bb_min[3];      // order-preserving images of the minima
-    unsigned long long bb_max[3];
     uint32_t nonfinite;
     uint32_t pad0;
     double lo[3];
@@ -47,10 +57,12 @@ struct DevMisc {
     uint32_t nleaves;
     uint32_t ngroups;
     uint32_t depth;
-    uint32_t walk_next;                // group work counter
+    uint32_t walk_next;                // group work counter of the walk
     uint32_t walk_overflow;            // set if a per-wave list would overflow
     unsigned long long sum_npp;
     unsigned long long sum_npc;
+    unsigned long long tot_npp;        // never reset: totals over all walks
+    unsigned long long tot_npc;
 };
 
 }  // namespace bh
@@ -94,13 +106,15 @@ struct bh_ctx {
 
     // ---- cells (level-major, key order within a level) ----
     uint32_t *c_first = nullptr, *c_count = nullptr, *c_child = nullptr, *c_nchild = nullptr;
-    uint32_t *c_parent = nullptr, *c_arrive = nullptr;
+    uint32_t *c_parent = nullptr;
     uint8_t *c_level = nullptr, *c_leaf = nullptr;
     double4 *c_com = nullptr;                // centre of mass, mass (float64)
     double *c_S = nullptr;                   // [c][6] float64 second moment
     float4 *c_q0 = nullptr, *c_q1 = nullptr; // float32 walk multipoles
     float *c_rcrit2 = nullptr;
-    uint4 *c_walk = nullptr;                 // per-cell walk record (walk.hip)
+    bh::WalkCell *c_rec = nullptr;           // per-cell walk record (walk.hip)
+    uint32_t *walk_spill = nullptr;          // per-wave overflow of the walk stack
+    int64_t walk_spill_waves = 0;
 
     // ---- groups ----
     uint32_t *g_first = nullptr, *g_count = nullptr, *g_npp = nullptr, *g_npc = nullptr;
@@ -111,12 +125,20 @@ struct bh_ctx {
     bh::DevMisc *misc = nullptr;             // device
     bh::DevMisc *misc_h = nullptr;           // pinned host mirror
     double *red = nullptr;                   // energy partial sums
+    double *bb_part = nullptr;               // bounding-box block partials [6][1024]
     int64_t red_len = 0;
     double *red_h = nullptr;                 // pinned host copy of the 6 sums
 
     hipEvent_t ev[8] = {};
     bh_stats stats{};
     int lanes_max = 0;
+
+    // start/end events around each walk-kernel launch, harvested lazily
+    static constexpr int kWalkRing = 64;
+    hipEvent_t wev[2 * kWalkRing] = {};
+    int wring_head = 0, wring_count = 0;
+    double walk_ms_total = 0.0, walk_ms_last = 0.0;
+    int64_t walk_launches = 0;
 };
 
 namespace bh {
@@ -134,7 +156,7 @@ hipError_t launch_tree(bh_ctx *c, int64_t n);
 hipError_t launch_groups(bh_ctx *c, int64_t n);
 hipError_t launch_group_boxes(bh_ctx *c, int64_t ngroups);
 hipError_t launch_moments(bh_ctx *c, int64_t ncells);
-hipError_t launch_rcrit(bh_ctx *c, int64_t ncells, float theta);
+hipError_t launch_rcrit(bh_ctx *c, int64_t ncells, float theta);   // also fills c_rec
 
 // sort.hip
 hipError_t radix_sort_pairs(bh_ctx *c, int64_t n);      // key[0]/val[0] -> key[0]/val[0]
@@ -147,11 +169,14 @@ int64_t scan_tmp_words(int64_t n);
 
 // walk.hip
 hipError_t launch_walk(bh_ctx *c, float theta, float eps);
+void walk_timer_harvest(bh_ctx *c, bool block);
+hipEvent_t *walk_timer_slot(bh_ctx *c);
 hipError_t launch_scatter(bh_ctx *c, float *acc, float *pot);
 
 // integrate.hip
 hipError_t launch_kick(bh_ctx *c, double h);
 hipError_t launch_drift(bh_ctx *c, double dt);
+hipError_t launch_kick_drift(bh_ctx *c, double h, double dt);
 hipError_t launch_energy(bh_ctx *c);
 hipError_t launch_set_velocities(bh_ctx *c, const double *vel);
 hipError_t launch_get_state(bh_ctx *c, double *pos, double *vel, float *acc, float *pot);
@@ -190,27 +215,46 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_incl_scan_add(T v)
+// Inclusive prefix sum over the 64 lanes with DPP: shifts of 1, 2, 4, 8 lanes
+// inside each row of 16 (lanes shifted in from outside the row read 0), then the
+// last lane of row 0 / row 2 is broadcast into rows 1 / 3, then lane 31 into
+// rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan_add(uint32_t v)
 {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T o = __shfl_up(v, d, kWave);
-        if (l >= d) v += o;
-    }
-    return v;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (uint32_t)x;
 }
 
-__device__ __forceinline__ int wave_incl_scan_max(int v)
+// Inclusive prefix maximum over the 64 lanes (same pattern; lanes outside a row
+// or a disabled row contribute INT_MIN).
+__device__ __forceinline__ int wave_incl_scan_max(int x)
 {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        int o = __shfl_up(v, d, kWave);
-        if (l >= d) v = v > o ? v : o;
-    }
-    return v;
+    const int lo = (int)0x80000000;
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x111, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x112, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x114, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x118, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
+// value of lane i (i uniform across the wavefront)
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int i)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, i);
+}
+
+// sum over the 64 lanes, the same in every lane
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    return lane_value(wave_incl_scan_add(v), kWave - 1);
 }
 
 template <typename T>
@@ -224,18 +268,6 @@ __device__ __forceinline__ T wave_sum(T v)
 __device__ __forceinline__ uint32_t readfirst(uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-
-// Order-preserving map of a double to an unsigned integer (for atomic min/max).
-__device__ __forceinline__ unsigned long long dbl_order(double x)
-{
-    unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double dbl_unorder(unsigned long long b)
-{
-    b = (b >> 63) ? (b & 0x7fffffffffffffffull) : ~b;
-    return __longlong_as_double((long long)b);
 }
 
 }  // namespace bh

@@ -65,10 +65,6 @@ __device__ __forceinline__ uint32_t coord_to_int(double x, double lo, double sca
 __global__ void misc_reset_kernel(DevMisc *m)
 {
     const int t = threadIdx.x;
-    if (t < 3) {
-        m->bb_min[t] = ~0ull;
-        m->bb_max[t] = 0ull;
-    }
     if (t == 0) {
         m->nonfinite = 0;
         m->nleaves = 0;
@@ -79,38 +75,47 @@ __global__ void misc_reset_kernel(DevMisc *m)
 
 struct AosSrc {
     const double *p;
-    __device__ double get(int64_t i, int k) const { return p[3 * i + k]; }
+    __device__ void get3(int64_t i, double *v) const
+    {
+        v[0] = p[3 * i];
+        v[1] = p[3 * i + 1];
+        v[2] = p[3 * i + 2];
+    }
 };
 struct P4Src {
     const double4 *p;
-    __device__ double get(int64_t i, int k) const
+    __device__ void get3(int64_t i, double *v) const
     {
-        const double4 v = p[i];
-        return k == 0 ? v.x : (k == 1 ? v.y : v.z);
+        const double4 q = p[i];
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
     }
 };
 
+constexpr int kBBoxBlocks = 1024;
+
+// Per-block minima and maxima of each axis; part[k * nblk + b], k = 0..2 minima,
+// 3..5 maxima.  A non-finite coordinate sets bit 0 of the misc flags.
 template <typename Src>
-__global__ void __launch_bounds__(kBlock) bbox_kernel(Src src, int64_t n, DevMisc *m)
+__global__ void __launch_bounds__(kBlock) bbox_kernel(Src src, int64_t n, double *__restrict__ part,
+                                                      DevMisc *m)
 {
     double lo[3] = {INFINITY, INFINITY, INFINITY};
     double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    uint32_t bad = 0;
+    bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
+        double v[3];
+        src.get3(i, v);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            double v = src.get(i, k);
-            if (!isfinite(v)) bad = 1;
-            lo[k] = fmin(lo[k], v);
-            hi[k] = fmax(hi[k], v);
+            bad |= !isfinite(v[k]);
+            lo[k] = fmin(lo[k], v[k]);
+            hi[k] = fmax(hi[k], v[k]);
         }
     }
-    __shared__ double s_lo[3][kBlock / kWave], s_hi[3][kBlock / kWave];
-    __shared__ uint32_t s_bad;
-    if (threadIdx.x == 0) s_bad = 0;
-    __syncthreads();
-    if (bad) atomicOr(&s_bad, 1u);
+    __shared__ double s_v[6][kBlock / kWave];
     const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -121,34 +126,49 @@ __global__ void __launch_bounds__(kBlock) bbox_kernel(Src src, int64_t n, DevMis
             b = fmax(b, __shfl_xor(b, d, kWave));
         }
         if (l == 0) {
-            s_lo[k][w] = a;
-            s_hi[k][w] = b;
+            s_v[k][w] = a;
+            s_v[3 + k][w] = b;
         }
     }
+    if (ballot(bad) && l == 0) atomicOr(&m->nonfinite, 1u);
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < 6) {
         const int k = threadIdx.x;
-        double a = s_lo[k][0], b = s_hi[k][0];
-        for (int i = 1; i < kBlock / kWave; ++i) {
-            a = fmin(a, s_lo[k][i]);
-            b = fmax(b, s_hi[k][i]);
-        }
-        if (a <= b) {  // the block saw at least one finite point on this axis
-            atomicMin(&m->bb_min[k], dbl_order(a));
-            atomicMax(&m->bb_max[k], dbl_order(b));
-        }
+        double a = s_v[k][0];
+        for (int i = 1; i < kBlock / kWave; ++i) a = k < 3 ? fmin(a, s_v[k][i]) : fmax(a, s_v[k][i]);
+        part[(int64_t)k * gridDim.x + blockIdx.x] = a;
     }
-    if (threadIdx.x == 0 && s_bad) atomicOr(&m->nonfinite, 1u);
 }
 
-// Cube side = largest extent (1 if all extents vanish); scale = 2^20 / side.
-__global__ void domain_kernel(DevMisc *m)
+// Reduce the block partials; cube side = largest extent (1 if all extents
+// vanish); scale = 2^20 / side.
+__global__ void __launch_bounds__(kBlock) domain_kernel(const double *__restrict__ part, int nblk,
+                                                        DevMisc *m)
 {
+    __shared__ double s_v[6][kBlock / kWave];
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    for (int k = 0; k < 6; ++k) {
+        double a = k < 3 ? INFINITY : -INFINITY;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) {
+            const double v = part[(int64_t)k * nblk + b];
+            a = k < 3 ? fmin(a, v) : fmax(a, v);
+        }
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const double o = __shfl_xor(a, d, kWave);
+            a = k < 3 ? fmin(a, o) : fmax(a, o);
+        }
+        if (l == 0) s_v[k][w] = a;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     double side = 0.0;
     for (int k = 0; k < 3; ++k) {
-        double lo = dbl_unorder(m->bb_min[k]);
-        double hi = dbl_unorder(m->bb_max[k]);
+        double lo = INFINITY, hi = -INFINITY;
+        for (int i = 0; i < kBlock / kWave; ++i) {
+            lo = fmin(lo, s_v[k][i]);
+            hi = fmax(hi, s_v[3 + k][i]);
+        }
         m->lo[k] = lo;
         double e = hi - lo;
         if (e > side) side = e;
@@ -166,9 +186,11 @@ keys_kernel(Src src, int64_t n, const DevMisc *__restrict__ m, uint64_t *__restr
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const double scale = m->scale;
-    uint32_t qx = coord_to_int(src.get(i, 0), m->lo[0], scale);
-    uint32_t qy = coord_to_int(src.get(i, 1), m->lo[1], scale);
-    uint32_t qz = coord_to_int(src.get(i, 2), m->lo[2], scale);
+    double v[3];
+    src.get3(i, v);
+    uint32_t qx = coord_to_int(v[0], m->lo[0], scale);
+    uint32_t qy = coord_to_int(v[1], m->lo[1], scale);
+    uint32_t qz = coord_to_int(v[2], m->lo[2], scale);
     key[i] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
     val[i] = (uint32_t)i;
 }
@@ -225,7 +247,7 @@ split_leaf_kernel(const uint64_t *__restrict__ key, int64_t n, int nleaf, uint8_
     const int H = nleaf;                          // halo on each side
     const int W = kTreeTile + 2 * H;              // split values held in LDS
     uint8_t *s_split = s_dyn;                     // [W]
-    uint8_t *s_pl = s_dyn + ((W + 15) & ~15);     // [kTreeTile][H] left prefix minima
+    uint8_t *s_pl = s_dyn + ((W + 15) & ~15);     // [H][kTreeTile] left prefix minima
     __shared__ uint32_t s_cnt[kLevels];
     __shared__ uint32_t s_leaves;
 
@@ -253,7 +275,7 @@ split_leaf_kernel(const uint64_t *__restrict__ key, int64_t n, int nleaf, uint8_
         for (int a = 0; a < H; ++a) {
             uint8_t v = (i - a <= 0) ? (uint8_t)0 : s_split[H + t - a];
             run = v < run ? v : run;
-            s_pl[t * H + a] = run;
+            s_pl[a * kTreeTile + t] = run;
         }
         // right prefix minima PR[b] over split(i + b'), b' = 1..b, combined with
         // PL[H - b]: lam = min_b max(PL[H - b], PR[b])
@@ -262,7 +284,7 @@ split_leaf_kernel(const uint64_t *__restrict__ key, int64_t n, int nleaf, uint8_
         for (int b = 1; b <= H; ++b) {
             uint8_t v = (i + b >= n) ? (uint8_t)0 : s_split[H + t + b];
             run = v < run ? v : run;
-            uint8_t pl = s_pl[t * H + (H - b)];
+            uint8_t pl = s_pl[(H - b) * kTreeTile + t];
             uint8_t mx = pl > run ? pl : run;
             best = mx < best ? mx : best;
         }
@@ -418,36 +440,48 @@ cell_ends_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__ 
     }
 }
 
-// group counts and tight boxes
+// group counts and tight boxes: one wavefront per group, lanes over particles
 __global__ void __launch_bounds__(kBlock)
 group_boxes_kernel(const uint32_t *__restrict__ g_first, int64_t ngroups, int64_t n,
                    const double4 *__restrict__ p4, uint32_t *__restrict__ g_count,
                    double4 *__restrict__ g_centre, float4 *__restrict__ g_half)
 {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= ngroups) return;
-    const uint32_t s = g_first[g];
-    const uint32_t e = (g + 1 < ngroups) ? g_first[g + 1] : (uint32_t)n;
+    constexpr int kSeg = 16;                       // lanes per group
+    const int64_t g = (int64_t)blockIdx.x * (kBlock / kSeg) + threadIdx.x / kSeg;
+    const int l = threadIdx.x % kSeg;
+    const bool valid = g < ngroups;
+    const uint32_t s = valid ? g_first[g] : 0u;
+    const uint32_t e = valid ? ((g + 1 < ngroups) ? g_first[g + 1] : (uint32_t)n) : 0u;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (uint32_t j = s; j < e; ++j) {
+    for (uint32_t j = s + l; j < e; j += kSeg) {
         const double4 p = p4[j];
         lo[0] = fmin(lo[0], p.x); hi[0] = fmax(hi[0], p.x);
         lo[1] = fmin(lo[1], p.y); hi[1] = fmax(hi[1], p.y);
         lo[2] = fmin(lo[2], p.z); hi[2] = fmax(hi[2], p.z);
     }
-    g_count[g] = e - s;
-    g_centre[g] = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2]),
-                               0.0);
-    g_half[g] = make_float4((float)(0.5 * (hi[0] - lo[0])), (float)(0.5 * (hi[1] - lo[1])),
-                            (float)(0.5 * (hi[2] - lo[2])), 0.0f);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int d = kSeg / 2; d > 0; d >>= 1) {
+            lo[k] = fmin(lo[k], __shfl_xor(lo[k], d, kWave));
+            hi[k] = fmax(hi[k], __shfl_xor(hi[k], d, kWave));
+        }
+    }
+    if (valid && l == 0) {
+        g_count[g] = e - s;
+        g_centre[g] = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]),
+                                   0.5 * (lo[2] + hi[2]), 0.0);
+        g_half[g] = make_float4((float)(0.5 * (hi[0] - lo[0])), (float)(0.5 * (hi[1] - lo[1])),
+                                (float)(0.5 * (hi[2] - lo[2])), 0.0f);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// moments: float64 monopole and second moment, leaves from particles, nodes from
-// children; the last child to finish computes its parent (children are always
-// read in array order, so the sums do not depend on which thread does it).
+// moments: float64 monopole and second moment, level by level from the deepest
+// (Sect. 3.2): a leaf from its particles, a node from its children (one level
+// deeper, finished by the previous launch), both in array order.
 
-__device__ __forceinline__ void store_walk_multipole(uint32_t c, double M, const double *S,
+__device__ __forceinline__ void store_walk_multipole(uint32_t c, const double *S,
                                                      float4 *__restrict__ q0, float4 *__restrict__ q1)
 {
     const double tr = (S[0] + S[1]) + S[2];
@@ -455,23 +489,27 @@ __device__ __forceinline__ void store_walk_multipole(uint32_t c, double M, const
                         (float)(3.0 * S[3]));
     q1[c] = make_float4((float)(3.0 * S[4]), (float)(3.0 * S[5]), (float)(0.5 * tr),
                         (float)(1.5 * tr));
-    (void)M;
 }
 
+// mode 0: the leaves among cells [begin, begin + count); mode 1: the nodes
+template <int kMode>
 __global__ void __launch_bounds__(kBlock)
-moments_kernel(int64_t ncells, const uint8_t *__restrict__ c_leaf,
-               const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
-               const uint32_t *__restrict__ c_parent, const uint32_t *__restrict__ c_child,
-               const uint32_t *__restrict__ c_nchild, uint32_t *__restrict__ arrive,
-               const double4 *__restrict__ p4, double4 *c_com, double *c_S,
-               float4 *__restrict__ q0, float4 *__restrict__ q1)
+moments_level_kernel(uint32_t begin, uint32_t count, const uint8_t *__restrict__ c_leaf,
+                     const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
+                     const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
+                     const double4 *__restrict__ p4, double4 *__restrict__ c_com,
+                     double *__restrict__ c_S, float4 *__restrict__ q0, float4 *__restrict__ q1)
 {
-    const int64_t c0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c0 >= ncells || !c_leaf[c0]) return;
-    uint32_t c = (uint32_t)c0;
-    {
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= count) return;
+    const uint32_t c = begin + t;
+    const bool leaf = c_leaf[c] != 0;
+    if (leaf != (kMode == 0)) return;
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    double S[6] = {0, 0, 0, 0, 0, 0};
+    double cx, cy, cz;
+    if (leaf) {
         const uint32_t s = c_first[c], e = s + c_count[c];
-        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
         for (uint32_t j = s; j < e; ++j) M = M + p4[j].w;
         for (uint32_t j = s; j < e; ++j) {
             const double4 p = p4[j];
@@ -479,28 +517,17 @@ moments_kernel(int64_t ncells, const uint8_t *__restrict__ c_leaf,
             sy = sy + p.w * p.y;
             sz = sz + p.w * p.z;
         }
-        const double cx = sx / M, cy = sy / M, cz = sz / M;
-        double S[6] = {0, 0, 0, 0, 0, 0};
+        cx = sx / M;
+        cy = sy / M;
+        cz = sz / M;
         for (uint32_t j = s; j < e; ++j) {
             const double4 p = p4[j];
             const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
             S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
             S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
         }
-        c_com[c] = make_double4(cx, cy, cz, M);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)c + k] = S[k];
-        store_walk_multipole(c, M, S, q0, q1);
-    }
-    while (c != 0) {
-        const uint32_t p = c_parent[c];
-        if ((int64_t)p >= ncells) return;
-        // release our cell's moments, then count in; the last child carries on
-        const uint32_t old = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1u != c_nchild[p]) return;
-        const uint32_t s = c_child[p], e = s + c_nchild[p];
-        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    } else {
+        const uint32_t s = c_child[c], e = s + c_nchild[c];
         for (uint32_t k = s; k < e; ++k) M = M + c_com[k].w;
         for (uint32_t k = s; k < e; ++k) {
             const double4 q = c_com[k];
@@ -508,8 +535,9 @@ moments_kernel(int64_t ncells, const uint8_t *__restrict__ c_leaf,
             sy = sy + q.w * q.y;
             sz = sz + q.w * q.z;
         }
-        const double cx = sx / M, cy = sy / M, cz = sz / M;
-        double S[6] = {0, 0, 0, 0, 0, 0};
+        cx = sx / M;
+        cy = sy / M;
+        cz = sz / M;
         for (uint32_t k = s; k < e; ++k) {
             const double4 q = c_com[k];
             const double ex = q.x - cx, ey = q.y - cy, ez = q.z - cz;
@@ -518,21 +546,24 @@ moments_kernel(int64_t ncells, const uint8_t *__restrict__ c_leaf,
             S[2] += Sk[2] + q.w * ez * ez; S[3] += Sk[3] + q.w * ex * ey;
             S[4] += Sk[4] + q.w * ex * ez; S[5] += Sk[5] + q.w * ey * ez;
         }
-        c_com[p] = make_double4(cx, cy, cz, M);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)p + k] = S[k];
-        store_walk_multipole(p, M, S, q0, q1);
-        c = p;
     }
+    c_com[c] = make_double4(cx, cy, cz, M);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)c + k] = S[k];
+    store_walk_multipole(c, S, q0, q1);
 }
 
 // Eq. (1): r_crit = l/theta + delta with l = L 2^-level and delta the distance of
-// the centre of mass from the cell's geometric centre; stored as float32 r_crit^2.
+// the centre of mass from the cell's geometric centre; stored as float32 r_crit^2,
+// together with the rest of the cell's walk record.
 __global__ void __launch_bounds__(kBlock)
 rcrit_kernel(int64_t ncells, float theta, const DevMisc *__restrict__ m,
              const uint8_t *__restrict__ c_level, const uint32_t *__restrict__ c_first,
+             const uint32_t *__restrict__ c_count, const uint32_t *__restrict__ c_child,
+             const uint32_t *__restrict__ c_nchild, const uint8_t *__restrict__ c_leaf,
              const uint64_t *__restrict__ skey, const double4 *__restrict__ c_com,
-             float *__restrict__ rcrit2)
+             const float4 *__restrict__ q0, const float4 *__restrict__ q1,
+             float *__restrict__ rcrit2, WalkCell *__restrict__ rec)
 {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= ncells) return;
@@ -546,17 +577,28 @@ rcrit_kernel(int64_t ncells, float theta, const DevMisc *__restrict__ m,
     const double dx = cm.x - gx, dy = cm.y - gy, dz = cm.z - gz;
     const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
     const double r = l / (double)theta + delta;
-    rcrit2[c] = (float)(r * r);
+    const float r2 = (float)(r * r);
+    rcrit2[c] = r2;
+    const bool leaf = c_leaf[c] != 0;
+    const float4 a = q0[c], b = q1[c];
+    WalkCell w;
+    w.cx = cm.x;
+    w.cy = cm.y;
+    w.cz = cm.z;
+    w.mass = (float)cm.w;
+    w.rcrit2 = r2;
+    w.link = leaf ? c_first[c] : c_child[c];
+    w.info = leaf ? (c_count[c] | 0x80000000u) : c_nchild[c];
+    w.s3[0] = a.x;
+    w.s3[1] = a.y;
+    w.s3[2] = a.z;
+    w.s3[3] = a.w;
+    w.s3[4] = b.x;
+    w.s3[5] = b.y;
+    rec[c] = w;
 }
 
 __global__ void fill_u8_kernel(uint8_t *p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
-}
-
-__global__ void fill_u32_kernel(uint32_t *p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -599,15 +641,16 @@ hipError_t launch_bbox(bh_ctx *c, const double *pos_aos, int64_t n)
     hipLaunchKernelGGL(misc_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
     BH_LAUNCH_CHECK();
     int grid = grid_for(n, kBlock);
-    if (grid > 2048) grid = 2048;
+    if (grid > kBBoxBlocks) grid = kBBoxBlocks;
     if (pos_aos)
         hipLaunchKernelGGL(bbox_kernel<AosSrc>, dim3(grid), dim3(kBlock), 0, c->stream,
-                           AosSrc{pos_aos}, n, c->misc);
+                           AosSrc{pos_aos}, n, c->bb_part, c->misc);
     else
         hipLaunchKernelGGL(bbox_kernel<P4Src>, dim3(grid), dim3(kBlock), 0, c->stream,
-                           P4Src{c->p4[c->cur]}, n, c->misc);
+                           P4Src{c->p4[c->cur]}, n, c->bb_part, c->misc);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(domain_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
+    hipLaunchKernelGGL(domain_kernel, dim3(1), dim3(kBlock), 0, c->stream, c->bb_part, grid,
+                       c->misc);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -682,7 +725,7 @@ hipError_t launch_groups(bh_ctx *c, int64_t n)
 hipError_t launch_group_boxes(bh_ctx *c, int64_t ngroups)
 {
     if (ngroups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(group_boxes_kernel, dim3(grid_for(ngroups, kBlock)), dim3(kBlock), 0,
+    hipLaunchKernelGGL(group_boxes_kernel, dim3(grid_for(ngroups, kBlock / 16)), dim3(kBlock), 0,
                        c->stream, c->g_first, ngroups, c->n, c->p4[c->cur], c->g_count,
                        c->g_centre, c->g_half);
     BH_LAUNCH_CHECK();
@@ -691,23 +734,32 @@ hipError_t launch_group_boxes(bh_ctx *c, int64_t ngroups)
 
 hipError_t launch_moments(bh_ctx *c, int64_t ncells)
 {
-    int fg = grid_for(ncells, 256);
-    if (fg > 4096) fg = 4096;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(fg), dim3(256), 0, c->stream, c->c_arrive, ncells);
+    // level counts were read back with the tree; deepest level first
+    const DevMisc &m = *c->misc_h;
+    // every leaf, whatever its level, from its particles
+    hipLaunchKernelGGL(moments_level_kernel<0>, dim3(grid_for(ncells, kBlock)), dim3(kBlock), 0,
+                       c->stream, 0u, (uint32_t)ncells, c->c_leaf, c->c_first, c->c_count,
+                       c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(moments_kernel, dim3(grid_for(ncells, kBlock)), dim3(kBlock), 0, c->stream,
-                       ncells, c->c_leaf, c->c_first, c->c_count, c->c_parent, c->c_child,
-                       c->c_nchild, c->c_arrive, c->p4[c->cur], c->c_com, c->c_S, c->c_q0,
-                       c->c_q1);
-    BH_LAUNCH_CHECK();
+    // nodes from their children, deepest level first (the deepest level holds only leaves)
+    for (int lev = (int)m.depth - 1; lev >= 0; --lev) {
+        const uint32_t cnt = m.level_count[lev];
+        if (!cnt) continue;
+        hipLaunchKernelGGL(moments_level_kernel<1>, dim3(grid_for(cnt, kBlock)), dim3(kBlock), 0,
+                           c->stream, m.level_offset[lev], cnt, c->c_leaf, c->c_first, c->c_count,
+                           c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0,
+                           c->c_q1);
+        BH_LAUNCH_CHECK();
+    }
     return hipSuccess;
 }
 
 hipError_t launch_rcrit(bh_ctx *c, int64_t ncells, float theta)
 {
     hipLaunchKernelGGL(rcrit_kernel, dim3(grid_for(ncells, kBlock)), dim3(kBlock), 0, c->stream,
-                       ncells, theta, c->misc, c->c_level, c->c_first, c->key[0], c->c_com,
-                       c->c_rcrit2);
+                       ncells, theta, c->misc, c->c_level, c->c_first, c->c_count, c->c_child,
+                       c->c_nchild, c->c_leaf, c->key[0], c->c_com, c->c_q0, c->c_q1,
+                       c->c_rcrit2, c->c_rec);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -26,6 +26,26 @@ kick_kernel(int64_t n, const float4 *__restrict__ acc4, double4 *__restrict__ v4
     v4[i] = v;
 }
 
+// v += a h; x += v dt in one pass (the first half of a kick-drift-kick step)
+__global__ void __launch_bounds__(kBlock)
+kick_drift_kernel(int64_t n, const float4 *__restrict__ acc4, double4 *__restrict__ v4,
+                  double4 *__restrict__ p4, double h, double dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float4 a = acc4[i];
+    double4 v = v4[i];
+    v.x = v.x + (double)a.x * h;
+    v.y = v.y + (double)a.y * h;
+    v.z = v.z + (double)a.z * h;
+    v4[i] = v;
+    double4 p = p4[i];
+    p.x = p.x + v.x * dt;
+    p.y = p.y + v.y * dt;
+    p.z = p.z + v.z * dt;
+    p4[i] = p;
+}
+
 __global__ void __launch_bounds__(kBlock)
 drift_kernel(int64_t n, const double4 *__restrict__ v4, double4 *__restrict__ p4, double dt)
 {
@@ -70,13 +90,25 @@ energy_partial_kernel(int64_t n, const double4 *__restrict__ p4, const double4 *
     if (threadIdx.x < 5) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void energy_final_kernel(const double *__restrict__ part, int nblk, double *__restrict__ out)
+// Fixed-order sum of the block partials: strided per thread, then a tree.
+__global__ void __launch_bounds__(kBlock)
+energy_final_kernel(const double *__restrict__ part, int nblk, double *__restrict__ out)
 {
-    const int k = threadIdx.x;
-    if (k >= 5) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)k * nblk + b];
-    out[k] = s;
+    __shared__ double sh[5][kBlock];
+    for (int k = 0; k < 5; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) s += part[(int64_t)k * nblk + b];
+        sh[k][threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int d = kBlock / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -134,6 +166,14 @@ hipError_t launch_kick(bh_ctx *c, double h)
     return hipSuccess;
 }
 
+hipError_t launch_kick_drift(bh_ctx *c, double h, double dt)
+{
+    hipLaunchKernelGGL(kick_drift_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
+                       c->acc4, c->v4[c->cur], c->p4[c->cur], h, dt);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
 hipError_t launch_drift(bh_ctx *c, double dt)
 {
     hipLaunchKernelGGL(drift_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
@@ -149,7 +189,7 @@ hipError_t launch_energy(bh_ctx *c)
     hipLaunchKernelGGL(energy_partial_kernel, dim3(nblk), dim3(kBlock), 0, c->stream, c->n,
                        c->p4[c->cur], c->v4[c->cur], c->acc4, c->red);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, c->stream, c->red, nblk,
+    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kBlock), 0, c->stream, c->red, nblk,
                        c->red + 5 * kRedBlocks);
     BH_LAUNCH_CHECK();
     return hipSuccess;

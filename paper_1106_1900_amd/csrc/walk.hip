@@ -1,29 +1,39 @@
 // walk.hip - the group walk and force evaluation (Sect. 2.2, 3.3).
 //
 // One wavefront (64 lanes) takes one group of at most 64 particles.  It walks
-// the tree breadth-first from the root: up to 64 cells are tested at a time,
-// one per lane, with the opening test of Eq. (1).  An accepted cell goes to the
-// cell list, an opened leaf to the particle list, an opened node pushes its
-// contiguous children.  As soon as a list holds 64 entries it is evaluated: the
-// 64 sources are staged in LDS as float32 offsets from the group's box centre
-// and every lane accumulates them on its particle.  Groups of at most 32, 21 or
-// 16 particles use 2, 3 or 4 lanes per particle, each lane taking every k-th
-// source, and the lanes are summed at the end (the paper's several threads per
-// particle).
+// the tree from the root: up to 64 cells are tested at a time, one per lane,
+// with the opening test of Eq. (1).  An accepted cell goes to the cell list, an
+// opened leaf to the particle list, an opened node pushes its contiguous
+// children.  As soon as a list holds 64 entries it is evaluated: the 64 sources
+// are staged in LDS as float32 offsets from the group's box centre and every
+// lane accumulates them on its particle.  A group of g particles uses
+// k = floor(64 / g) lanes per particle (the paper uses up to 4 threads per
+// particle); lane (p, s) takes sources s, s + k, s + 2k, ... of each tile and
+// the k partial sums are added at the end.
 //
 // Per wavefront, in LDS:
-//   stack : pending cell ranges (first cell, count <= 8) packed in 32 bits.  A
-//           pop takes up to 64 cells from the top; each pop pushes at most 64
-//           ranges, all deeper than anything popped before them that is still on
-//           the stack, so at most 64 ranges per level (21 levels) are ever held.
+//   stack : pending cell ranges (first cell, count <= 8) packed in 32 bits, used
+//           last-in first-out.  A pop takes up to 64 cells from the top; each pop
+//           pushes at most 64 ranges, all deeper than anything popped before them
+//           that is still held, so at most 64 ranges per level (21 levels, 1344)
+//           can be on it.  The first 256 entries live in LDS; deeper entries go to
+//           a per-wavefront region in device memory (rare: a Plummer sphere of 2^20
+//           particles needs about 50 at theta = 0.75 and 140 at theta = 0.4).
 //   pc    : accepted cells (< 64 between evaluations, 128 entries).
 //   pp    : opened leaves as (first particle, count) ranges (< 64 particles
 //           pending between evaluations, so < 128 ranges).
-//   tile  : 64 staged sources (3 x float4 for a cell, 1 x float4 for a particle).
+//   tile  : 64 staged sources plus padding (far away, zero mass) so that every
+//           lane runs the same number of iterations.
 //
-// Every pair goes through float32 arithmetic on group-centred offsets; each
-// 64-source tile is summed in plain float32 and the tile sums are added to the
-// particle's totals with an error-free two-sum (compensated accumulation).
+// Every pair goes through float32 arithmetic on group-centred offsets; each tile
+// is summed in plain float32 and the tile sums are added to the particle's
+// totals with an error-free two-sum (compensated accumulation).
+//
+// Groups are handed out in Morton order from one device-wide counter, so at any
+// moment all 256 CUs work on neighbouring groups whose interaction lists overlap:
+// the active part of the tree stays small and shared in the Infinity Cache.
+// (Splitting the groups into per-XCD ranges, so that each XCD's L2 sees one
+// region, measured 17% slower at N = 2^20.)
 #include "bh_internal.h"
 
 #pragma clang fp contract(off)
@@ -34,6 +44,22 @@ namespace {
 constexpr int kWalkBlock = kWalkWaves * kWave;
 constexpr int kPcCap = 128;
 constexpr int kPpCap = 128;
+constexpr int kLdsStack = 256;
+constexpr int kSpillPerWave = kStackCap - kLdsStack;
+// Lane (p, s) reads tile entries s + t k for t < ceil(cnt / k): at most index 83
+// for k = floor(64 / g); the tail is padding.
+constexpr int kTileCap = 96;
+constexpr float kFar = 1.0e30f;
+#ifndef BH_WALK_UNROLL
+#define BH_WALK_UNROLL 4
+#endif
+#ifndef BH_WALK_WAVES_PER_EU
+#define BH_WALK_WAVES_PER_EU 4
+#endif
+constexpr int kUnroll = BH_WALK_UNROLL;   // tile entries per loop trip
+#ifndef BH_WALK_BLOCKS_PER_CU
+#define BH_WALK_BLOCKS_PER_CU 8
+#endif
 
 struct WalkArgs {
     int64_t ngroups;
@@ -43,23 +69,23 @@ struct WalkArgs {
     const double4 *g_centre;
     const float4 *g_half;
     const double4 *p4;        // sources and targets: x, y, z, mass (sorted order)
-    const double4 *c_com;     // centre of mass, mass
-    const float4 *c_q0;       // 3Sxx, 3Syy, 3Szz, 3Sxy
-    const float4 *c_q1;       // 3Sxz, 3Syz, tr(S)/2, 3 tr(S)/2
-    const uint4 *c_walk;      // first child or particle, nchild or count|leaf bit, rcrit2 bits
+    const WalkCell *rec;      // per-cell walk records
     float4 *acc4;             // out: ax, ay, az, pot (sorted order)
     uint32_t *g_npp;
     uint32_t *g_npc;
+    uint32_t *spill;          // kSpillPerWave entries per wavefront of the grid
     DevMisc *misc;
     float eps2;
 };
 
 struct WaveLds {
-    uint32_t stack[kStackCap];
+    uint32_t stack[kLdsStack];
     uint32_t pc[kPcCap];
     uint2 pp[kPpCap];
     int mark[kWave];
-    float4 tile[3 * kWave];
+    float4 ta[kTileCap];      // offset x, y, z; mass
+    float4 tb[kTileCap];      // 3Sxx, 3Syy, 3Szz, 3Sxy
+    float4 tc[kTileCap];      // 3Sxz, 3Syz, tr(S)/2, 3 tr(S)/2
 };
 
 struct Acc {
@@ -77,8 +103,10 @@ __device__ __forceinline__ void comp_add(float &s, float &c, float t)
     c = c + err;
 }
 
-// Pop up to 64 elements from a list of ranges kept as a stack in LDS.  Lane j
-// receives element j of the popped run in *elem; returns how many were popped.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Pop up to 64 elements from a list of ranges kept as a stack.  Lane j receives
+// element j of the popped run in *elem; returns how many were popped.
 template <class List>
 __device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &elem)
 {
@@ -95,8 +123,8 @@ __device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &e
     }
     const bool full = lane < m && take == cnt;
     const int nfull = __popcll(ballot(full));
-    const uint32_t total = __shfl(incl, m - 1, kWave);
-    const int got = total < (uint32_t)kWave ? (int)total : kWave;
+    const uint32_t total = lane_value(incl, m - 1);
+    const int got = uniform(total < (uint32_t)kWave ? (int)total : kWave);
     mark[lane] = -1;
     wave_sync();
     if (take > 0) mark[excl] = lane;
@@ -108,19 +136,32 @@ __device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &e
     elem = fs + ((uint32_t)lane - es);
     if (lane == nfull && lane < m && take > 0 && take < cnt) list.set(top - 1 - lane, f + take, cnt - take);
     top -= nfull;
-    wave_sync();
+    list.sync();
     return got;
 }
 
+// Cell ranges packed as first << 3 | (count - 1); LDS first, then device memory.
 struct CellStack {
     uint32_t *s;
+    volatile uint32_t *spill;
     __device__ void get(int i, uint32_t &f, uint32_t &c) const
     {
-        const uint32_t v = s[i];
+        const uint32_t v = i < kLdsStack ? s[i] : spill[i - kLdsStack];
         f = v >> 3;
         c = (v & 7u) + 1u;
     }
-    __device__ void set(int i, uint32_t f, uint32_t c) const { s[i] = (f << 3) | (c - 1u); }
+    __device__ void set(int i, uint32_t f, uint32_t c) const
+    {
+        const uint32_t v = (f << 3) | (c - 1u);
+        if (i < kLdsStack) s[i] = v;
+        else spill[i - kLdsStack] = v;
+    }
+    // stores to device memory must have landed before another lane reads them
+    __device__ void sync() const
+    {
+        __builtin_amdgcn_s_waitcnt(0);
+        wave_sync();
+    }
 };
 
 struct LeafList {
@@ -132,6 +173,7 @@ struct LeafList {
         c = v.y;
     }
     __device__ void set(int i, uint32_t f, uint32_t c) const { s[i] = make_uint2(f, c); }
+    __device__ void sync() const { wave_sync(); }
 };
 
 // particle j on the lane's target (offsets o from the group centre)
@@ -167,7 +209,6 @@ __device__ __forceinline__ void pc_term(const float4 A, const float4 B, const fl
     const float rho2 = rho * rho;
     const float rho3 = rho2 * rho;
     const float rho5 = rho3 * rho2;
-    // 3 S r with B = (3Sxx, 3Syy, 3Szz, 3Sxy), C = (3Sxz, 3Syz, trS/2, 3trS/2)
     const float sx = __builtin_fmaf(B.x, rx, __builtin_fmaf(B.w, ry, C.x * rz));
     const float sy = __builtin_fmaf(B.w, rx, __builtin_fmaf(B.y, ry, C.y * rz));
     const float sz = __builtin_fmaf(C.x, rx, __builtin_fmaf(C.y, ry, B.z * rz));
@@ -187,101 +228,173 @@ __device__ __forceinline__ void pc_term(const float4 A, const float4 B, const fl
     az = __builtin_fmaf(rho5, sz, az);
 }
 
+struct Target {
+    float ox, oy, oz;
+    int sub, k;
+};
+
 template <bool kEps0>
-__device__ __forceinline__ void eval_pc(const WalkArgs &a, WaveLds &L, const uint32_t *list, int cnt,
-                                        const double4 gc, bool tact, int sub, int k, float ox,
-                                        float oy, float oz, Acc &acc)
+__device__ __forceinline__ void run_pc(const WaveLds &L, int cnt, const Target &t, float eps2,
+                                       Acc &acc)
 {
-    const int lane = lane_id();
-    if (lane < cnt) {
-        const uint32_t c = list[lane];
-        const double4 cm = a.c_com[c];
-        L.tile[lane] = make_float4((float)(cm.x - gc.x), (float)(cm.y - gc.y), (float)(cm.z - gc.z),
-                                   (float)cm.w);
-        L.tile[kWave + lane] = a.c_q0[c];
-        L.tile[2 * kWave + lane] = a.c_q1[c];
+    float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+    const int k = t.k;
+    const int T = uniform((cnt + k - 1) / k);
+    int j = t.sub;
+    int it = 0;
+    for (; it + kUnroll <= T; it += kUnroll) {
+        float4 A[kUnroll], B[kUnroll], C[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            A[u] = L.ta[j + u * k];
+            B[u] = L.tb[j + u * k];
+            C[u] = L.tc[j + u * k];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            pc_term<kEps0>(A[u], B[u], C[u], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
+        j += kUnroll * k;
     }
-    wave_sync();
-    if (tact) {
-        float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-        for (int j = sub; j < cnt; j += k)
-            pc_term<kEps0>(L.tile[j], L.tile[kWave + j], L.tile[2 * kWave + j], ox, oy, oz, a.eps2,
-                           ax, ay, az, ph);
-        comp_add(acc.ax, acc.cx, ax);
-        comp_add(acc.ay, acc.cy, ay);
-        comp_add(acc.az, acc.cz, az);
-        comp_add(acc.ph, acc.cp, ph);
+    for (; it < T; ++it) {
+        pc_term<kEps0>(L.ta[j], L.tb[j], L.tc[j], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
+        j += k;
     }
-    wave_sync();
+    comp_add(acc.ax, acc.cx, ax);
+    comp_add(acc.ay, acc.cy, ay);
+    comp_add(acc.az, acc.cz, az);
+    comp_add(acc.ph, acc.cp, ph);
 }
 
 template <bool kEps0>
+__device__ __forceinline__ void run_pp(const WaveLds &L, int cnt, const Target &t, float eps2,
+                                       Acc &acc)
+{
+    float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+    const int k = t.k;
+    const int T = uniform((cnt + k - 1) / k);
+    int j = t.sub;
+    int it = 0;
+    for (; it + kUnroll <= T; it += kUnroll) {
+        float4 S[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) S[u] = L.ta[j + u * k];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) pp_term<kEps0>(S[u], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
+        j += kUnroll * k;
+    }
+    for (; it < T; ++it) {
+        pp_term<kEps0>(L.ta[j], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
+        j += k;
+    }
+    comp_add(acc.ax, acc.cx, ax);
+    comp_add(acc.ay, acc.cy, ay);
+    comp_add(acc.az, acc.cz, az);
+    comp_add(acc.ph, acc.cp, ph);
+}
+
+// stage up to 64 cells of the cell list and evaluate them
+template <bool kEps0>
+__device__ __forceinline__ void eval_pc(const WalkArgs &a, WaveLds &L, const uint32_t *list, int cnt,
+                                        const double4 gc, const Target &t, Acc &acc)
+{
+    const int lane = lane_id();
+    if (lane < cnt) {
+        const WalkCell *r = a.rec + list[lane];
+        const double4 c0 = *reinterpret_cast<const double4 *>(r);       // cx, cy, cz, (mass, rcrit2)
+        const float2 sa = *reinterpret_cast<const float2 *>(&r->s3[0]);
+        const float4 sb = *reinterpret_cast<const float4 *>(&r->s3[2]);
+        const float mass = r->mass;
+        const float tr3 = (sa.x + sa.y) + sb.x;      // 3 tr(S)
+        L.ta[lane] = make_float4((float)(c0.x - gc.x), (float)(c0.y - gc.y), (float)(c0.z - gc.z), mass);
+        L.tb[lane] = make_float4(sa.x, sa.y, sb.x, sb.y);
+        L.tc[lane] = make_float4(sb.z, sb.w, tr3 * (1.0f / 6.0f), tr3 * 0.5f);
+    } else {
+        L.ta[lane] = make_float4(kFar, kFar, kFar, 0.0f);
+        L.tb[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+        L.tc[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    wave_sync();
+    if (t.sub < t.k) run_pc<kEps0>(L, cnt, t, a.eps2, acc);
+    wave_sync();
+}
+
+// stage up to 64 particles (lane j holds particle index idx) and evaluate them
+template <bool kEps0>
 __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t idx, int cnt,
-                                        const double4 gc, bool tact, int sub, int k, float ox,
-                                        float oy, float oz, Acc &acc)
+                                        const double4 gc, const Target &t, Acc &acc)
 {
     const int lane = lane_id();
     if (lane < cnt) {
         const double4 p = a.p4[idx];
-        L.tile[lane] = make_float4((float)(p.x - gc.x), (float)(p.y - gc.y), (float)(p.z - gc.z),
-                                   (float)p.w);
+        L.ta[lane] = make_float4((float)(p.x - gc.x), (float)(p.y - gc.y), (float)(p.z - gc.z), (float)p.w);
+    } else {
+        L.ta[lane] = make_float4(kFar, kFar, kFar, 0.0f);
     }
     wave_sync();
-    if (tact) {
-        float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-        for (int j = sub; j < cnt; j += k) pp_term<kEps0>(L.tile[j], ox, oy, oz, a.eps2, ax, ay, az, ph);
-        comp_add(acc.ax, acc.cx, ax);
-        comp_add(acc.ay, acc.cy, ay);
-        comp_add(acc.az, acc.cz, az);
-        comp_add(acc.ph, acc.cp, ph);
-    }
+    if (t.sub < t.k) run_pp<kEps0>(L, cnt, t, a.eps2, acc);
     wave_sync();
 }
 
+// next group from the device-wide counter (false when all are taken)
+__device__ __forceinline__ bool next_group(const WalkArgs &a, uint32_t &g)
+{
+    uint32_t v = 0;
+    if (lane_id() == 0) v = atomicAdd(&a.misc->walk_next, 1u);
+    g = readfirst(v);
+    return (int64_t)g < a.ngroups;
+}
+
 template <bool kEps0>
-__global__ void __launch_bounds__(kWalkBlock) walk_kernel(WalkArgs a)
+__global__ void __launch_bounds__(kWalkBlock)
+__attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs a)
 {
     __shared__ WaveLds s_lds[kWalkWaves];
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
     WaveLds &L = s_lds[w];
-    CellStack stack{L.stack};
+    const int64_t wave_global = (int64_t)blockIdx.x * kWalkWaves + w;
+    CellStack stack{L.stack, a.spill + wave_global * kSpillPerWave};
     LeafList leaves{L.pp};
 
-    for (;;) {
-        uint32_t gnext = 0;
-        if (lane == 0) gnext = atomicAdd(&a.misc->walk_next, 1u);
-        const uint32_t g = readfirst(gnext);
-        if ((int64_t)g >= a.ngroups) break;
+    // tile padding beyond the 64 staged entries: far away, zero mass
+    for (int i = kWave + lane; i < kTileCap; i += kWave) {
+        L.ta[i] = make_float4(kFar, kFar, kFar, 0.0f);
+        L.tb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        L.tc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    wave_sync();
 
+    unsigned long long wave_pp = 0, wave_pc = 0;   // interaction totals of this wavefront
+    bool wave_overflow = false;
+    uint32_t g;
+    while (next_group(a, g)) {
         const uint32_t gs = a.g_first[g];
-        const int gn = (int)a.g_count[g];
+        const int gn = uniform((int)a.g_count[g]);
         const double4 gc = a.g_centre[g];
         const float4 gh = a.g_half[g];
-        int k = kWave / gn;
-        k = k > 4 ? 4 : k;
+        Target t;
+        t.k = uniform(kWave / gn);
         const int p = lane % gn;
-        const int sub = lane / gn;
-        const bool tact = sub < k;
-        float ox = 0.f, oy = 0.f, oz = 0.f, mi = 0.f;
-        if (tact) {
+        t.sub = lane / gn;
+        float mi = 0.f;
+        t.ox = t.oy = t.oz = 0.f;
+        if (t.sub < t.k) {
             const double4 q = a.p4[gs + p];
-            ox = (float)(q.x - gc.x);
-            oy = (float)(q.y - gc.y);
-            oz = (float)(q.z - gc.z);
+            t.ox = (float)(q.x - gc.x);
+            t.oy = (float)(q.y - gc.y);
+            t.oz = (float)(q.z - gc.z);
             mi = (float)q.w;
         }
         Acc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
-        int top = 0;
+        int top = 1;
         if (lane == 0) stack.set(0, 0u, 1u);   // the root
-        top = 1;
+        wave_sync();
         int pc_n = 0, pp_n = 0;
         uint32_t pend = 0, npp = 0, npc = 0;
         bool overflow = false;
-        wave_sync();
-
         uint32_t iters = 0;
+
         while (top > 0) {
             // a correct tree visits each cell at most once per group
             if (++iters > a.ncells + 1u) {
@@ -292,10 +405,14 @@ __global__ void __launch_bounds__(kWalkBlock) walk_kernel(WalkArgs a)
             const int got = pop64(stack, top, L.mark, cell);
             const bool has = lane < got && cell < a.ncells;
             bool acc_cell = false, leaf = false;
-            uint4 wk = make_uint4(0, 0, 0, 0);
+            uint32_t link = 0, info = 0;
             if (has) {
-                const double4 cm = a.c_com[cell];
-                wk = a.c_walk[cell];
+                const WalkCell *r = a.rec + cell;
+                const double4 cm = *reinterpret_cast<const double4 *>(r);
+                const uint2 li = *reinterpret_cast<const uint2 *>(&r->link);
+                const float rc2 = r->rcrit2;
+                link = li.x;
+                info = li.y;
                 const float dx = fabsf((float)(cm.x - gc.x)) - gh.x;
                 const float dy = fabsf((float)(cm.y - gc.y)) - gh.y;
                 const float dz = fabsf((float)(cm.z - gc.z)) - gh.z;
@@ -303,8 +420,8 @@ __global__ void __launch_bounds__(kWalkBlock) walk_kernel(WalkArgs a)
                 const float uy = dy > 0.0f ? dy : 0.0f;
                 const float uz = dz > 0.0f ? dz : 0.0f;
                 const float d2 = (ux * ux + uy * uy) + uz * uz;
-                acc_cell = d2 > __uint_as_float(wk.z);
-                leaf = (wk.y >> 31) != 0u;
+                acc_cell = d2 > rc2;
+                leaf = (info >> 31) != 0u;
             }
             // accepted cells -> cell list
             const unsigned long long bpc = ballot(has && acc_cell);
@@ -314,10 +431,10 @@ __global__ void __launch_bounds__(kWalkBlock) walk_kernel(WalkArgs a)
             // opened leaves -> particle list
             const bool isl = has && !acc_cell && leaf;
             const unsigned long long bpp = ballot(isl);
-            const uint32_t lc = isl ? (wk.y & 0x7fffffffu) : 0u;
-            if (isl) L.pp[pp_n + mask_rank(bpp)] = make_uint2(wk.x, lc);
+            const uint32_t lc = isl ? (info & 0x7fffffffu) : 0u;
+            if (isl) L.pp[pp_n + mask_rank(bpp)] = make_uint2(link, lc);
             pp_n += __popcll(bpp);
-            const uint32_t lsum = wave_sum(lc);
+            const uint32_t lsum = wave_sum_u32(lc);
             pend += lsum;
             npp += lsum;
             // opened nodes -> children onto the stack
@@ -327,12 +444,12 @@ __global__ void __launch_bounds__(kWalkBlock) walk_kernel(WalkArgs a)
             if (top + nn > kStackCap) {
                 overflow = true;
             } else {
-                if (isn) stack.set(top + mask_rank(bn), wk.x, wk.y);
+                if (isn) stack.set(top + mask_rank(bn), link, info);
                 top += nn;
             }
-            wave_sync();
+            stack.sync();
             while (pc_n >= kWave) {
-                eval_pc<kEps0>(a, L, L.pc + (pc_n - kWave), kWave, gc, tact, sub, k, ox, oy, oz, acc);
+                eval_pc<kEps0>(a, L, L.pc + (pc_n - kWave), kWave, gc, t, acc);
                 pc_n -= kWave;
             }
             while (pend >= (uint32_t)kWave) {
@@ -343,12 +460,12 @@ __global__ void __launch_bounds__(kWalkBlock) walk_kernel(WalkArgs a)
                     pend = 0;
                     break;
                 }
-                eval_pp<kEps0>(a, L, idx, n, gc, tact, sub, k, ox, oy, oz, acc);
+                eval_pp<kEps0>(a, L, idx, n, gc, t, acc);
                 pend -= (uint32_t)n;
             }
             if (overflow) break;
         }
-        if (pc_n > 0) eval_pc<kEps0>(a, L, L.pc, pc_n, gc, tact, sub, k, ox, oy, oz, acc);
+        if (pc_n > 0) eval_pc<kEps0>(a, L, L.pc, pc_n, gc, t, acc);
         while (pend > 0) {
             uint32_t idx;
             const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx) : 0;
@@ -356,26 +473,30 @@ __global__ void __launch_bounds__(kWalkBlock) walk_kernel(WalkArgs a)
                 overflow = true;
                 break;
             }
-            eval_pp<kEps0>(a, L, idx, n, gc, tact, sub, k, ox, oy, oz, acc);
+            eval_pp<kEps0>(a, L, idx, n, gc, t, acc);
             pend -= (uint32_t)n < pend ? (uint32_t)n : pend;
         }
 
-        // combine the k lanes of each particle
+        // add the k partial sums of each particle: halving steps over the
+        // sub-lane index, in a fixed order
         float ax = acc.ax + acc.cx, ay = acc.ay + acc.cy, az = acc.az + acc.cz, ph = acc.ph + acc.cp;
-        for (int s = 1; s < k; ++s) {
-            const int srcl = lane + s * gn;
-            const float bx = __shfl(ax, srcl < kWave ? srcl : lane, kWave);
-            const float by = __shfl(ay, srcl < kWave ? srcl : lane, kWave);
-            const float bz = __shfl(az, srcl < kWave ? srcl : lane, kWave);
-            const float bp = __shfl(ph, srcl < kWave ? srcl : lane, kWave);
-            if (sub == 0) {
+        for (int kk = t.k; kk > 1;) {
+            const int h = (kk + 1) >> 1;
+            const int src = lane + h * gn;
+            const int srcl = src < kWave ? src : lane;
+            const float bx = __shfl(ax, srcl, kWave);
+            const float by = __shfl(ay, srcl, kWave);
+            const float bz = __shfl(az, srcl, kWave);
+            const float bp = __shfl(ph, srcl, kWave);
+            if (t.sub + h < kk) {
                 ax += bx;
                 ay += by;
                 az += bz;
                 ph += bp;
             }
+            kk = h;
         }
-        if (sub == 0 && lane < gn) {
+        if (t.sub == 0 && lane < gn) {
             // the particle met itself once in the particle list: with eps > 0 that
             // term added -m/eps to the potential and nothing to the acceleration
             if (!kEps0) ph = ph + mi * __builtin_amdgcn_rsqf(a.eps2);
@@ -384,11 +505,18 @@ __global__ void __launch_bounds__(kWalkBlock) walk_kernel(WalkArgs a)
         if (lane == 0) {
             a.g_npp[g] = npp;
             a.g_npc[g] = npc;
-            atomicAdd(&a.misc->sum_npp, (unsigned long long)npp * (unsigned long long)gn);
-            atomicAdd(&a.misc->sum_npc, (unsigned long long)npc * (unsigned long long)gn);
-            if (overflow) atomicOr(&a.misc->walk_overflow, 1u);
         }
+        wave_pp += (unsigned long long)npp * (unsigned long long)gn;
+        wave_pc += (unsigned long long)npc * (unsigned long long)gn;
+        wave_overflow |= overflow;
         wave_sync();
+    }
+    if (lane == 0) {
+        atomicAdd(&a.misc->sum_npp, wave_pp);
+        atomicAdd(&a.misc->sum_npc, wave_pc);
+        atomicAdd(&a.misc->tot_npp, wave_pp);
+        atomicAdd(&a.misc->tot_npc, wave_pc);
+        if (wave_overflow) atomicOr(&a.misc->walk_overflow, 1u);
     }
 }
 
@@ -400,22 +528,6 @@ __global__ void walk_reset_kernel(DevMisc *m)
         m->sum_npp = 0;
         m->sum_npc = 0;
     }
-}
-
-// per-cell walk record: (first child, nchild) for nodes, (first particle, count |
-// leaf bit) for leaves, and the float32 opening radius squared
-__global__ void __launch_bounds__(256)
-pack_walk_kernel(int64_t ncells, const uint8_t *__restrict__ c_leaf,
-                 const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
-                 const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
-                 const float *__restrict__ rcrit2, uint4 *__restrict__ c_walk)
-{
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= ncells) return;
-    const bool leaf = c_leaf[c] != 0;
-    const uint32_t x = leaf ? c_first[c] : c_child[c];
-    const uint32_t y = leaf ? (c_count[c] | 0x80000000u) : c_nchild[c];
-    c_walk[c] = make_uint4(x, y, __float_as_uint(rcrit2[c]), 0u);
 }
 
 __global__ void __launch_bounds__(256)
@@ -436,17 +548,66 @@ scatter_kernel(int64_t n, const float4 *__restrict__ acc4, const uint32_t *__res
 
 }  // namespace
 
+// Harvest finished walk timings; with block == true wait for all of them.
+void walk_timer_harvest(bh_ctx *c, bool block)
+{
+    while (c->wring_count > 0) {
+        hipEvent_t *ev = &c->wev[2 * c->wring_head];
+        if (!block && hipEventQuery(ev[1]) != hipSuccess) break;
+        if (block) (void)hipEventSynchronize(ev[1]);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) {
+            c->walk_ms_total += ms;
+            c->walk_ms_last = ms;
+            c->walk_launches += 1;
+        }
+        c->wring_head = (c->wring_head + 1) % bh_ctx::kWalkRing;
+        c->wring_count -= 1;
+    }
+    (void)hipGetLastError();
+}
+
+// Next free pair of timing events (the oldest is harvested if the ring is full).
+hipEvent_t *walk_timer_slot(bh_ctx *c)
+{
+    if (!c->wev[0]) return nullptr;
+    walk_timer_harvest(c, false);
+    if (c->wring_count == bh_ctx::kWalkRing) {
+        hipEvent_t *old = &c->wev[2 * c->wring_head];
+        (void)hipEventSynchronize(old[1]);
+        walk_timer_harvest(c, false);
+    }
+    const int slot = (c->wring_head + c->wring_count) % bh_ctx::kWalkRing;
+    c->wring_count += 1;
+    return &c->wev[2 * slot];
+}
+
 hipError_t launch_walk(bh_ctx *c, float theta, float eps)
 {
     (void)theta;
-    const int64_t nc = c->ncells;
-    uint4 *cw = c->c_walk;
-    hipLaunchKernelGGL(pack_walk_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, c->stream,
-                       nc, c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild, c->c_rcrit2,
-                       cw);
-    BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(walk_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
     BH_LAUNCH_CHECK();
+    int dev_cus = 256;
+    if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+        hipSuccess)
+        dev_cus = 256;
+    int64_t blocks = (int64_t)dev_cus * BH_WALK_BLOCKS_PER_CU;
+    const int64_t need = (c->ngroups + kWalkWaves - 1) / kWalkWaves;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    const int64_t waves = blocks * kWalkWaves;
+    if (waves > c->walk_spill_waves) {
+        if (c->walk_spill) {
+            BH_HIP_TRY(hipStreamSynchronize(c->stream));
+            BH_HIP_TRY(hipFree(c->walk_spill));
+            c->bytes -= c->walk_spill_waves * kSpillPerWave * 4;
+            c->walk_spill = nullptr;
+            c->walk_spill_waves = 0;
+        }
+        BH_HIP_TRY(hipMalloc((void **)&c->walk_spill, (size_t)waves * kSpillPerWave * 4));
+        c->walk_spill_waves = waves;
+        c->bytes += waves * kSpillPerWave * 4;
+    }
     WalkArgs a;
     a.ngroups = c->ngroups;
     a.ncells = (uint32_t)c->ncells;
@@ -455,28 +616,21 @@ hipError_t launch_walk(bh_ctx *c, float theta, float eps)
     a.g_centre = c->g_centre;
     a.g_half = c->g_half;
     a.p4 = c->p4[c->cur];
-    a.c_com = c->c_com;
-    a.c_q0 = c->c_q0;
-    a.c_q1 = c->c_q1;
-    a.c_walk = cw;
+    a.rec = c->c_rec;
     a.acc4 = c->acc4;
     a.g_npp = c->g_npp;
     a.g_npc = c->g_npc;
+    a.spill = c->walk_spill;
     a.misc = c->misc;
     a.eps2 = eps * eps;
-    int dev_cus = 256;
-    if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
-        hipSuccess)
-        dev_cus = 256;
-    int64_t blocks = (int64_t)dev_cus * 8;
-    const int64_t need = (c->ngroups + kWalkWaves - 1) / kWalkWaves;
-    if (blocks > need) blocks = need;
-    if (blocks < 1) blocks = 1;
+    hipEvent_t *ev = walk_timer_slot(c);
+    if (ev) BH_HIP_TRY(hipEventRecord(ev[0], c->stream));
     if (a.eps2 > 0.0f)
         hipLaunchKernelGGL(walk_kernel<false>, dim3((unsigned)blocks), dim3(kWalkBlock), 0, c->stream, a);
     else
         hipLaunchKernelGGL(walk_kernel<true>, dim3((unsigned)blocks), dim3(kWalkBlock), 0, c->stream, a);
     BH_LAUNCH_CHECK();
+    if (ev) BH_HIP_TRY(hipEventRecord(ev[1], c->stream));
     return hipSuccess;
 }
 

@@ -131,3 +131,10 @@ def test_plummer_1m_full_size():
     rng = np.random.default_rng(7)
     groups = np.sort(rng.choice(t.ngroups, 300, replace=False))
     compare_forces(acc.cpu().numpy(), pot.cpu().numpy(), t, 0.75, 1 / 64, groups)
+
+
+def test_small_opening_angle_deep_stack():
+    # theta = 0.15 opens many nodes per level: long interaction lists and a deep
+    # walk stack
+    pos, _, m = workloads.plummer(60_000, 41)
+    _full_check(pos, m, 0.15, 0.01, label="theta-0.15")

@@ -138,3 +138,29 @@ def test_small_opening_angle_deep_stack():
     # walk stack
     pos, _, m = workloads.plummer(60_000, 41)
     _full_check(pos, m, 0.15, 0.01, label="theta-0.15")
+
+
+def test_galaxy_4m_full_size():
+    # three-component galaxy, N = 4,194,304, theta 0.4, eps 0.02: tree and all
+    # counts bit-exact, forces on sampled groups against the oracle, and the error
+    # against float64 direct summation on seeded targets
+    import torch
+    pos, _, m = workloads.galaxy(seed=3)
+    say("case galaxy-4M")
+    ctx = gpu_build(pos, m)
+    acc, pot = ctx.compute_forces(0.4, 0.02)
+    torch.cuda.synchronize()
+    ex = ctx.export_tree()
+    t = oracle.Tree(pos, m)
+    compare_tree(ex, t)
+    compare_walk(ex, t, 0.4)
+    rng = np.random.default_rng(13)
+    groups = np.sort(rng.choice(t.ngroups, 200, replace=False))
+    a = acc.cpu().numpy()
+    compare_forces(a, pot.cpu().numpy(), t, 0.4, 0.02, groups)
+    tgt = np.sort(rng.choice(pos.shape[0], 128, replace=False))
+    ad, _ = oracle.direct(pos, m, 0.02, tgt)
+    err = np.linalg.norm(a[tgt].astype(np.float64) - ad, axis=1) / np.linalg.norm(ad, axis=1)
+    say("galaxy-4M vs direct: median", np.median(err), "p99", np.percentile(err, 99))
+    assert np.median(err) <= 1e-3 and np.percentile(err, 99) <= 1e-2
+    ctx.close()

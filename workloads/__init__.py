@@ -8,6 +8,7 @@ All arrays are float64 NumPy arrays: positions and velocities of shape (n, 3), m
 of shape (n,).
 """
 
+from .galaxy import galaxy
 from .plummer import plummer, plummer_radii
 from .shapes import (
     two_body,
@@ -19,6 +20,7 @@ from .shapes import (
 )
 
 __all__ = [
+    "galaxy",
     "plummer",
     "plummer_radii",
     "two_body",

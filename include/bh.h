@@ -43,12 +43,14 @@ typedef struct bh_ctx bh_ctx;
  * ncrit: most particles in a walk group (Sect. 2.2, 64 in the paper; at most 64
  * here, one wavefront per group); max_n: particles to reserve room for up front
  * (0: grow on demand); hbm_budget_bytes: cap on the device memory the context
- * may hold (0: no cap). */
+ * may hold (0: no cap); max_clusters: clusters of a batch to reserve room for
+ * (0: grow on demand). */
 typedef struct {
     int32_t nleaf;
     int32_t ncrit;
     int64_t max_n;
     int64_t hbm_budget_bytes;
+    int64_t max_clusters;
 } bh_params;
 
 /* Per-build and per-walk figures.  Times are device time between events on the
@@ -76,6 +78,8 @@ typedef struct {
     int64_t walk_kernel_launches;
     int64_t total_npp;      /* sum_npp accumulated over all walks */
     int64_t total_npc;      /* sum_npc accumulated over all walks */
+    int64_t nclusters;      /* clusters loaded (1 after bh_build_tree) */
+    int64_t graph_launches; /* captured steps replayed by bh_batch_run */
 } bh_stats;
 
 /* Host copies of the tree for checking it element by element.  Every pointer is
@@ -106,7 +110,8 @@ typedef struct {
     int64_t *npc;       /* [ngroups] accepted cells, last force call */
 } bh_tree_host;
 
-/* Fill *p with the defaults: nleaf 16, ncrit 64, max_n 0, budget 0. */
+/* Fill *p with the defaults: nleaf 16, ncrit 64, max_n 0, budget 0,
+ * max_clusters 0. */
 int bh_default_params(bh_params *p);
 
 /* Create a context.  p may be NULL (defaults).  hip_stream is a hipStream_t the
@@ -139,7 +144,9 @@ int bh_compute_forces(bh_ctx *ctx, float theta, float eps, float *acc, float *po
 
 /* One leapfrog step (Sect. 3.1) as kick-drift-kick: v += a dt/2; x += v dt
  * (float64); rebuild the tree; forces with the last theta and eps; v += a dt/2.
- * Needs a prior bh_compute_forces.  Synchronous like bh_build_tree. */
+ * Needs a prior bh_compute_forces.  Enqueued without waiting for the device;
+ * device-side errors are reported by the next synchronous call (see
+ * bh_batch_run). */
 int bh_leapfrog_step(bh_ctx *ctx, double dt);
 
 /* Copy the state out in caller order; any pointer may be NULL.  pos, vel:
@@ -154,7 +161,8 @@ int bh_set_state(bh_ctx *ctx, const double *pos, const double *vel);
 /* Energy and momentum in float64 from the current velocities and the last
  * potentials (Eq. (3) ingredients): out[0..6] = T, W, E = T + W, Px, Py, Pz,
  * and (E0 - E) / E0 with E0 the energy at the first bh_energy call after a
- * build or set_state (host array).  Synchronous. */
+ * build or set_state (host array).  On a batch: sums over all clusters.
+ * Synchronous. */
 int bh_energy(bh_ctx *ctx, double out[7]);
 
 /* Host copy of the latest figures.  Synchronous. */
@@ -162,6 +170,60 @@ int bh_stats_get(bh_ctx *ctx, bh_stats *out);
 
 /* Host copies of the tree (see bh_tree_host).  Synchronous. */
 int bh_export_tree(bh_ctx *ctx, const bh_tree_host *out);
+
+/* ---------------------------------------------------------------------------
+ * Batches: K independent particle systems ("clusters") in one context.  Each
+ * cluster gets its own domain and tree (the trees of the batch form one forest:
+ * cluster k's root is cell k), its own opening angle, softening, leaf and group
+ * sizes and time step, while every phase runs as one launch over the whole batch
+ * and the walk takes its groups from one queue.  The single-system calls above
+ * are the K = 1 case; on a batch, bh_compute_forces and bh_leapfrog_step set theta,
+ * eps and dt of every cluster, and bh_get_state / bh_set_state / bh_set_velocities
+ * use the concatenated caller order (cluster 0's particles, then cluster 1's, ...).
+ */
+
+/* One cluster of a batch. */
+typedef struct {
+    int64_t n;          /* particles, >= 1 */
+    float theta;        /* opening angle of Eq. (1), in (0, 1] */
+    float eps;          /* Plummer softening, >= 0 */
+    double dt;          /* leapfrog step used by bh_batch_run (finite; 0 leaves the
+                           cluster's positions and velocities as they are while its
+                           forces are evaluated) */
+    int32_t nleaf;      /* 1..64; 0: the context's nleaf */
+    int32_t ncrit;      /* 1..64; 0: the context's ncrit */
+} bh_cluster;
+
+/* Load k clusters and build their forest.  clusters: host [k].  pos: device
+ * [sum n][3] float64, mass: device [sum n] float64 (> 0), vel: device [sum n][3]
+ * float64 or NULL (zero), all in concatenated order.  Copied in.  Synchronous
+ * (validates the inputs).  BH_EINVAL for k < 1, a bad cluster entry, a total of
+ * 2^31 particles or more, or non-finite data. */
+int bh_batch_build(bh_ctx *ctx, const bh_cluster *clusters, int64_t k, const double *pos,
+                   const double *mass, const double *vel);
+
+/* Change theta, eps and dt of the loaded clusters (host [k], k and each n, nleaf
+ * and ncrit as loaded; nleaf / ncrit 0 match the context's values).  Takes effect
+ * for work enqueued afterwards. */
+int bh_batch_set_params(bh_ctx *ctx, const bh_cluster *clusters, int64_t k);
+
+/* Forces of every cluster with its own theta and eps, from its current tree
+ * (see bh_compute_forces for acc and pot; concatenated caller order). */
+int bh_batch_forces(bh_ctx *ctx, float *acc, float *pot);
+
+/* nsteps kick-drift-kick steps of every cluster with its own dt (Sect. 3.1):
+ * each step rebuilds every tree and recomputes every force.  The step is
+ * captured once into a HIP graph per buffer layout and replayed, so it costs
+ * one graph launch on the context stream; nothing is read back and the call
+ * does not wait for the device.  Needs a prior force evaluation.  Errors found
+ * on the device (non-finite coordinates after a step) are reported by the next
+ * synchronous call (bh_energy, bh_batch_energy, bh_stats_get, bh_export_tree). */
+int bh_batch_run(bh_ctx *ctx, int32_t nsteps);
+
+/* Per-cluster energy and momentum: out host [k][7] as in bh_energy, each
+ * cluster's E0 taken at its first call after a build or state change.
+ * Synchronous. */
+int bh_batch_energy(bh_ctx *ctx, double *out);
 
 /* Message for the last non-zero status of this context (never NULL). */
 const char *bh_last_error(bh_ctx *ctx);

@@ -9,6 +9,7 @@ import of ``Context`` fails.
 
 from .binding import (  # noqa: F401
     BHError,
+    Cluster,
     Context,
     Stats,
     library_path,
@@ -16,4 +17,4 @@ from .binding import (  # noqa: F401
     declared_functions,
 )
 
-__all__ = ["BHError", "Context", "Stats", "library_path", "load_library", "declared_functions"]
+__all__ = ["BHError", "Cluster", "Context", "Stats", "library_path", "load_library", "declared_functions"]

@@ -26,7 +26,14 @@ class BHError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
-                ("max_n", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_int64)]
+                ("max_n", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_int64),
+                ("max_clusters", ctypes.c_int64)]
+
+
+class Cluster(ctypes.Structure):
+    """One cluster of a batch (bh_cluster)."""
+    _fields_ = [("n", ctypes.c_int64), ("theta", ctypes.c_float), ("eps", ctypes.c_float),
+                ("dt", ctypes.c_double), ("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -39,7 +46,8 @@ class Stats(ctypes.Structure):
                 ("ms_walk", ctypes.c_double), ("device_bytes", ctypes.c_int64),
                 ("ms_walk_kernel", ctypes.c_double), ("walk_kernel_ms_total", ctypes.c_double),
                 ("walk_kernel_launches", ctypes.c_int64), ("total_npp", ctypes.c_int64),
-                ("total_npc", ctypes.c_int64)]
+                ("total_npc", ctypes.c_int64), ("nclusters", ctypes.c_int64),
+                ("graph_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +99,11 @@ def load_library():
         "bh_energy": (i32, [_vp, _vp]),
         "bh_stats_get": (i32, [_vp, ctypes.POINTER(Stats)]),
         "bh_export_tree": (i32, [_vp, ctypes.POINTER(TreeHost)]),
+        "bh_batch_build": (i32, [_vp, ctypes.POINTER(Cluster), i64, _vp, _vp, _vp]),
+        "bh_batch_set_params": (i32, [_vp, ctypes.POINTER(Cluster), i64]),
+        "bh_batch_forces": (i32, [_vp, _vp, _vp]),
+        "bh_batch_run": (i32, [_vp, ctypes.c_int32]),
+        "bh_batch_energy": (i32, [_vp, _vp]),
         "bh_last_error": (ctypes.c_char_p, [_vp]),
     }
     for name, (res, args) in sig.items():
@@ -119,10 +132,11 @@ def _dev_ptr(t, dtype, shape=None, name="tensor"):
 class Context:
     """One particle system on the device (bh_ctx)."""
 
-    def __init__(self, nleaf=16, ncrit=64, max_n=0, hbm_budget_bytes=0, stream=None):
+    def __init__(self, nleaf=16, ncrit=64, max_n=0, hbm_budget_bytes=0, stream=None,
+                 max_clusters=0):
         import torch
         self._L = load_library()
-        p = Params(nleaf, ncrit, max_n, hbm_budget_bytes)
+        p = Params(nleaf, ncrit, max_n, hbm_budget_bytes, max_clusters)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -166,6 +180,58 @@ class Context:
         self._check(self._L.bh_build_tree(self._h, pp, mp, n))
         self._keep = None
         self.n = n
+        self.k = 1
+
+    # --- batches ------------------------------------------------------------
+    @staticmethod
+    def _table(clusters):
+        """clusters: sequence of dicts with n, theta, eps and optional dt, nleaf,
+        ncrit (0: the context's)."""
+        arr = (Cluster * len(clusters))()
+        for a, q in zip(arr, clusters):
+            a.n = int(q["n"])
+            a.theta = float(q["theta"])
+            a.eps = float(q["eps"])
+            a.dt = float(q.get("dt", 0.0))
+            a.nleaf = int(q.get("nleaf", 0))
+            a.ncrit = int(q.get("ncrit", 0))
+        return arr
+
+    def batch_build(self, clusters, pos, mass, vel=None):
+        """Load clusters (concatenated pos [N,3], mass [N], vel [N,3] or None)."""
+        import torch
+        n = int(sum(int(q["n"]) for q in clusters))
+        tab = self._table(clusters)
+        pp = _dev_ptr(pos, torch.float64, (n, 3), "pos")
+        mp = _dev_ptr(mass, torch.float64, (n,), "mass")
+        vp = _dev_ptr(vel, torch.float64, (n, 3), "vel")
+        self._keep = (pos, mass, vel)
+        self._check(self._L.bh_batch_build(self._h, tab, len(clusters), pp, mp, vp))
+        self._keep = None
+        self.n = n
+        self.k = len(clusters)
+
+    def batch_set_params(self, clusters):
+        self._check(self._L.bh_batch_set_params(self._h, self._table(clusters), len(clusters)))
+
+    def batch_forces(self, acc=None, pot=None, want=True):
+        import torch
+        if want and acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float32, device=self._device())
+        if want and pot is None:
+            pot = torch.empty((self.n,), dtype=torch.float32, device=self._device())
+        ap = _dev_ptr(acc, torch.float32, (self.n, 3), "acc")
+        pp = _dev_ptr(pot, torch.float32, (self.n,), "pot")
+        self._check(self._L.bh_batch_forces(self._h, ap, pp))
+        return acc, pot
+
+    def batch_run(self, nsteps):
+        self._check(self._L.bh_batch_run(self._h, int(nsteps)))
+
+    def batch_energy(self):
+        out = np.zeros((self.k, 7))
+        self._check(self._L.bh_batch_energy(self._h, out.ctypes.data_as(_vp)))
+        return out
 
     def set_velocities(self, vel):
         import torch

@@ -1,18 +1,15 @@
 // api.hip - the C ABI declared in include/bh.h: context and device memory, the
-// build / force / leapfrog sequences, state copies, energy, statistics and the
-// host export used to check the tree element by element.
+// cluster table of a batch, the build / force / leapfrog sequences (eager, or
+// captured once into a HIP graph and replayed), state copies, energy,
+// statistics and the host export used to check the tree element by element.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
-#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
 
 #include "bh_internal.h"
-
-namespace bh {
-int64_t energy_words();
-}
 
 using namespace bh;
 
@@ -26,26 +23,25 @@ int fail(bh_ctx *c, int code, const char *msg)
 
 int hip_fail(bh_ctx *c, hipError_t e, const char *where)
 {
-    if (c) {
-        c->err = std::string(where) + ": " + hipGetErrorString(e);
-    }
+    (void)hipGetLastError();
+    if (c) c->err = std::string(where) + ": " + hipGetErrorString(e);
     return BH_EDEVICE;
 }
 
-#define TRY_HIP(c, expr)                                   \
-    do {                                                   \
-        hipError_t e__ = (expr);                           \
-        if (e__ != hipSuccess) return hip_fail((c), e__, #expr); \
+#define TRY_HIP(c, expr)                                             \
+    do {                                                             \
+        hipError_t e__ = (expr);                                     \
+        if (e__ != hipSuccess) return hip_fail((c), e__, #expr);     \
     } while (0)
 
-template <typename T>
-hipError_t dalloc(bh_ctx *c, T **p, int64_t count)
-{
-    const int64_t bytes = (int64_t)sizeof(T) * (count > 0 ? count : 1);
-    hipError_t e = hipMalloc((void **)p, (size_t)bytes);
-    if (e == hipSuccess) c->bytes += bytes;
-    return e;
-}
+#define TRY_ST(expr)              \
+    do {                          \
+        int st__ = (expr);        \
+        if (st__) return st__;    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory
 
 template <typename T>
 void dfree(T *&p)
@@ -54,8 +50,25 @@ void dfree(T *&p)
     p = nullptr;
 }
 
+template <typename T>
+void hfree(T *&p)
+{
+    if (p) (void)hipHostFree((void *)p);
+    p = nullptr;
+}
+
+void drop_graphs(bh_ctx *c)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
+        c->graph_exec[k] = nullptr;
+    }
+    c->graph_layout = -1;
+}
+
 void free_buffers(bh_ctx *c)
 {
+    drop_graphs(c);
     for (int i = 0; i < 2; ++i) {
         dfree(c->p4[i]);
         dfree(c->v4[i]);
@@ -64,6 +77,7 @@ void free_buffers(bh_ctx *c)
         dfree(c->val[i]);
     }
     dfree(c->acc4);
+    dfree(c->pcl);
     dfree(c->split);
     dfree(c->lam);
     dfree(c->gflag);
@@ -83,175 +97,476 @@ void free_buffers(bh_ctx *c)
     dfree(c->c_rcrit2);
     dfree(c->c_rec);
     dfree(c->walk_spill);
-    c->walk_spill_waves = 0;
     dfree(c->g_first);
     dfree(c->g_count);
     dfree(c->g_npp);
     dfree(c->g_npc);
     dfree(c->g_centre);
     dfree(c->g_half);
-    dfree(c->red);
+    dfree(c->clus);
+    dfree(c->dom);
+    dfree(c->chunks);
+    dfree(c->bb_part);
+    dfree(c->e_part);
+    dfree(c->e_out);
+    hfree(c->clus_h);
+    hfree(c->chunks_h);
+    hfree(c->e_out_h);
+    c->walk_spill_waves = 0;
     c->bytes = 0;
-    c->cap_n = 0;
-    c->cap_c = 0;
+    c->cap_n = c->cap_c = c->cap_k = c->cap_chunks = 0;
+    c->built = false;
+    c->have_forces = false;
+    c->layout += 1;
 }
 
-// Worst-case cell count: nodes hold more than nleaf particles and nodes of one
-// level are disjoint, so at most 20 n / (nleaf + 1) nodes; at most n leaves.
-int64_t cell_bound(int64_t n, int nleaf)
+// Worst-case cell count of a forest of K trees over n particles whose smallest
+// leaf size is nleaf: nodes hold more than nleaf particles and the nodes of one
+// level are disjoint, so at most 20 n / (nleaf + 1) nodes below the roots; at
+// most n leaves; K roots.
+int64_t cell_bound(int64_t n, int64_t K, int nleaf)
 {
-    return n + (20 * n) / (nleaf + 1) + 2;
+    return n + (20 * n) / (nleaf + 1) + 2 * K + 2;
 }
 
-int64_t bytes_for(int64_t n, int nleaf)
+struct Sizes {
+    int64_t n, K, chunks, cells, blk, scan, spill_waves;
+};
+
+Sizes sizes_for(bh_ctx *c, int64_t n, int64_t K, int nleaf_min)
 {
-    const int64_t nc = cell_bound(n, nleaf);
-    const int64_t per_p = 2 * 32 + 2 * 32 + 2 * 4 + 16 + 2 * 8 + 2 * 4 + 3 + 64;
-    const int64_t per_c = 5 * 4 + 2 + 32 + 48 + 32 + 4 + 64;
-    const int64_t blk_words = std::max(sort_blk_words(n), (int64_t)kLevels * ((n + kTreeTile - 1) / kTreeTile) + kLevels);
-    return n * per_p + nc * per_c + 4 * (blk_words + scan_tmp_words(n)) + 8 * energy_words();
+    Sizes z;
+    z.n = n;
+    z.K = K;
+    z.chunks = n / kChunk + K + 1;     // every layout with <= n particles, <= K clusters
+    z.cells = cell_bound(n, K, nleaf_min);
+    z.blk = std::max(sort_blk_words(n), (int64_t)kLevels * ((n + kTreeTile - 1) / kTreeTile) + kLevels);
+    z.scan = scan_tmp_words(n);
+    z.spill_waves = walk_grid_waves(c);
+    return z;
 }
 
-int ensure_capacity(bh_ctx *c, int64_t n)
+// Walks every device buffer of the context with its element size and count.
+template <typename F>
+hipError_t each_buffer(bh_ctx *c, const Sizes &z, F f)
 {
-    if (n <= c->cap_n) return BH_OK;
-    int64_t want = n;
-    if (c->p.max_n > want) want = c->p.max_n;
-    if (c->p.hbm_budget_bytes > 0 && bytes_for(want, c->p.nleaf) > c->p.hbm_budget_bytes) {
-        if (bytes_for(n, c->p.nleaf) > c->p.hbm_budget_bytes)
-            return fail(c, BH_ENOMEM, "particle count exceeds the context's memory budget");
-        want = n;
-    }
-    free_buffers(c);
-    const int64_t nc = cell_bound(want, c->p.nleaf);
-    c->blk_len = std::max(sort_blk_words(want),
-                          (int64_t)kLevels * ((want + kTreeTile - 1) / kTreeTile) + kLevels);
-    c->scan_len = scan_tmp_words(want);
-    c->red_len = energy_words();
     hipError_t e = hipSuccess;
-#define A(ptr, cnt) \
-    if (e == hipSuccess) e = dalloc(c, &(ptr), (cnt))
+#define B(ptr, cnt) \
+    if (e == hipSuccess) e = f(&(ptr), sizeof(*(ptr)), (cnt))
     for (int i = 0; i < 2; ++i) {
-        A(c->p4[i], want);
-        A(c->v4[i], want);
-        A(c->pid[i], want);
-        A(c->key[i], want);
-        A(c->val[i], want);
+        B(c->p4[i], z.n);
+        B(c->v4[i], z.n);
+        B(c->pid[i], z.n);
+        B(c->key[i], z.n);
+        B(c->val[i], z.n);
     }
-    A(c->acc4, want);
-    A(c->split, want);
-    A(c->lam, want);
-    A(c->gflag, want);
-    A(c->blk, c->blk_len);
-    A(c->scan_tmp, c->scan_len);
-    A(c->c_first, nc);
-    A(c->c_count, nc);
-    A(c->c_child, nc);
-    A(c->c_nchild, nc);
-    A(c->c_parent, nc);
-    A(c->c_level, nc);
-    A(c->c_leaf, nc);
-    A(c->c_com, nc);
-    A(c->c_S, 6 * nc);
-    A(c->c_q0, nc);
-    A(c->c_q1, nc);
-    A(c->c_rcrit2, nc);
-    A(c->c_rec, nc);
-    A(c->g_first, want);
-    A(c->g_count, want);
-    A(c->g_npp, want);
-    A(c->g_npc, want);
-    A(c->g_centre, want);
-    A(c->g_half, want);
-    A(c->red, c->red_len);
-#undef A
+    B(c->acc4, z.n);
+    B(c->pcl, z.n);
+    B(c->split, z.n);
+    B(c->lam, z.n);
+    B(c->gflag, z.n);
+    B(c->blk, z.blk);
+    B(c->scan_tmp, z.scan);
+    B(c->c_first, z.cells);
+    B(c->c_count, z.cells);
+    B(c->c_child, z.cells);
+    B(c->c_nchild, z.cells);
+    B(c->c_parent, z.cells);
+    B(c->c_level, z.cells);
+    B(c->c_leaf, z.cells);
+    B(c->c_com, z.cells);
+    B(c->c_S, 6 * z.cells);
+    B(c->c_q0, z.cells);
+    B(c->c_q1, z.cells);
+    B(c->c_rcrit2, z.cells);
+    B(c->c_rec, z.cells);
+    B(c->walk_spill, walk_spill_words(z.spill_waves));
+    B(c->g_first, z.n);
+    B(c->g_count, z.n);
+    B(c->g_npp, z.n);
+    B(c->g_npc, z.n);
+    B(c->g_centre, z.n);
+    B(c->g_half, z.n);
+    B(c->clus, z.K);
+    B(c->dom, z.K);
+    B(c->chunks, z.chunks);
+    B(c->bb_part, 6 * z.chunks);
+    B(c->e_part, 5 * z.chunks);
+    B(c->e_out, 5 * z.K);
+#undef B
+    return e;
+}
+
+int64_t bytes_for(bh_ctx *c, const Sizes &z)
+{
+    int64_t total = 0;
+    bh_ctx tmp;     // pointers only
+    (void)each_buffer(&tmp, z, [&](auto **, size_t sz, int64_t cnt) {
+        total += (int64_t)sz * std::max<int64_t>(cnt, 1);
+        return hipSuccess;
+    });
+    (void)c;
+    return total;
+}
+
+// Room for n particles in K clusters with the given smallest leaf size; keeps
+// the buffers if they already fit.  Reallocation drops the loaded system.
+int ensure_capacity(bh_ctx *c, int64_t n, int64_t K, int nleaf_min)
+{
+    const int64_t nchunks_max = n / kChunk + K + 1;
+    if (n <= c->cap_n && K <= c->cap_k && nchunks_max <= c->cap_chunks &&
+        cell_bound(n, K, nleaf_min) <= c->cap_c)
+        return BH_OK;
+    int64_t wn = std::max(n, c->p.max_n);
+    int64_t wk = std::max(K, c->p.max_clusters);
+    const int lmin = std::min(nleaf_min, (int)c->p.nleaf);
+    Sizes z = sizes_for(c, wn, wk, lmin);
+    if (c->p.hbm_budget_bytes > 0 && bytes_for(c, z) > c->p.hbm_budget_bytes) {
+        z = sizes_for(c, n, K, nleaf_min);
+        if (bytes_for(c, z) > c->p.hbm_budget_bytes)
+            return fail(c, BH_ENOMEM, "particle count exceeds the context's memory budget");
+    }
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_buffers(c);
+    hipError_t e = each_buffer(c, z, [&](auto **pp, size_t sz, int64_t cnt) {
+        const int64_t bytes = (int64_t)sz * std::max<int64_t>(cnt, 1);
+        hipError_t r = hipMalloc((void **)pp, (size_t)bytes);
+        if (r == hipSuccess) c->bytes += bytes;
+        return r;
+    });
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->clus_h, sizeof(DevCluster) * (size_t)z.K, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->chunks_h, sizeof(Chunk) * (size_t)z.chunks, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->e_out_h, sizeof(double) * 5 * (size_t)z.K, hipHostMallocDefault);
     if (e != hipSuccess) {
         free_buffers(c);
         (void)hipGetLastError();
         return fail(c, BH_ENOMEM, "device allocation failed");
     }
-    c->cap_n = want;
-    c->cap_c = nc;
+    c->cap_n = z.n;
+    c->cap_k = z.K;
+    c->cap_chunks = z.chunks;
+    c->cap_c = z.cells;
+    c->walk_spill_waves = z.spill_waves;
     return BH_OK;
 }
 
-// Read the device scalars back (synchronous) and check the build's flags.
-int read_misc(bh_ctx *c)
+// ---------------------------------------------------------------------------
+// host staging of the cluster table
+
+// The pinned staging arrays may be rewritten only once earlier uploads from
+// them have completed.
+int staging_ready(bh_ctx *c)
+{
+    if (c->staging_busy) {
+        TRY_HIP(c, hipStreamSynchronize(c->stream));
+        c->staging_busy = false;
+    }
+    return BH_OK;
+}
+
+int upload_clusters(bh_ctx *c)
+{
+    TRY_HIP(c, hipMemcpyAsync(c->clus, c->clus_h, sizeof(DevCluster) * (size_t)c->K,
+                              hipMemcpyHostToDevice, c->stream));
+    c->staging_busy = true;
+    return BH_OK;
+}
+
+bool bad_theta(float theta) { return !(theta > 0.0f && theta <= 1.0f); }
+bool bad_eps(float eps) { return !(eps >= 0.0f) || !std::isfinite(eps); }
+
+// Checks a cluster table and resolves leaf / group sizes of 0 to the context's.
+int check_clusters(bh_ctx *c, const bh_cluster *cl, int64_t K, std::vector<bh_cluster> &out,
+                   int64_t *total)
+{
+    if (!cl) return fail(c, BH_EINVAL, "null cluster table");
+    if (K < 1 || K > 0x7fffffffLL) return fail(c, BH_EINVAL, "number of clusters must be >= 1");
+    out.assign(cl, cl + K);
+    int64_t n = 0;
+    for (auto &q : out) {
+        if (q.nleaf == 0) q.nleaf = c->p.nleaf;
+        if (q.ncrit == 0) q.ncrit = c->p.ncrit;
+        if (q.n < 1) return fail(c, BH_EINVAL, "every cluster needs n >= 1");
+        if (q.nleaf < 1 || q.nleaf > 64 || q.ncrit < 1 || q.ncrit > 64)
+            return fail(c, BH_EINVAL, "cluster nleaf and ncrit must be in 1..64");
+        if (bad_theta(q.theta)) return fail(c, BH_EINVAL, "cluster theta must be in (0, 1]");
+        if (bad_eps(q.eps)) return fail(c, BH_EINVAL, "cluster eps must be finite and >= 0");
+        if (!std::isfinite(q.dt)) return fail(c, BH_EINVAL, "cluster dt must be finite");
+        n += q.n;
+        if (n > 0x7fffffffLL) return fail(c, BH_EINVAL, "a batch holds fewer than 2^31 particles");
+    }
+    *total = n;
+    return BH_OK;
+}
+
+void fill_params(DevCluster &d, const bh_cluster &q)
+{
+    d.dt = q.dt;
+    d.theta = q.theta;
+    const float e = q.eps;
+    d.eps2 = e * e;
+}
+
+// Writes the cluster and chunk tables of the (checked) batch to the staging
+// arrays and uploads them.
+int load_table(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n)
+{
+    TRY_ST(staging_ready(c));
+    const int64_t K = (int64_t)cl.size();
+    int64_t first = 0, nch = 0;
+    int lmax = 1;
+    for (int64_t k = 0; k < K; ++k) {
+        const bh_cluster &q = cl[k];
+        DevCluster d;
+        memset(&d, 0, sizeof(d));
+        fill_params(d, q);
+        d.first = (uint32_t)first;
+        d.n = (uint32_t)q.n;
+        d.nleaf = (uint32_t)q.nleaf;
+        d.ncrit = (uint32_t)q.ncrit;
+        d.chunk0 = (uint32_t)nch;
+        for (int64_t b = 0; b < q.n; b += kChunk) {
+            Chunk ch;
+            ch.cluster = (uint32_t)k;
+            ch.begin = (uint32_t)(first + b);
+            ch.end = (uint32_t)(first + std::min<int64_t>(q.n, b + kChunk));
+            ch.pad = 0;
+            c->chunks_h[nch++] = ch;
+        }
+        d.nchunk = (uint32_t)(nch - d.chunk0);
+        c->clus_h[k] = d;
+        lmax = std::max(lmax, (int)q.nleaf);
+        first += q.n;
+    }
+    c->n = n;
+    c->K = K;
+    c->nchunks = nch;
+    c->max_nleaf = lmax;
+    c->host_clusters = cl;
+    c->layout += 1;
+    TRY_HIP(c, hipMemcpyAsync(c->chunks, c->chunks_h, sizeof(Chunk) * (size_t)nch,
+                              hipMemcpyHostToDevice, c->stream));
+    TRY_ST(upload_clusters(c));
+    return BH_OK;
+}
+
+// Sets theta, eps and dt of clusters from a table (uploads only if any changed).
+int update_params(bh_ctx *c, const std::vector<bh_cluster> &cl)
+{
+    bool changed = false;
+    for (int64_t k = 0; k < c->K && !changed; ++k) {
+        const bh_cluster &a = c->host_clusters[k], &b = cl[k];
+        changed = a.theta != b.theta || a.eps != b.eps || a.dt != b.dt;
+    }
+    if (!changed) return BH_OK;
+    TRY_ST(staging_ready(c));
+    for (int64_t k = 0; k < c->K; ++k) fill_params(c->clus_h[k], cl[k]);
+    c->host_clusters = cl;
+    return upload_clusters(c);
+}
+
+// ---------------------------------------------------------------------------
+// sequences
+
+hipError_t rec(bh_ctx *c, int i)
+{
+    if (c->capturing) return hipSuccess;
+    return hipEventRecord(c->ev[i], c->stream);
+}
+
+hipError_t enqueue_finish_build(bh_ctx *c)
+{
+    BH_HIP_TRY(rec(c, 3));
+    BH_HIP_TRY(launch_tree(c));
+    BH_HIP_TRY(launch_groups(c));
+    BH_HIP_TRY(launch_group_boxes(c));
+    BH_HIP_TRY(rec(c, 4));
+    BH_HIP_TRY(launch_moments(c));
+    BH_HIP_TRY(rec(c, 5));
+    return hipSuccess;
+}
+
+// Build from caller arrays in cluster order (first load of a system).
+hipError_t enqueue_load(bh_ctx *c, const double *pos, const double *mass, const double *vel)
+{
+    c->cur = 0;
+    BH_HIP_TRY(launch_cluster_ids(c));
+    BH_HIP_TRY(rec(c, 0));
+    BH_HIP_TRY(launch_domain(c, pos));
+    BH_HIP_TRY(launch_keys(c, pos));
+    BH_HIP_TRY(rec(c, 1));
+    BH_HIP_TRY(radix_sort_pairs(c));
+    BH_HIP_TRY(rec(c, 2));
+    BH_HIP_TRY(launch_reorder_from_caller(c, pos, mass, vel, c->val[0]));
+    return enqueue_finish_build(c);
+}
+
+// Rebuild from the particles held in the context (after a drift or set_state).
+hipError_t enqueue_rebuild(bh_ctx *c)
+{
+    BH_HIP_TRY(rec(c, 0));
+    BH_HIP_TRY(launch_domain(c, nullptr));
+    BH_HIP_TRY(launch_keys(c, nullptr));
+    BH_HIP_TRY(rec(c, 1));
+    BH_HIP_TRY(radix_sort_pairs(c));
+    BH_HIP_TRY(rec(c, 2));
+    BH_HIP_TRY(launch_reorder(c, c->val[0]));
+    return enqueue_finish_build(c);
+}
+
+hipError_t enqueue_forces(bh_ctx *c, float *acc, float *pot)
+{
+    BH_HIP_TRY(rec(c, 6));
+    BH_HIP_TRY(launch_rcrit(c));
+    BH_HIP_TRY(launch_walk(c, !c->capturing));
+    BH_HIP_TRY(launch_scatter(c, acc, pot));
+    BH_HIP_TRY(rec(c, 7));
+    return hipSuccess;
+}
+
+// kick-drift-kick with each cluster's dt
+hipError_t enqueue_step(bh_ctx *c)
+{
+    BH_HIP_TRY(launch_kick_drift(c));
+    BH_HIP_TRY(enqueue_rebuild(c));
+    BH_HIP_TRY(enqueue_forces(c, nullptr, nullptr));
+    BH_HIP_TRY(launch_kick(c));
+    return hipSuccess;
+}
+
+// One step as a graph replay.  The particle buffers ping-pong once per step, so
+// there is one captured graph per parity; both are recaptured when the buffers
+// or the cluster layout change.  Capture runs on a private stream (the caller's
+// may be the null stream, which cannot capture); the replay runs on the context
+// stream.  No memset or event record is captured.
+int step_graph(bh_ctx *c)
+{
+    if (c->graph_layout != c->layout) {
+        TRY_HIP(c, hipStreamSynchronize(c->stream));
+        drop_graphs(c);
+        c->graph_layout = c->layout;
+    }
+    const int k = c->cur;
+    if (!c->graph_exec[k]) {
+        if (!c->cap_stream) TRY_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        c->capturing = true;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+        hipError_t e_step = hipSuccess;
+        hipGraph_t g = nullptr;
+        if (e == hipSuccess) {
+            e_step = enqueue_step(c);
+            e = hipStreamEndCapture(c->stream, &g);
+        }
+        c->stream = user;
+        c->capturing = false;
+        c->cur = k;
+        if (e_step != hipSuccess) e = e_step;
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec[k], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph_exec[k] = nullptr;
+            return hip_fail(c, e, "capture of the leapfrog step");
+        }
+    }
+    TRY_HIP(c, hipGraphLaunch(c->graph_exec[k], c->stream));
+    c->cur = k ^ 1;
+    c->graph_launches += 1;
+    return BH_OK;
+}
+
+// Drains the stream, refreshes the host copies of the device counts and
+// reports (then clears) the error bits raised on the device since the last
+// check.
+int sync_check(bh_ctx *c)
 {
     TRY_HIP(c, hipMemcpyAsync(c->misc_h, c->misc, sizeof(DevMisc), hipMemcpyDeviceToHost, c->stream));
     TRY_HIP(c, hipStreamSynchronize(c->stream));
-    return BH_OK;
-}
-
-// Tree, groups and moments from the particles now in key order.
-int finish_build(bh_ctx *c)
-{
-    const int64_t n = c->n;
-    TRY_HIP(c, hipEventRecord(c->ev[3], c->stream));
-    TRY_HIP(c, launch_tree(c, n));
-    TRY_HIP(c, launch_groups(c, n));
-    int st = read_misc(c);
-    if (st) return st;
+    c->staging_busy = false;
     const DevMisc &m = *c->misc_h;
-    if (m.nonfinite & 1u) {
-        c->built = false;
-        return fail(c, BH_EINVAL, "non-finite particle coordinate");
-    }
-    if (m.nonfinite & 2u) {
-        c->built = false;
-        return fail(c, BH_EINVAL, "particle mass must be finite and > 0");
-    }
-    if (m.nonfinite & 4u) {
-        c->built = false;
-        return fail(c, BH_EDEVICE, "cell capacity exceeded");
-    }
     c->ncells = m.ncells;
     c->ngroups = m.ngroups;
     c->nleaves = m.nleaves;
     c->depth = (int)m.depth;
-    if (c->ncells < 1 || c->ncells > c->cap_c || c->ngroups < 1 || c->ngroups > n) {
+    const uint32_t bits = m.nonfinite;
+    const uint32_t over = m.walk_overflow;
+    if (bits || over) {
+        TRY_HIP(c, hipMemsetAsync(&c->misc->nonfinite, 0, sizeof(uint32_t), c->stream));
+        TRY_HIP(c, hipMemsetAsync(&c->misc->walk_overflow, 0, sizeof(uint32_t), c->stream));
+        TRY_HIP(c, hipStreamSynchronize(c->stream));
         c->built = false;
+        c->have_forces = false;
+        if (bits & 1u) return fail(c, BH_EINVAL, "non-finite particle coordinate");
+        if (bits & 2u) return fail(c, BH_EINVAL, "particle mass must be finite and > 0");
+        if (bits & 4u) return fail(c, BH_EDEVICE, "cell capacity exceeded");
+        return fail(c, BH_EDEVICE, "walk list overflow");
+    }
+    if (c->built && (c->ncells < c->K || c->ncells > c->cap_c || c->ngroups < c->K ||
+                     c->ngroups > c->n)) {
+        c->built = false;
+        c->have_forces = false;
         return fail(c, BH_EDEVICE, "tree construction produced inconsistent counts");
     }
-    TRY_HIP(c, launch_group_boxes(c, c->ngroups));
-    TRY_HIP(c, hipEventRecord(c->ev[4], c->stream));
-    TRY_HIP(c, launch_moments(c, c->ncells));
-    TRY_HIP(c, hipEventRecord(c->ev[5], c->stream));
-    c->built = true;
-    c->have_forces = false;
     return BH_OK;
 }
 
-// Rebuild from the particles held in the context (after a drift or set_state).
-int rebuild(bh_ctx *c)
+void reset_e0(bh_ctx *c)
 {
-    const int64_t n = c->n;
-    TRY_HIP(c, hipEventRecord(c->ev[0], c->stream));
-    TRY_HIP(c, launch_bbox(c, nullptr, n));
-    TRY_HIP(c, launch_keys(c, nullptr, n));
-    TRY_HIP(c, hipEventRecord(c->ev[1], c->stream));
-    TRY_HIP(c, radix_sort_pairs(c, n));
-    TRY_HIP(c, hipEventRecord(c->ev[2], c->stream));
-    TRY_HIP(c, launch_reorder(c, c->val[0], n));
-    return finish_build(c);
+    c->have_e0 = false;
+    c->have_e0_k.assign((size_t)c->K, 0);
+    c->e0_k.assign((size_t)c->K, 0.0);
 }
 
-int forces(bh_ctx *c, float theta, float eps, float *acc, float *pot)
+int load(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n, const double *pos,
+         const double *mass, const double *vel)
 {
-    TRY_HIP(c, hipEventRecord(c->ev[6], c->stream));
-    TRY_HIP(c, launch_rcrit(c, c->ncells, theta));
-    TRY_HIP(c, launch_walk(c, theta, eps));
-    TRY_HIP(c, launch_scatter(c, acc, pot));
-    TRY_HIP(c, hipEventRecord(c->ev[7], c->stream));
-    c->theta = theta;
-    c->eps = eps;
+    int lmin = 64;
+    for (auto &q : cl) lmin = std::min(lmin, (int)q.nleaf);
+    TRY_ST(ensure_capacity(c, n, (int64_t)cl.size(), lmin));
+    c->built = false;
+    c->have_forces = false;
+    TRY_ST(load_table(c, cl, n));
+    reset_e0(c);
+    TRY_HIP(c, enqueue_load(c, pos, mass, vel));
+    c->built = true;
+    return sync_check(c);
+}
+
+int run_forces(bh_ctx *c, float *acc, float *pot)
+{
+    if (!c->built) return fail(c, BH_ESTATE, "forces need a built tree");
+    TRY_HIP(c, enqueue_forces(c, acc, pot));
     c->have_forces = true;
     return BH_OK;
 }
 
-bool bad_theta_eps(float theta, float eps)
+int energies(bh_ctx *c)
 {
-    return !(theta > 0.0f && theta <= 1.0f) || !(eps >= 0.0f) || !std::isfinite(eps);
+    if (!c->have_forces) return fail(c, BH_ESTATE, "energy needs potentials from a force call");
+    TRY_HIP(c, launch_energy(c));
+    TRY_HIP(c, hipMemcpyAsync(c->e_out_h, c->e_out, sizeof(double) * 5 * (size_t)c->K,
+                              hipMemcpyDeviceToHost, c->stream));
+    return sync_check(c);
+}
+
+void fill_energy(double *out, const double *s, double *e0, bool *have)
+{
+    const double T = s[0], W = s[1], E = T + W;
+    if (!*have) {
+        *e0 = E;
+        *have = true;
+    }
+    out[0] = T;
+    out[1] = W;
+    out[2] = E;
+    out[3] = s[2];
+    out[4] = s[3];
+    out[5] = s[4];
+    out[6] = (*e0 != 0.0) ? (*e0 - E) / *e0 : 0.0;
 }
 
 }  // namespace
@@ -265,6 +580,7 @@ int bh_default_params(bh_params *p)
     p->ncrit = 64;
     p->max_n = 0;
     p->hbm_budget_bytes = 0;
+    p->max_clusters = 0;
     return BH_OK;
 }
 
@@ -276,7 +592,7 @@ int bh_create(bh_ctx **out, const bh_params *p, void *hip_stream)
     bh_default_params(&q);
     if (p) q = *p;
     if (q.nleaf < 1 || q.nleaf > 64 || q.ncrit < 1 || q.ncrit > 64 || q.max_n < 0 ||
-        q.hbm_budget_bytes < 0)
+        q.hbm_budget_bytes < 0 || q.max_clusters < 0 || q.max_n > 0x7fffffffLL)
         return BH_EINVAL;
     bh_ctx *c = new (std::nothrow) bh_ctx();
     if (!c) return BH_ENOMEM;
@@ -284,15 +600,9 @@ int bh_create(bh_ctx **out, const bh_params *p, void *hip_stream)
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipMalloc((void **)&c->misc, sizeof(DevMisc)) != hipSuccess ||
-        hipMalloc((void **)&c->bb_part, 6 * 1024 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void **)&c->misc_h, sizeof(DevMisc), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->red_h, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&c->misc_h, sizeof(DevMisc), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
-        if (c->misc) (void)hipFree(c->misc);
-        if (c->bb_part) (void)hipFree(c->bb_part);
-        if (c->misc_h) (void)hipHostFree(c->misc_h);
-        if (c->red_h) (void)hipHostFree(c->red_h);
-        delete c;
+        bh_destroy(c);
         return BH_EDEVICE;
     }
     for (int i = 0; i < 8; ++i) {
@@ -317,7 +627,7 @@ int bh_create(bh_ctx **out, const bh_params *p, void *hip_stream)
         return BH_EDEVICE;
     }
     if (q.max_n > 0) {
-        int st = ensure_capacity(c, q.max_n);
+        int st = ensure_capacity(c, q.max_n, std::max<int64_t>(1, q.max_clusters), q.nleaf);
         if (st) {
             bh_destroy(c);
             return st;
@@ -334,13 +644,13 @@ int bh_destroy(bh_ctx *c)
     else (void)hipDeviceSynchronize();
     free_buffers(c);
     if (c->misc) (void)hipFree(c->misc);
-    if (c->bb_part) (void)hipFree(c->bb_part);
-    if (c->misc_h) (void)hipHostFree(c->misc_h);
-    if (c->red_h) (void)hipHostFree(c->red_h);
+    hfree(c->misc_h);
     for (int i = 0; i < 8; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     for (int i = 0; i < 2 * bh_ctx::kWalkRing; ++i)
         if (c->wev[i]) (void)hipEventDestroy(c->wev[i]);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    (void)hipGetLastError();
     delete c;
     return BH_OK;
 }
@@ -350,21 +660,42 @@ int bh_build_tree(bh_ctx *c, const double *pos, const double *mass, int64_t n)
     if (!c) return BH_EINVAL;
     if (!pos || !mass) return fail(c, BH_EINVAL, "null pos or mass");
     if (n < 1 || n > 0x7fffffffLL) return fail(c, BH_EINVAL, "n must be in [1, 2^31)");
-    int st = ensure_capacity(c, n);
-    if (st) return st;
-    c->n = n;
-    c->cur = 0;
-    c->built = false;
-    c->have_forces = false;
-    c->have_e0 = false;
-    TRY_HIP(c, hipEventRecord(c->ev[0], c->stream));
-    TRY_HIP(c, launch_bbox(c, pos, n));
-    TRY_HIP(c, launch_keys(c, pos, n));
-    TRY_HIP(c, hipEventRecord(c->ev[1], c->stream));
-    TRY_HIP(c, radix_sort_pairs(c, n));
-    TRY_HIP(c, hipEventRecord(c->ev[2], c->stream));
-    TRY_HIP(c, launch_reorder_from_caller(c, pos, mass, c->val[0], n));
-    return finish_build(c);
+    bh_cluster one;
+    one.n = n;
+    // theta, eps and dt are set by the force and step calls
+    one.theta = c->K == 1 && !c->host_clusters.empty() ? c->host_clusters[0].theta : 0.75f;
+    one.eps = c->K == 1 && !c->host_clusters.empty() ? c->host_clusters[0].eps : 0.0f;
+    one.dt = c->K == 1 && !c->host_clusters.empty() ? c->host_clusters[0].dt : 0.0;
+    one.nleaf = c->p.nleaf;
+    one.ncrit = c->p.ncrit;
+    return load(c, std::vector<bh_cluster>(1, one), n, pos, mass, nullptr);
+}
+
+int bh_batch_build(bh_ctx *c, const bh_cluster *clusters, int64_t k, const double *pos,
+                   const double *mass, const double *vel)
+{
+    if (!c) return BH_EINVAL;
+    if (!pos || !mass) return fail(c, BH_EINVAL, "null pos or mass");
+    std::vector<bh_cluster> cl;
+    int64_t n = 0;
+    TRY_ST(check_clusters(c, clusters, k, cl, &n));
+    return load(c, cl, n, pos, mass, vel);
+}
+
+int bh_batch_set_params(bh_ctx *c, const bh_cluster *clusters, int64_t k)
+{
+    if (!c) return BH_EINVAL;
+    if (!c->built) return fail(c, BH_ESTATE, "no batch loaded");
+    std::vector<bh_cluster> cl;
+    int64_t n = 0;
+    TRY_ST(check_clusters(c, clusters, k, cl, &n));
+    if (k != c->K) return fail(c, BH_EINVAL, "cluster count differs from the loaded batch");
+    for (int64_t i = 0; i < k; ++i) {
+        const bh_cluster &a = c->host_clusters[i], &b = cl[i];
+        if (a.n != b.n || a.nleaf != b.nleaf || a.ncrit != b.ncrit)
+            return fail(c, BH_EINVAL, "n, nleaf and ncrit must match the loaded batch");
+    }
+    return update_params(c, cl);
 }
 
 int bh_set_velocities(bh_ctx *c, const double *vel)
@@ -373,30 +704,51 @@ int bh_set_velocities(bh_ctx *c, const double *vel)
     if (!vel) return fail(c, BH_EINVAL, "null vel");
     if (!c->built) return fail(c, BH_ESTATE, "no particles loaded");
     TRY_HIP(c, launch_set_velocities(c, vel));
-    c->have_e0 = false;
+    reset_e0(c);
     return BH_OK;
 }
 
 int bh_compute_forces(bh_ctx *c, float theta, float eps, float *acc, float *pot)
 {
     if (!c) return BH_EINVAL;
-    if (bad_theta_eps(theta, eps)) return fail(c, BH_EINVAL, "theta must be in (0, 1] and eps >= 0");
+    if (bad_theta(theta) || bad_eps(eps))
+        return fail(c, BH_EINVAL, "theta must be in (0, 1] and eps >= 0");
     if (!c->built) return fail(c, BH_ESTATE, "compute_forces needs a built tree");
-    return forces(c, theta, eps, acc, pot);
+    std::vector<bh_cluster> cl = c->host_clusters;
+    for (auto &q : cl) {
+        q.theta = theta;
+        q.eps = eps;
+    }
+    TRY_ST(update_params(c, cl));
+    return run_forces(c, acc, pot);
+}
+
+int bh_batch_forces(bh_ctx *c, float *acc, float *pot)
+{
+    if (!c) return BH_EINVAL;
+    return run_forces(c, acc, pot);
 }
 
 int bh_leapfrog_step(bh_ctx *c, double dt)
 {
     if (!c) return BH_EINVAL;
     if (!std::isfinite(dt)) return fail(c, BH_EINVAL, "dt must be finite");
-    if (!c->built || !c->have_forces) return fail(c, BH_ESTATE, "leapfrog_step needs a prior compute_forces");
-    const float theta = c->theta, eps = c->eps;
-    TRY_HIP(c, launch_kick_drift(c, 0.5 * dt, dt));
-    int st = rebuild(c);
-    if (st) return st;
-    st = forces(c, theta, eps, nullptr, nullptr);
-    if (st) return st;
-    TRY_HIP(c, launch_kick(c, 0.5 * dt));
+    if (!c->built || !c->have_forces)
+        return fail(c, BH_ESTATE, "leapfrog_step needs a prior compute_forces");
+    std::vector<bh_cluster> cl = c->host_clusters;
+    for (auto &q : cl) q.dt = dt;
+    TRY_ST(update_params(c, cl));
+    TRY_HIP(c, enqueue_step(c));
+    return BH_OK;
+}
+
+int bh_batch_run(bh_ctx *c, int32_t nsteps)
+{
+    if (!c) return BH_EINVAL;
+    if (nsteps < 0) return fail(c, BH_EINVAL, "nsteps must be >= 0");
+    if (!c->built || !c->have_forces)
+        return fail(c, BH_ESTATE, "batch_run needs a prior force evaluation");
+    for (int32_t s = 0; s < nsteps; ++s) TRY_ST(step_graph(c));
     return BH_OK;
 }
 
@@ -415,32 +767,34 @@ int bh_set_state(bh_ctx *c, const double *pos, const double *vel)
     if (!pos || !vel) return fail(c, BH_EINVAL, "null pos or vel");
     if (!c->built) return fail(c, BH_ESTATE, "no particles loaded");
     TRY_HIP(c, launch_set_positions(c, pos, vel));
-    c->have_e0 = false;
-    return rebuild(c);
+    reset_e0(c);
+    c->have_forces = false;
+    TRY_HIP(c, enqueue_rebuild(c));
+    return sync_check(c);
 }
 
 int bh_energy(bh_ctx *c, double out[7])
 {
     if (!c) return BH_EINVAL;
     if (!out) return fail(c, BH_EINVAL, "null out");
-    if (!c->have_forces) return fail(c, BH_ESTATE, "energy needs potentials from compute_forces");
-    TRY_HIP(c, launch_energy(c));
-    TRY_HIP(c, hipMemcpyAsync(c->red_h, c->red + (c->red_len - 8), 5 * sizeof(double),
-                              hipMemcpyDeviceToHost, c->stream));
-    TRY_HIP(c, hipStreamSynchronize(c->stream));
-    const double T = c->red_h[0], W = c->red_h[1];
-    const double E = T + W;
-    if (!c->have_e0) {
-        c->e0 = E;
-        c->have_e0 = true;
+    TRY_ST(energies(c));
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int64_t k = 0; k < c->K; ++k)
+        for (int j = 0; j < 5; ++j) s[j] += c->e_out_h[5 * k + j];
+    fill_energy(out, s, &c->e0, &c->have_e0);
+    return BH_OK;
+}
+
+int bh_batch_energy(bh_ctx *c, double *out)
+{
+    if (!c) return BH_EINVAL;
+    if (!out) return fail(c, BH_EINVAL, "null out");
+    TRY_ST(energies(c));
+    for (int64_t k = 0; k < c->K; ++k) {
+        bool have = c->have_e0_k[k] != 0;
+        fill_energy(out + 7 * k, c->e_out_h + 5 * k, &c->e0_k[k], &have);
+        c->have_e0_k[k] = have ? 1 : 0;
     }
-    out[0] = T;
-    out[1] = W;
-    out[2] = E;
-    out[3] = c->red_h[2];
-    out[4] = c->red_h[3];
-    out[5] = c->red_h[4];
-    out[6] = (c->e0 != 0.0) ? (c->e0 - E) / c->e0 : 0.0;
     return BH_OK;
 }
 
@@ -448,8 +802,7 @@ int bh_stats_get(bh_ctx *c, bh_stats *out)
 {
     if (!c) return BH_EINVAL;
     if (!out) return fail(c, BH_EINVAL, "null out");
-    int st = read_misc(c);
-    if (st) return st;
+    const int st = sync_check(c);
     bh_stats s;
     memset(&s, 0, sizeof(s));
     s.n = c->n;
@@ -477,9 +830,10 @@ int bh_stats_get(bh_ctx *c, bh_stats *out)
     s.walk_kernel_launches = c->walk_launches;
     s.total_npp = (int64_t)c->misc_h->tot_npp;
     s.total_npc = (int64_t)c->misc_h->tot_npc;
+    s.nclusters = c->K;
+    s.graph_launches = c->graph_launches;
     *out = s;
-    if (c->misc_h->walk_overflow) return fail(c, BH_EDEVICE, "walk list overflow");
-    return BH_OK;
+    return st;
 }
 
 int bh_export_tree(bh_ctx *c, const bh_tree_host *o)
@@ -487,7 +841,7 @@ int bh_export_tree(bh_ctx *c, const bh_tree_host *o)
     if (!c) return BH_EINVAL;
     if (!o) return fail(c, BH_EINVAL, "null out");
     if (!c->built) return fail(c, BH_ESTATE, "no tree");
-    TRY_HIP(c, hipStreamSynchronize(c->stream));
+    TRY_ST(sync_check(c));
     const int64_t n = c->n, nc = c->ncells, ng = c->ngroups;
     auto get = [&](auto *dst, const auto *src, int64_t cnt) -> hipError_t {
         return hipMemcpy(dst, src, sizeof(*src) * (size_t)cnt, hipMemcpyDeviceToHost);
@@ -517,7 +871,8 @@ int bh_export_tree(bh_ctx *c, const bh_tree_host *o)
         if (o->parent) o->parent[i] = parent[i] == kNone ? -1 : (int64_t)parent[i];
         if (o->child) o->child[i] = leaf[i] ? -1 : (int64_t)child[i];
         if (o->nchild) o->nchild[i] = leaf[i] ? 0 : (int32_t)nchild[i];
-        if (o->prefix) o->prefix[i] = first[i] < (uint32_t)n ? (skey[first[i]] >> (3 * (kMaxLevel - level[i]))) : 0;
+        if (o->prefix)
+            o->prefix[i] = first[i] < (uint32_t)n ? (skey[first[i]] >> (3 * (kMaxLevel - level[i]))) : 0;
     }
     if (o->mass || o->com) {
         std::vector<double4> com(nc);

@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/bh.h"
 
@@ -44,13 +45,47 @@ struct alignas(64) WalkCell {
 };
 static_assert(sizeof(WalkCell) == 64, "walk record must be one 64-byte block");
 
+// One cluster of a batch: its particles are [first, first + n) of the particle
+// arrays (the same range before and after sorting), with its own opening angle,
+// softening, leaf and group sizes and time step.  Set by the host.
+struct DevCluster {
+    double dt;           // leapfrog step
+    float theta;         // opening angle of Eq. (1)
+    float eps2;          // squared Plummer softening (float32 eps squared)
+    uint32_t first;      // first particle
+    uint32_t n;          // particles
+    uint32_t nleaf;      // most particles in a leaf
+    uint32_t ncrit;      // most particles in a group
+    uint32_t chunk0;     // first chunk of the cluster in the chunk table
+    uint32_t nchunk;     // chunks of the cluster
+    uint32_t pad[2];
+};
+static_assert(sizeof(DevCluster) == 48, "cluster record layout");
+
+// The cubic domain of one cluster (App. B), computed on the device at each build.
+struct DevDomain {
+    double lo[3];        // lower corner
+    double L;            // cube side
+    double scale;        // 2^20 / L
+    double pad[3];
+};
+
+// A contiguous piece of one cluster's particles, processed by one block of the
+// segmented kernels (bounding box, keys, energy).
+struct Chunk {
+    uint32_t cluster;
+    uint32_t begin;
+    uint32_t end;
+    uint32_t pad;
+};
+constexpr int kChunk = 4096;           // particles per chunk
+
 // Small device-side scalars shared by the build and walk kernels.
 struct DevMisc {
+    // error bits, kept until the host reads and clears them: bit 0 non-finite
+    // coordinate, bit 1 bad mass, bit 2 cell capacity
     uint32_t nonfinite;
     uint32_t pad0;
-    double lo[3];
-    double L;
-    double scale;
     uint32_t level_count[kLevels];
     uint32_t level_offset[kLevels + 1];
     uint32_t ncells;
@@ -73,21 +108,38 @@ struct bh_ctx {
     bh_params p{};
     std::string err;
 
-    int64_t n = 0;          // particles in the current system
+    int64_t n = 0;          // particles in the current system (all clusters)
+    int64_t K = 0;          // clusters
+    int64_t nchunks = 0;
+    int max_nleaf = 16;     // largest leaf size over the clusters (LDS halo of the tree build)
     int64_t cap_n = 0;      // particle capacity of the buffers
     int64_t cap_c = 0;      // cell capacity
+    int64_t cap_k = 0;      // cluster capacity
+    int64_t cap_chunks = 0;
     int64_t bytes = 0;      // device bytes held
     int cur = 0;            // which particle buffer holds the current state
     bool built = false;
     bool have_forces = false;
     bool have_e0 = false;
-    double e0 = 0.0;
-    float theta = 0.75f;
-    float eps = 0.0f;
+    int64_t layout = 0;     // changes whenever buffers or the cluster table change
 
-    // host copies of counts after a build
+    // host copies of counts, refreshed at synchronisation points
     int64_t ncells = 0, ngroups = 0, nleaves = 0;
     int depth = 0;
+
+    // ---- clusters ----
+    bh::DevCluster *clus = nullptr;          // device [K]
+    bh::DevCluster *clus_h = nullptr;        // pinned host staging of the table
+    bh::DevDomain *dom = nullptr;            // device [K]
+    bh::Chunk *chunks = nullptr;             // device [nchunks]
+    bh::Chunk *chunks_h = nullptr;           // pinned host staging
+    bool staging_busy = false;               // an upload from the staging may be in flight
+    uint32_t *pcl = nullptr;                 // cluster of each particle position
+    std::vector<double> e0_k;                // per-cluster energy at the first energy call
+    std::vector<uint8_t> have_e0_k;
+    double e0 = 0.0;                         // the same for the whole batch (bh_energy)
+    std::vector<bh_cluster> host_clusters;   // the loaded cluster table as given
+    bool capturing = false;                  // enqueueing into a graph: no event records
 
     // ---- particle buffers (sorted order) ----
     double4 *p4[2] = {nullptr, nullptr};     // x, y, z, mass
@@ -124,14 +176,13 @@ struct bh_ctx {
     // ---- scalars ----
     bh::DevMisc *misc = nullptr;             // device
     bh::DevMisc *misc_h = nullptr;           // pinned host mirror
-    double *red = nullptr;                   // energy partial sums
-    double *bb_part = nullptr;               // bounding-box block partials [6][1024]
-    int64_t red_len = 0;
-    double *red_h = nullptr;                 // pinned host copy of the 6 sums
+    double *bb_part = nullptr;               // bounding-box chunk partials [nchunks][6]
+    double *e_part = nullptr;                // energy chunk partials [nchunks][5]
+    double *e_out = nullptr;                 // energy per cluster [K][5]
+    double *e_out_h = nullptr;               // pinned host copy
 
     hipEvent_t ev[8] = {};
     bh_stats stats{};
-    int lanes_max = 0;
 
     // start/end events around each walk-kernel launch, harvested lazily
     static constexpr int kWalkRing = 64;
@@ -139,6 +190,12 @@ struct bh_ctx {
     int wring_head = 0, wring_count = 0;
     double walk_ms_total = 0.0, walk_ms_last = 0.0;
     int64_t walk_launches = 0;
+    int64_t graph_launches = 0;
+
+    // captured leapfrog step, one per parity of the particle ping-pong buffers
+    hipStream_t cap_stream = nullptr;        // capture only, never runs work
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    int64_t graph_layout = -1;
 };
 
 namespace bh {
@@ -146,37 +203,40 @@ namespace bh {
 // ---------------------------------------------------------------------------
 // launchers (each returns hipSuccess or the first HIP error)
 
-// build.hip
-hipError_t launch_bbox(bh_ctx *c, const double *pos_aos, int64_t n);   // pos_aos NULL: use p4[cur]
-hipError_t launch_keys(bh_ctx *c, const double *pos_aos, int64_t n);
+// build.hip: each takes the particles in the current buffers unless a caller
+// array is given (initial load, caller order = cluster order)
+hipError_t launch_domain(bh_ctx *c, const double *pos_aos);
+hipError_t launch_keys(bh_ctx *c, const double *pos_aos);
 hipError_t launch_reorder_from_caller(bh_ctx *c, const double *pos_aos, const double *mass,
-                                      const uint32_t *perm, int64_t n);
-hipError_t launch_reorder(bh_ctx *c, const uint32_t *perm, int64_t n);
-hipError_t launch_tree(bh_ctx *c, int64_t n);
-hipError_t launch_groups(bh_ctx *c, int64_t n);
-hipError_t launch_group_boxes(bh_ctx *c, int64_t ngroups);
-hipError_t launch_moments(bh_ctx *c, int64_t ncells);
-hipError_t launch_rcrit(bh_ctx *c, int64_t ncells, float theta);   // also fills c_rec
+                                      const double *vel, const uint32_t *perm);
+hipError_t launch_reorder(bh_ctx *c, const uint32_t *perm);
+hipError_t launch_tree(bh_ctx *c);
+hipError_t launch_groups(bh_ctx *c);
+hipError_t launch_group_boxes(bh_ctx *c);
+hipError_t launch_moments(bh_ctx *c);
+hipError_t launch_rcrit(bh_ctx *c);                 // per-cluster theta; also fills c_rec
+hipError_t launch_cluster_ids(bh_ctx *c);           // pcl from the chunk table
 
 // sort.hip
-hipError_t radix_sort_pairs(bh_ctx *c, int64_t n);      // key[0]/val[0] -> key[0]/val[0]
-hipError_t exclusive_scan_u32(bh_ctx *c, const uint32_t *in, uint32_t *out, int64_t n,
-                              uint32_t *total);          // total: device scalar or NULL
+hipError_t radix_sort_pairs(bh_ctx *c);             // sorts key[0]/val[0] of n particles
+                                                    // within clusters; result in key[0]/val[0]
 hipError_t compact_flags(bh_ctx *c, const uint8_t *flags, int64_t n, uint32_t *idx,
                          uint32_t *count);
 int64_t sort_blk_words(int64_t n);
 int64_t scan_tmp_words(int64_t n);
 
 // walk.hip
-hipError_t launch_walk(bh_ctx *c, float theta, float eps);
+hipError_t launch_walk(bh_ctx *c, bool timed);
 void walk_timer_harvest(bh_ctx *c, bool block);
 hipEvent_t *walk_timer_slot(bh_ctx *c);
 hipError_t launch_scatter(bh_ctx *c, float *acc, float *pot);
+hipError_t launch_zero_acc(bh_ctx *c);
+int64_t walk_spill_words(int64_t waves);
+int64_t walk_grid_waves(bh_ctx *c);
 
-// integrate.hip
-hipError_t launch_kick(bh_ctx *c, double h);
-hipError_t launch_drift(bh_ctx *c, double dt);
-hipError_t launch_kick_drift(bh_ctx *c, double h, double dt);
+// integrate.hip (per-cluster dt from the cluster table)
+hipError_t launch_kick(bh_ctx *c);
+hipError_t launch_kick_drift(bh_ctx *c);
 hipError_t launch_energy(bh_ctx *c);
 hipError_t launch_set_velocities(bh_ctx *c, const double *vel);
 hipError_t launch_get_state(bh_ctx *c, double *pos, double *vel, float *acc, float *pot);

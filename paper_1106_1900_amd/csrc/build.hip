@@ -3,6 +3,13 @@
 // (Sect. 2.1), links, groups (Sect. 2.2), float64 multipole moments (Sect. 3.2)
 // and the opening radius of Eq. (1) (Sect. 3.3).
 //
+// Every kernel works on a batch of K independent clusters held back to back in
+// the particle arrays (K = 1 for a single system).  Each cluster keeps its own
+// domain, keys, tree and groups; the cell array holds the cells of all clusters,
+// level-major, and within a level in particle order, so each cluster's cells form
+// exactly its own (level, key) ordered array, interleaved by level with the
+// others.  Level 0 holds the K roots in cluster order.
+//
 // The paper forms cells level by level: it masks the keys of particles not yet in
 // a leaf, groups equal masked keys by compaction, marks cells of at most N_leaf
 // particles as leaves and repeats down to the deepest level, then links parents
@@ -10,7 +17,8 @@
 // here with a fixed number of launches, independent of the depth:
 //
 //   split(i)  = first level at which sorted particles i-1 and i fall in
-//               different cells (from the common key prefix; 21 if equal keys);
+//               different cells (from the common key prefix; 21 if equal keys;
+//               0 at the first particle of a cluster);
 //   leaf(i)   = the level of the leaf holding particle i: the first level at
 //               which the run of particles sharing i's key prefix is at most
 //               N_leaf long, or 20 (found from split() within +-N_leaf of i);
@@ -21,6 +29,10 @@
 // from the per-level ranks of the same particle, and a cell's end is the first
 // start after it at the same or a shallower level.  The result is the paper's
 // cell array exactly, in its order.
+//
+// No kernel here needs a count on the host: cell, group and level counts stay in
+// device memory and the kernels that depend on them loop over fixed grids, so a
+// whole build can be captured in a HIP graph.
 #include "bh_internal.h"
 
 #pragma clang fp contract(off)
@@ -30,6 +42,7 @@ namespace bh {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kFixedGrid = 2048;       // grid of the kernels that read their size on the device
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v)
 {
@@ -60,13 +73,14 @@ __device__ __forceinline__ uint32_t coord_to_int(double x, double lo, double sca
     return f >= (double)kQMax ? kQMax : (uint32_t)f;
 }
 
+inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
 // ---------------------------------------------------------------------------
 
+// counts of the build; the error bits stay until the host clears them
 __global__ void misc_reset_kernel(DevMisc *m)
 {
-    const int t = threadIdx.x;
-    if (t == 0) {
-        m->nonfinite = 0;
+    if (threadIdx.x == 0) {
         m->nleaves = 0;
         m->ngroups = 0;
         m->ncells = 0;
@@ -93,19 +107,25 @@ struct P4Src {
     }
 };
 
-constexpr int kBBoxBlocks = 1024;
-
-// Per-block minima and maxima of each axis; part[k * nblk + b], k = 0..2 minima,
-// 3..5 maxima.  A non-finite coordinate sets bit 0 of the misc flags.
-template <typename Src>
-__global__ void __launch_bounds__(kBlock) bbox_kernel(Src src, int64_t n, double *__restrict__ part,
-                                                      DevMisc *m)
+// cluster of every particle position, from the chunk table
+__global__ void __launch_bounds__(kBlock)
+cluster_ids_kernel(const Chunk *__restrict__ chunks, uint32_t *__restrict__ pcl)
 {
+    const Chunk ch = chunks[blockIdx.x];
+    for (uint32_t i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) pcl[i] = ch.cluster;
+}
+
+// Per-chunk minima and maxima of each axis: part[6 b + k], k = 0..2 minima, 3..5
+// maxima.  A non-finite coordinate sets bit 0 of the misc flags.
+template <typename Src>
+__global__ void __launch_bounds__(kBlock)
+bbox_kernel(Src src, const Chunk *__restrict__ chunks, double *__restrict__ part, DevMisc *m)
+{
+    const Chunk ch = chunks[blockIdx.x];
     double lo[3] = {INFINITY, INFINITY, INFINITY};
     double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    for (uint32_t i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) {
         double v[3];
         src.get3(i, v);
 #pragma unroll
@@ -136,79 +156,74 @@ __global__ void __launch_bounds__(kBlock) bbox_kernel(Src src, int64_t n, double
         const int k = threadIdx.x;
         double a = s_v[k][0];
         for (int i = 1; i < kBlock / kWave; ++i) a = k < 3 ? fmin(a, s_v[k][i]) : fmax(a, s_v[k][i]);
-        part[(int64_t)k * gridDim.x + blockIdx.x] = a;
+        part[6 * (int64_t)blockIdx.x + k] = a;
     }
 }
 
-// Reduce the block partials; cube side = largest extent (1 if all extents
-// vanish); scale = 2^20 / side.
-__global__ void __launch_bounds__(kBlock) domain_kernel(const double *__restrict__ part, int nblk,
-                                                        DevMisc *m)
+// One thread per cluster: reduce its chunk partials; cube side = largest extent
+// (1 if all extents vanish); scale = 2^20 / side.
+__global__ void __launch_bounds__(kBlock)
+domain_kernel(const double *__restrict__ part, const DevCluster *__restrict__ clus,
+              DevDomain *__restrict__ dom, int64_t K)
 {
-    __shared__ double s_v[6][kBlock / kWave];
-    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
-    for (int k = 0; k < 6; ++k) {
-        double a = k < 3 ? INFINITY : -INFINITY;
-        for (int b = threadIdx.x; b < nblk; b += kBlock) {
-            const double v = part[(int64_t)k * nblk + b];
-            a = k < 3 ? fmin(a, v) : fmax(a, v);
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= K) return;
+    const DevCluster cl = clus[c];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t b = cl.chunk0; b < cl.chunk0 + cl.nchunk; ++b) {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], part[6 * (int64_t)b + k]);
+            hi[k] = fmax(hi[k], part[6 * (int64_t)b + 3 + k]);
         }
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) {
-            const double o = __shfl_xor(a, d, kWave);
-            a = k < 3 ? fmin(a, o) : fmax(a, o);
-        }
-        if (l == 0) s_v[k][w] = a;
     }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
+    DevDomain d;
     double side = 0.0;
     for (int k = 0; k < 3; ++k) {
-        double lo = INFINITY, hi = -INFINITY;
-        for (int i = 0; i < kBlock / kWave; ++i) {
-            lo = fmin(lo, s_v[k][i]);
-            hi = fmax(hi, s_v[3 + k][i]);
-        }
-        m->lo[k] = lo;
-        double e = hi - lo;
+        d.lo[k] = lo[k];
+        d.pad[k] = 0.0;
+        double e = hi[k] - lo[k];
         if (e > side) side = e;
     }
     if (side == 0.0) side = 1.0;
-    m->L = side;
-    m->scale = 1048576.0 / side;
+    d.L = side;
+    d.scale = 1048576.0 / side;
+    dom[c] = d;
 }
 
 template <typename Src>
 __global__ void __launch_bounds__(kBlock)
-keys_kernel(Src src, int64_t n, const DevMisc *__restrict__ m, uint64_t *__restrict__ key,
-            uint32_t *__restrict__ val)
+keys_kernel(Src src, const Chunk *__restrict__ chunks, const DevDomain *__restrict__ dom,
+            uint64_t *__restrict__ key, uint32_t *__restrict__ val)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const double scale = m->scale;
-    double v[3];
-    src.get3(i, v);
-    uint32_t qx = coord_to_int(v[0], m->lo[0], scale);
-    uint32_t qy = coord_to_int(v[1], m->lo[1], scale);
-    uint32_t qz = coord_to_int(v[2], m->lo[2], scale);
-    key[i] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
-    val[i] = (uint32_t)i;
+    const Chunk ch = chunks[blockIdx.x];
+    const DevDomain &cl = dom[ch.cluster];
+    const double lx = cl.lo[0], ly = cl.lo[1], lz = cl.lo[2], scale = cl.scale;
+    for (uint32_t i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) {
+        double v[3];
+        src.get3(i, v);
+        const uint32_t qx = coord_to_int(v[0], lx, scale);
+        const uint32_t qy = coord_to_int(v[1], ly, scale);
+        const uint32_t qz = coord_to_int(v[2], lz, scale);
+        key[i] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+        val[i] = i;
+    }
 }
 
 __global__ void __launch_bounds__(kBlock)
 reorder_from_caller_kernel(const double *__restrict__ pos, const double *__restrict__ mass,
-                           const uint32_t *__restrict__ perm, int64_t n, double4 *__restrict__ p4,
-                           double4 *__restrict__ v4, uint32_t *__restrict__ pid, DevMisc *m)
+                           const double *__restrict__ vel, const uint32_t *__restrict__ perm,
+                           int64_t n, double4 *__restrict__ p4, double4 *__restrict__ v4,
+                           uint32_t *__restrict__ pid, DevMisc *m)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const uint32_t s = perm[i];
+    const int64_t s = perm[i];
     const double ms = mass[s];
     if (!(ms > 0.0) || !isfinite(ms)) atomicOr(&m->nonfinite, 2u);
-    p4[i] = make_double4(pos[3 * (int64_t)s], pos[3 * (int64_t)s + 1], pos[3 * (int64_t)s + 2],
-                         ms);
-    v4[i] = make_double4(0.0, 0.0, 0.0, 0.0);
-    pid[i] = s;
+    p4[i] = make_double4(pos[3 * s], pos[3 * s + 1], pos[3 * s + 2], ms);
+    v4[i] = vel ? make_double4(vel[3 * s], vel[3 * s + 1], vel[3 * s + 2], 0.0)
+                : make_double4(0.0, 0.0, 0.0, 0.0);
+    pid[i] = (uint32_t)s;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -237,14 +252,15 @@ __device__ __forceinline__ uint8_t split_level(uint64_t a, uint64_t b)
 }
 
 // Per particle: split level, leaf level; per block and level: number of cells
-// starting in the block.  blk layout: [level][block].
+// starting in the block.  blk layout: [level][block].  H is the largest leaf size
+// of the batch (the halo); each particle uses its own cluster's leaf size.
 __global__ void __launch_bounds__(kTreeTile)
-split_leaf_kernel(const uint64_t *__restrict__ key, int64_t n, int nleaf, uint8_t *__restrict__ split,
+split_leaf_kernel(const uint64_t *__restrict__ key, const uint32_t *__restrict__ pcl, int64_t n,
+                  int H, const DevCluster *__restrict__ clus, uint8_t *__restrict__ split,
                   uint8_t *__restrict__ lam, uint32_t *__restrict__ blk, int nblk,
                   DevMisc *__restrict__ m)
 {
     extern __shared__ uint8_t s_dyn[];
-    const int H = nleaf;                          // halo on each side
     const int W = kTreeTile + 2 * H;              // split values held in LDS
     uint8_t *s_split = s_dyn;                     // [W]
     uint8_t *s_pl = s_dyn + ((W + 15) & ~15);     // [H][kTreeTile] left prefix minima
@@ -255,11 +271,12 @@ split_leaf_kernel(const uint64_t *__restrict__ key, int64_t n, int nleaf, uint8_
     const int64_t base = (int64_t)blockIdx.x * kTreeTile;
     if (t < kLevels) s_cnt[t] = 0;
     if (t == 0) s_leaves = 0;
-    // split of global index j, with the conventions split(0) = 0 and split(n) = 0
+    // split of global index j, with split = 0 at the first particle of a cluster
+    // and at n
     for (int u = t; u < W; u += kTreeTile) {
         int64_t j = base - H + u;
         uint8_t v;
-        if (j <= 0 || j >= n) v = 0;
+        if (j <= 0 || j >= n || pcl[j] != pcl[j - 1]) v = 0;
         else v = split_level(key[j - 1], key[j]);
         s_split[u] = v;
     }
@@ -269,22 +286,23 @@ split_leaf_kernel(const uint64_t *__restrict__ key, int64_t n, int nleaf, uint8_
     const bool valid = i < n;
     uint8_t sp = 0, lm = 0;
     if (valid) {
+        const int h = (int)clus[pcl[i]].nleaf;
         sp = s_split[H + t];
         // left prefix minima PL[a] = min split(i - a'), a' = 0..a
         uint8_t run = 255;
-        for (int a = 0; a < H; ++a) {
+        for (int a = 0; a < h; ++a) {
             uint8_t v = (i - a <= 0) ? (uint8_t)0 : s_split[H + t - a];
             run = v < run ? v : run;
             s_pl[a * kTreeTile + t] = run;
         }
         // right prefix minima PR[b] over split(i + b'), b' = 1..b, combined with
-        // PL[H - b]: lam = min_b max(PL[H - b], PR[b])
+        // PL[h - b]: leaf level = min_b max(PL[h - b], PR[b])
         uint8_t best = 255;
         run = 255;
-        for (int b = 1; b <= H; ++b) {
+        for (int b = 1; b <= h; ++b) {
             uint8_t v = (i + b >= n) ? (uint8_t)0 : s_split[H + t + b];
             run = v < run ? v : run;
-            uint8_t pl = s_pl[(H - b) * kTreeTile + t];
+            uint8_t pl = s_pl[(h - b) * kTreeTile + t];
             uint8_t mx = pl > run ? pl : run;
             best = mx < best ? mx : best;
         }
@@ -305,6 +323,31 @@ split_leaf_kernel(const uint64_t *__restrict__ key, int64_t n, int nleaf, uint8_
     __syncthreads();
     if (t < kLevels) blk[(int64_t)t * nblk + blockIdx.x] = s_cnt[t];
     if (t == 0 && s_leaves) atomicAdd(&m->nleaves, s_leaves);
+}
+
+// one block per level: exclusive scan of the level's block counts in place
+__global__ void scan_levels_kernel(uint32_t *__restrict__ blk, int nblk, uint32_t *__restrict__ tot)
+{
+    __shared__ uint32_t s_tmp[4];
+    uint32_t *row = blk + (int64_t)blockIdx.x * nblk;
+    uint32_t run = 0;
+    const int t = threadIdx.x, w = t / kWave, l = t % kWave;
+    for (int b0 = 0; b0 < nblk; b0 += 256) {
+        int b = b0 + t;
+        uint32_t v = b < nblk ? row[b] : 0u;
+        uint32_t inc = wave_incl_scan_add(v);
+        if (l == kWave - 1) s_tmp[w] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot4 = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (k < w) off += s_tmp[k];
+            tot4 += s_tmp[k];
+        }
+        __syncthreads();
+        if (b < nblk) row[b] = run + off + inc - v;
+        run += tot4;
+    }
+    if (t == 0) tot[blockIdx.x] = run;
 }
 
 // level counts -> level offsets (level-major order), total cells, depth.
@@ -337,7 +380,7 @@ struct Ranks {
     uint32_t anc[kLevels];
 };
 
-__device__ __forceinline__ void level_ranks(int64_t i, bool valid, uint8_t sp, uint8_t lm,
+__device__ __forceinline__ void level_ranks(bool valid, uint8_t sp, uint8_t lm,
                                             const uint32_t *__restrict__ blk_scanned, int nblk,
                                             const DevMisc *__restrict__ m, uint32_t (*s_wc)[kLevels],
                                             Ranks &r)
@@ -373,7 +416,7 @@ emit_cells_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__
     const uint8_t sp = valid ? split[i] : (uint8_t)255;
     const uint8_t lm = valid ? lam[i] : (uint8_t)0;
     Ranks r;
-    level_ranks(i, valid, sp, lm, blk_scanned, nblk, m, s_wc, r);
+    level_ranks(valid, sp, lm, blk_scanned, nblk, m, s_wc, r);
     if (!valid || sp > lm || m->ncells == 0) return;
 #pragma unroll
     for (int lev = 0; lev < kLevels; ++lev) {
@@ -392,7 +435,8 @@ emit_cells_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__
 // Cell ends (hence counts), numbers of children, and group starts.
 __global__ void __launch_bounds__(kTreeTile)
 cell_ends_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__ lam, int64_t n,
-                 int ncrit, const uint32_t *__restrict__ blk_scanned, int nblk,
+                 const uint32_t *__restrict__ pcl, const DevCluster *__restrict__ clus,
+                 const uint32_t *__restrict__ blk_scanned, int nblk,
                  const DevMisc *__restrict__ m, const uint32_t *__restrict__ c_first,
                  const uint32_t *__restrict__ c_parent, const uint32_t *__restrict__ c_child,
                  uint32_t *__restrict__ c_count, uint32_t *__restrict__ c_nchild,
@@ -404,8 +448,9 @@ cell_ends_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__ 
     const uint8_t sp = valid ? split[i] : (uint8_t)255;
     const uint8_t lm = valid ? lam[i] : (uint8_t)0;
     Ranks r;
-    level_ranks(i, valid, sp, lm, blk_scanned, nblk, m, s_wc, r);
+    level_ranks(valid, sp, lm, blk_scanned, nblk, m, s_wc, r);
     if (!valid || sp > lm || m->ncells == 0) return;
+    const uint32_t ncrit = clus[pcl[i]].ncrit;
     uint32_t e = (uint32_t)n;            // running end: min over shallower levels
     uint32_t prev_count = 0;             // count of the level above (the parent)
     bool grouped = false;
@@ -427,52 +472,57 @@ cell_ends_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__ 
                 if (last) c_nchild[p] = a - c_child[p] + 1u;
             }
             // group: at most ncrit particles and the parent holds more (or root)
-            if (!grouped && cnt <= (uint32_t)ncrit && (lev == 0 || prev_count > (uint32_t)ncrit)) {
+            if (!grouped && cnt <= ncrit && (lev == 0 || prev_count > ncrit)) {
                 gflag[i] = 1;
                 grouped = true;
             }
             // a leaf still larger than ncrit is cut into runs of ncrit particles
-            if (lev == lm && cnt > (uint32_t)ncrit) {
-                for (uint32_t o = 0; o < cnt; o += (uint32_t)ncrit) gflag[i + o] = 1;
+            if (lev == lm && cnt > ncrit) {
+                for (uint32_t o = 0; o < cnt; o += ncrit) gflag[i + o] = 1;
             }
         }
         prev_count = cnt;
     }
 }
 
-// group counts and tight boxes: one wavefront per group, lanes over particles
+// group counts and tight boxes: 16 lanes per group, grid-stride over the groups
+// counted on the device
 __global__ void __launch_bounds__(kBlock)
-group_boxes_kernel(const uint32_t *__restrict__ g_first, int64_t ngroups, int64_t n,
+group_boxes_kernel(const uint32_t *__restrict__ g_first, const DevMisc *__restrict__ m, int64_t n,
                    const double4 *__restrict__ p4, uint32_t *__restrict__ g_count,
                    double4 *__restrict__ g_centre, float4 *__restrict__ g_half)
 {
     constexpr int kSeg = 16;                       // lanes per group
-    const int64_t g = (int64_t)blockIdx.x * (kBlock / kSeg) + threadIdx.x / kSeg;
+    const int64_t ngroups = m->ngroups;
     const int l = threadIdx.x % kSeg;
-    const bool valid = g < ngroups;
-    const uint32_t s = valid ? g_first[g] : 0u;
-    const uint32_t e = valid ? ((g + 1 < ngroups) ? g_first[g + 1] : (uint32_t)n) : 0u;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (uint32_t j = s + l; j < e; j += kSeg) {
-        const double4 p = p4[j];
-        lo[0] = fmin(lo[0], p.x); hi[0] = fmax(hi[0], p.x);
-        lo[1] = fmin(lo[1], p.y); hi[1] = fmax(hi[1], p.y);
-        lo[2] = fmin(lo[2], p.z); hi[2] = fmax(hi[2], p.z);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-#pragma unroll
-        for (int d = kSeg / 2; d > 0; d >>= 1) {
-            lo[k] = fmin(lo[k], __shfl_xor(lo[k], d, kWave));
-            hi[k] = fmax(hi[k], __shfl_xor(hi[k], d, kWave));
+    for (int64_t g0 = (int64_t)blockIdx.x * (kBlock / kSeg); g0 < ngroups;
+         g0 += (int64_t)gridDim.x * (kBlock / kSeg)) {
+        const int64_t g = g0 + threadIdx.x / kSeg;
+        const bool valid = g < ngroups;
+        const uint32_t s = valid ? g_first[g] : 0u;
+        const uint32_t e = valid ? ((g + 1 < ngroups) ? g_first[g + 1] : (uint32_t)n) : 0u;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (uint32_t j = s + l; j < e; j += kSeg) {
+            const double4 p = p4[j];
+            lo[0] = fmin(lo[0], p.x); hi[0] = fmax(hi[0], p.x);
+            lo[1] = fmin(lo[1], p.y); hi[1] = fmax(hi[1], p.y);
+            lo[2] = fmin(lo[2], p.z); hi[2] = fmax(hi[2], p.z);
         }
-    }
-    if (valid && l == 0) {
-        g_count[g] = e - s;
-        g_centre[g] = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]),
-                                   0.5 * (lo[2] + hi[2]), 0.0);
-        g_half[g] = make_float4((float)(0.5 * (hi[0] - lo[0])), (float)(0.5 * (hi[1] - lo[1])),
-                                (float)(0.5 * (hi[2] - lo[2])), 0.0f);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int d = kSeg / 2; d > 0; d >>= 1) {
+                lo[k] = fmin(lo[k], __shfl_xor(lo[k], d, kWave));
+                hi[k] = fmax(hi[k], __shfl_xor(hi[k], d, kWave));
+            }
+        }
+        if (valid && l == 0) {
+            g_count[g] = e - s;
+            g_centre[g] = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]),
+                                       0.5 * (lo[2] + hi[2]), 0.0);
+            g_half[g] = make_float4((float)(0.5 * (hi[0] - lo[0])), (float)(0.5 * (hi[1] - lo[1])),
+                                    (float)(0.5 * (hi[2] - lo[2])), 0.0f);
+        }
     }
 }
 
@@ -491,111 +541,119 @@ __device__ __forceinline__ void store_walk_multipole(uint32_t c, const double *S
                         (float)(1.5 * tr));
 }
 
-// mode 0: the leaves among cells [begin, begin + count); mode 1: the nodes
-template <int kMode>
+// kLeaves: every leaf of the tree (any level); otherwise the nodes of one level.
+template <bool kLeaves>
 __global__ void __launch_bounds__(kBlock)
-moments_level_kernel(uint32_t begin, uint32_t count, const uint8_t *__restrict__ c_leaf,
-                     const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
-                     const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
-                     const double4 *__restrict__ p4, double4 *__restrict__ c_com,
-                     double *__restrict__ c_S, float4 *__restrict__ q0, float4 *__restrict__ q1)
+moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restrict__ c_leaf,
+               const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
+               const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
+               const double4 *__restrict__ p4, double4 *__restrict__ c_com,
+               double *__restrict__ c_S, float4 *__restrict__ q0, float4 *__restrict__ q1)
 {
-    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= count) return;
-    const uint32_t c = begin + t;
-    const bool leaf = c_leaf[c] != 0;
-    if (leaf != (kMode == 0)) return;
-    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-    double S[6] = {0, 0, 0, 0, 0, 0};
-    double cx, cy, cz;
-    if (leaf) {
-        const uint32_t s = c_first[c], e = s + c_count[c];
-        for (uint32_t j = s; j < e; ++j) M = M + p4[j].w;
-        for (uint32_t j = s; j < e; ++j) {
-            const double4 p = p4[j];
-            sx = sx + p.w * p.x;
-            sy = sy + p.w * p.y;
-            sz = sz + p.w * p.z;
+    const uint32_t begin = kLeaves ? 0u : m->level_offset[level];
+    const uint32_t count = kLeaves ? m->ncells : m->level_count[level];
+    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < count; t += gridDim.x * kBlock) {
+        const uint32_t c = begin + t;
+        const bool leaf = c_leaf[c] != 0;
+        if (leaf != kLeaves) continue;
+        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        double S[6] = {0, 0, 0, 0, 0, 0};
+        double cx, cy, cz;
+        if (kLeaves) {
+            const uint32_t s = c_first[c], e = s + c_count[c];
+            for (uint32_t j = s; j < e; ++j) M = M + p4[j].w;
+            for (uint32_t j = s; j < e; ++j) {
+                const double4 p = p4[j];
+                sx = sx + p.w * p.x;
+                sy = sy + p.w * p.y;
+                sz = sz + p.w * p.z;
+            }
+            cx = sx / M;
+            cy = sy / M;
+            cz = sz / M;
+            for (uint32_t j = s; j < e; ++j) {
+                const double4 p = p4[j];
+                const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+                S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
+                S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
+            }
+        } else {
+            const uint32_t s = c_child[c], e = s + c_nchild[c];
+            for (uint32_t k = s; k < e; ++k) M = M + c_com[k].w;
+            for (uint32_t k = s; k < e; ++k) {
+                const double4 q = c_com[k];
+                sx = sx + q.w * q.x;
+                sy = sy + q.w * q.y;
+                sz = sz + q.w * q.z;
+            }
+            cx = sx / M;
+            cy = sy / M;
+            cz = sz / M;
+            for (uint32_t k = s; k < e; ++k) {
+                const double4 q = c_com[k];
+                const double ex = q.x - cx, ey = q.y - cy, ez = q.z - cz;
+                const double *Sk = c_S + 6 * (int64_t)k;
+                S[0] += Sk[0] + q.w * ex * ex; S[1] += Sk[1] + q.w * ey * ey;
+                S[2] += Sk[2] + q.w * ez * ez; S[3] += Sk[3] + q.w * ex * ey;
+                S[4] += Sk[4] + q.w * ex * ez; S[5] += Sk[5] + q.w * ey * ez;
+            }
         }
-        cx = sx / M;
-        cy = sy / M;
-        cz = sz / M;
-        for (uint32_t j = s; j < e; ++j) {
-            const double4 p = p4[j];
-            const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
-            S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
-            S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
-        }
-    } else {
-        const uint32_t s = c_child[c], e = s + c_nchild[c];
-        for (uint32_t k = s; k < e; ++k) M = M + c_com[k].w;
-        for (uint32_t k = s; k < e; ++k) {
-            const double4 q = c_com[k];
-            sx = sx + q.w * q.x;
-            sy = sy + q.w * q.y;
-            sz = sz + q.w * q.z;
-        }
-        cx = sx / M;
-        cy = sy / M;
-        cz = sz / M;
-        for (uint32_t k = s; k < e; ++k) {
-            const double4 q = c_com[k];
-            const double ex = q.x - cx, ey = q.y - cy, ez = q.z - cz;
-            const double *Sk = c_S + 6 * (int64_t)k;
-            S[0] += Sk[0] + q.w * ex * ex; S[1] += Sk[1] + q.w * ey * ey;
-            S[2] += Sk[2] + q.w * ez * ez; S[3] += Sk[3] + q.w * ex * ey;
-            S[4] += Sk[4] + q.w * ex * ez; S[5] += Sk[5] + q.w * ey * ez;
-        }
-    }
-    c_com[c] = make_double4(cx, cy, cz, M);
+        c_com[c] = make_double4(cx, cy, cz, M);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)c + k] = S[k];
-    store_walk_multipole(c, S, q0, q1);
+        for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)c + k] = S[k];
+        store_walk_multipole(c, S, q0, q1);
+    }
 }
 
 // Eq. (1): r_crit = l/theta + delta with l = L 2^-level and delta the distance of
 // the centre of mass from the cell's geometric centre; stored as float32 r_crit^2,
-// together with the rest of the cell's walk record.
+// together with the rest of the cell's walk record.  theta and the domain are
+// those of the cell's cluster.
 __global__ void __launch_bounds__(kBlock)
-rcrit_kernel(int64_t ncells, float theta, const DevMisc *__restrict__ m,
-             const uint8_t *__restrict__ c_level, const uint32_t *__restrict__ c_first,
-             const uint32_t *__restrict__ c_count, const uint32_t *__restrict__ c_child,
-             const uint32_t *__restrict__ c_nchild, const uint8_t *__restrict__ c_leaf,
-             const uint64_t *__restrict__ skey, const double4 *__restrict__ c_com,
-             const float4 *__restrict__ q0, const float4 *__restrict__ q1,
-             float *__restrict__ rcrit2, WalkCell *__restrict__ rec)
+rcrit_kernel(const DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
+             const DevDomain *__restrict__ dom, const uint32_t *__restrict__ pcl, const uint8_t *__restrict__ c_level,
+             const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
+             const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
+             const uint8_t *__restrict__ c_leaf, const uint64_t *__restrict__ skey,
+             const double4 *__restrict__ c_com, const float4 *__restrict__ q0,
+             const float4 *__restrict__ q1, float *__restrict__ rcrit2, WalkCell *__restrict__ rec)
 {
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= ncells) return;
-    const int lev = c_level[c];
-    const double l = ldexp(m->L, -lev);
-    const uint64_t pre = skey[c_first[c]] >> (3 * (kMaxLevel - lev));
-    const double gx = m->lo[0] + ((double)compact3(pre) + 0.5) * l;
-    const double gy = m->lo[1] + ((double)compact3(pre >> 1) + 0.5) * l;
-    const double gz = m->lo[2] + ((double)compact3(pre >> 2) + 0.5) * l;
-    const double4 cm = c_com[c];
-    const double dx = cm.x - gx, dy = cm.y - gy, dz = cm.z - gz;
-    const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
-    const double r = l / (double)theta + delta;
-    const float r2 = (float)(r * r);
-    rcrit2[c] = r2;
-    const bool leaf = c_leaf[c] != 0;
-    const float4 a = q0[c], b = q1[c];
-    WalkCell w;
-    w.cx = cm.x;
-    w.cy = cm.y;
-    w.cz = cm.z;
-    w.mass = (float)cm.w;
-    w.rcrit2 = r2;
-    w.link = leaf ? c_first[c] : c_child[c];
-    w.info = leaf ? (c_count[c] | 0x80000000u) : c_nchild[c];
-    w.s3[0] = a.x;
-    w.s3[1] = a.y;
-    w.s3[2] = a.z;
-    w.s3[3] = a.w;
-    w.s3[4] = b.x;
-    w.s3[5] = b.y;
-    rec[c] = w;
+    const uint32_t ncells = m->ncells;
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < ncells; c += gridDim.x * kBlock) {
+        const uint32_t f = c_first[c];
+        const uint32_t k = pcl[f];
+        const DevDomain &cl = dom[k];
+        const float theta = clus[k].theta;
+        const int lev = c_level[c];
+        const double l = ldexp(cl.L, -lev);
+        const uint64_t pre = skey[f] >> (3 * (kMaxLevel - lev));
+        const double gx = cl.lo[0] + ((double)compact3(pre) + 0.5) * l;
+        const double gy = cl.lo[1] + ((double)compact3(pre >> 1) + 0.5) * l;
+        const double gz = cl.lo[2] + ((double)compact3(pre >> 2) + 0.5) * l;
+        const double4 cm = c_com[c];
+        const double dx = cm.x - gx, dy = cm.y - gy, dz = cm.z - gz;
+        const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
+        const double r = l / (double)theta + delta;
+        const float r2 = (float)(r * r);
+        rcrit2[c] = r2;
+        const bool leaf = c_leaf[c] != 0;
+        const float4 a = q0[c], b = q1[c];
+        WalkCell w;
+        w.cx = cm.x;
+        w.cy = cm.y;
+        w.cz = cm.z;
+        w.mass = (float)cm.w;
+        w.rcrit2 = r2;
+        w.link = leaf ? f : c_child[c];
+        w.info = leaf ? (c_count[c] | 0x80000000u) : c_nchild[c];
+        w.s3[0] = a.x;
+        w.s3[1] = a.y;
+        w.s3[2] = a.z;
+        w.s3[3] = a.w;
+        w.s3[4] = b.x;
+        w.s3[5] = b.y;
+        rec[c] = w;
+    }
 }
 
 __global__ void fill_u8_kernel(uint8_t *p, int64_t n)
@@ -605,97 +663,78 @@ __global__ void fill_u8_kernel(uint8_t *p, int64_t n)
         p[i] = 0;
 }
 
-__global__ void scan_levels_kernel(uint32_t *__restrict__ blk, int nblk, uint32_t *__restrict__ tot)
-{
-    // one block per level: exclusive scan of the level's block counts in place
-    __shared__ uint32_t s_tmp[4];
-    uint32_t *row = blk + (int64_t)blockIdx.x * nblk;
-    uint32_t run = 0;
-    const int t = threadIdx.x, w = t / kWave, l = t % kWave;
-    for (int b0 = 0; b0 < nblk; b0 += 256) {
-        int b = b0 + t;
-        uint32_t v = b < nblk ? row[b] : 0u;
-        uint32_t inc = wave_incl_scan_add(v);
-        if (l == kWave - 1) s_tmp[w] = inc;
-        __syncthreads();
-        uint32_t off = 0, tot4 = 0;
-        for (int k = 0; k < 4; ++k) {
-            if (k < w) off += s_tmp[k];
-            tot4 += s_tmp[k];
-        }
-        __syncthreads();
-        if (b < nblk) row[b] = run + off + inc - v;
-        run += tot4;
-    }
-    if (t == 0) tot[blockIdx.x] = run;
-}
-
-inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
 
-hipError_t launch_bbox(bh_ctx *c, const double *pos_aos, int64_t n)
+hipError_t launch_cluster_ids(bh_ctx *c)
 {
-    hipLaunchKernelGGL(misc_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
-    BH_LAUNCH_CHECK();
-    int grid = grid_for(n, kBlock);
-    if (grid > kBBoxBlocks) grid = kBBoxBlocks;
-    if (pos_aos)
-        hipLaunchKernelGGL(bbox_kernel<AosSrc>, dim3(grid), dim3(kBlock), 0, c->stream,
-                           AosSrc{pos_aos}, n, c->bb_part, c->misc);
-    else
-        hipLaunchKernelGGL(bbox_kernel<P4Src>, dim3(grid), dim3(kBlock), 0, c->stream,
-                           P4Src{c->p4[c->cur]}, n, c->bb_part, c->misc);
-    BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(domain_kernel, dim3(1), dim3(kBlock), 0, c->stream, c->bb_part, grid,
-                       c->misc);
+    hipLaunchKernelGGL(cluster_ids_kernel, dim3((unsigned)c->nchunks), dim3(kBlock), 0, c->stream,
+                       c->chunks, c->pcl);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_keys(bh_ctx *c, const double *pos_aos, int64_t n)
+hipError_t launch_domain(bh_ctx *c, const double *pos_aos)
+{
+    hipLaunchKernelGGL(misc_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
+    BH_LAUNCH_CHECK();
+    if (pos_aos)
+        hipLaunchKernelGGL(bbox_kernel<AosSrc>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
+                           c->stream, AosSrc{pos_aos}, c->chunks, c->bb_part, c->misc);
+    else
+        hipLaunchKernelGGL(bbox_kernel<P4Src>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
+                           c->stream, P4Src{c->p4[c->cur]}, c->chunks, c->bb_part, c->misc);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(domain_kernel, dim3(grid_for(c->K, kBlock)), dim3(kBlock), 0, c->stream,
+                       c->bb_part, c->clus, c->dom, c->K);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_keys(bh_ctx *c, const double *pos_aos)
 {
     if (pos_aos)
-        hipLaunchKernelGGL(keys_kernel<AosSrc>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
-                           c->stream, AosSrc{pos_aos}, n, c->misc, c->key[0], c->val[0]);
+        hipLaunchKernelGGL(keys_kernel<AosSrc>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
+                           c->stream, AosSrc{pos_aos}, c->chunks, c->dom, c->key[0], c->val[0]);
     else
-        hipLaunchKernelGGL(keys_kernel<P4Src>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
-                           c->stream, P4Src{c->p4[c->cur]}, n, c->misc, c->key[0], c->val[0]);
+        hipLaunchKernelGGL(keys_kernel<P4Src>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
+                           c->stream, P4Src{c->p4[c->cur]}, c->chunks, c->dom, c->key[0],
+                           c->val[0]);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_reorder_from_caller(bh_ctx *c, const double *pos_aos, const double *mass,
-                                      const uint32_t *perm, int64_t n)
+                                      const double *vel, const uint32_t *perm)
 {
-    hipLaunchKernelGGL(reorder_from_caller_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
-                       c->stream, pos_aos, mass, perm, n, c->p4[c->cur], c->v4[c->cur],
+    hipLaunchKernelGGL(reorder_from_caller_kernel, dim3(grid_for(c->n, kBlock)), dim3(kBlock), 0,
+                       c->stream, pos_aos, mass, vel, perm, c->n, c->p4[c->cur], c->v4[c->cur],
                        c->pid[c->cur], c->misc);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_reorder(bh_ctx *c, const uint32_t *perm, int64_t n)
+hipError_t launch_reorder(bh_ctx *c, const uint32_t *perm)
 {
     const int s = c->cur, d = c->cur ^ 1;
-    hipLaunchKernelGGL(reorder_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, c->stream,
-                       c->p4[s], c->v4[s], c->pid[s], perm, n, c->p4[d], c->v4[d], c->pid[d]);
+    hipLaunchKernelGGL(reorder_kernel, dim3(grid_for(c->n, kBlock)), dim3(kBlock), 0, c->stream,
+                       c->p4[s], c->v4[s], c->pid[s], perm, c->n, c->p4[d], c->v4[d], c->pid[d]);
     BH_LAUNCH_CHECK();
     c->cur = d;
     return hipSuccess;
 }
 
-hipError_t launch_tree(bh_ctx *c, int64_t n)
+hipError_t launch_tree(bh_ctx *c)
 {
+    const int64_t n = c->n;
     const int nblk = grid_for(n, kTreeTile);
     uint32_t *blk = c->blk;                       // [kLevels][nblk]
     uint32_t *tot = c->blk + (int64_t)kLevels * nblk;
-    const int H = c->p.nleaf;
+    const int H = c->max_nleaf;
     const size_t lds = (size_t)((kTreeTile + 2 * H + 15) & ~15) + (size_t)kTreeTile * H;
     hipLaunchKernelGGL(split_leaf_kernel, dim3(nblk), dim3(kTreeTile), lds, c->stream, c->key[0],
-                       n, H, c->split, c->lam, blk, nblk, c->misc);
+                       c->pcl, n, H, c->clus, c->split, c->lam, blk, nblk, c->misc);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(scan_levels_kernel, dim3(kLevels), dim3(256), 0, c->stream, blk, nblk, tot);
     BH_LAUNCH_CHECK();
@@ -711,55 +750,54 @@ hipError_t launch_tree(bh_ctx *c, int64_t n)
     hipLaunchKernelGGL(fill_u8_kernel, dim3(fg), dim3(256), 0, c->stream, c->gflag, n);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(cell_ends_kernel, dim3(nblk), dim3(kTreeTile), 0, c->stream, c->split,
-                       c->lam, n, c->p.ncrit, blk, nblk, c->misc, c->c_first, c->c_parent,
+                       c->lam, n, c->pcl, c->clus, blk, nblk, c->misc, c->c_first, c->c_parent,
                        c->c_child, c->c_count, c->c_nchild, c->gflag);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_groups(bh_ctx *c, int64_t n)
+hipError_t launch_groups(bh_ctx *c)
 {
-    return compact_flags(c, c->gflag, n, c->g_first, &c->misc->ngroups);
+    return compact_flags(c, c->gflag, c->n, c->g_first, &c->misc->ngroups);
 }
 
-hipError_t launch_group_boxes(bh_ctx *c, int64_t ngroups)
+hipError_t launch_group_boxes(bh_ctx *c)
 {
-    if (ngroups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(group_boxes_kernel, dim3(grid_for(ngroups, kBlock / 16)), dim3(kBlock), 0,
-                       c->stream, c->g_first, ngroups, c->n, c->p4[c->cur], c->g_count,
-                       c->g_centre, c->g_half);
+    int g = grid_for(c->n, kBlock / 16);
+    if (g > kFixedGrid) g = kFixedGrid;
+    hipLaunchKernelGGL(group_boxes_kernel, dim3(g), dim3(kBlock), 0, c->stream, c->g_first, c->misc,
+                       c->n, c->p4[c->cur], c->g_count, c->g_centre, c->g_half);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_moments(bh_ctx *c, int64_t ncells)
+hipError_t launch_moments(bh_ctx *c)
 {
-    // level counts were read back with the tree; deepest level first
-    const DevMisc &m = *c->misc_h;
+    int g = grid_for(c->cap_c, kBlock);
+    if (g > kFixedGrid) g = kFixedGrid;
     // every leaf, whatever its level, from its particles
-    hipLaunchKernelGGL(moments_level_kernel<0>, dim3(grid_for(ncells, kBlock)), dim3(kBlock), 0,
-                       c->stream, 0u, (uint32_t)ncells, c->c_leaf, c->c_first, c->c_count,
-                       c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
+    hipLaunchKernelGGL(moments_kernel<true>, dim3(g), dim3(kBlock), 0, c->stream, 0, c->misc,
+                       c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild, c->p4[c->cur],
+                       c->c_com, c->c_S, c->c_q0, c->c_q1);
     BH_LAUNCH_CHECK();
-    // nodes from their children, deepest level first (the deepest level holds only leaves)
-    for (int lev = (int)m.depth - 1; lev >= 0; --lev) {
-        const uint32_t cnt = m.level_count[lev];
-        if (!cnt) continue;
-        hipLaunchKernelGGL(moments_level_kernel<1>, dim3(grid_for(cnt, kBlock)), dim3(kBlock), 0,
-                           c->stream, m.level_offset[lev], cnt, c->c_leaf, c->c_first, c->c_count,
-                           c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0,
-                           c->c_q1);
+    // nodes from their children, deepest level first (level 20 holds only leaves);
+    // levels below the tree's depth have no cells and return at once
+    for (int lev = kMaxLevel - 1; lev >= 0; --lev) {
+        hipLaunchKernelGGL(moments_kernel<false>, dim3(g), dim3(kBlock), 0, c->stream, lev,
+                           c->misc, c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild,
+                           c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
         BH_LAUNCH_CHECK();
     }
     return hipSuccess;
 }
 
-hipError_t launch_rcrit(bh_ctx *c, int64_t ncells, float theta)
+hipError_t launch_rcrit(bh_ctx *c)
 {
-    hipLaunchKernelGGL(rcrit_kernel, dim3(grid_for(ncells, kBlock)), dim3(kBlock), 0, c->stream,
-                       ncells, theta, c->misc, c->c_level, c->c_first, c->c_count, c->c_child,
-                       c->c_nchild, c->c_leaf, c->key[0], c->c_com, c->c_q0, c->c_q1,
-                       c->c_rcrit2, c->c_rec);
+    int g = grid_for(c->cap_c, kBlock);
+    if (g > kFixedGrid) g = kFixedGrid;
+    hipLaunchKernelGGL(rcrit_kernel, dim3(g), dim3(kBlock), 0, c->stream, c->misc, c->clus, c->dom,
+                       c->pcl, c->c_level, c->c_first, c->c_count, c->c_child, c->c_nchild, c->c_leaf,
+                       c->key[0], c->c_com, c->c_q0, c->c_q1, c->c_rcrit2, c->c_rec);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

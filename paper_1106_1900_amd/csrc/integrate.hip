@@ -13,11 +13,14 @@ constexpr int kRedBlocks = 1024;
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// v += a h with h = dt / 2 of the particle's cluster
 __global__ void __launch_bounds__(kBlock)
-kick_kernel(int64_t n, const float4 *__restrict__ acc4, double4 *__restrict__ v4, double h)
+kick_kernel(int64_t n, const uint32_t *__restrict__ pcl, const DevCluster *__restrict__ clus,
+            const float4 *__restrict__ acc4, double4 *__restrict__ v4)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
+    const double h = 0.5 * clus[pcl[i]].dt;
     const float4 a = acc4[i];
     double4 v = v4[i];
     v.x = v.x + (double)a.x * h;
@@ -28,11 +31,14 @@ kick_kernel(int64_t n, const float4 *__restrict__ acc4, double4 *__restrict__ v4
 
 // v += a h; x += v dt in one pass (the first half of a kick-drift-kick step)
 __global__ void __launch_bounds__(kBlock)
-kick_drift_kernel(int64_t n, const float4 *__restrict__ acc4, double4 *__restrict__ v4,
-                  double4 *__restrict__ p4, double h, double dt)
+kick_drift_kernel(int64_t n, const uint32_t *__restrict__ pcl, const DevCluster *__restrict__ clus,
+                  const float4 *__restrict__ acc4, double4 *__restrict__ v4,
+                  double4 *__restrict__ p4)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
+    const double dt = clus[pcl[i]].dt;
+    const double h = 0.5 * dt;
     const float4 a = acc4[i];
     double4 v = v4[i];
     v.x = v.x + (double)a.x * h;
@@ -46,28 +52,16 @@ kick_drift_kernel(int64_t n, const float4 *__restrict__ acc4, double4 *__restric
     p4[i] = p;
 }
 
+// Per chunk: T, W, Px, Py, Pz partial sums (fixed order: strided per thread,
+// then a tree over the block); part[5 chunk + k].
 __global__ void __launch_bounds__(kBlock)
-drift_kernel(int64_t n, const double4 *__restrict__ v4, double4 *__restrict__ p4, double dt)
+energy_partial_kernel(const Chunk *__restrict__ chunks, const double4 *__restrict__ p4,
+                      const double4 *__restrict__ v4, const float4 *__restrict__ acc4,
+                      double *__restrict__ part)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const double4 v = v4[i];
-    double4 p = p4[i];
-    p.x = p.x + v.x * dt;
-    p.y = p.y + v.y * dt;
-    p.z = p.z + v.z * dt;
-    p4[i] = p;
-}
-
-// Block partial sums of T, W, Px, Py, Pz over a grid-stride range (fixed order),
-// then one block adds the partials in block order.
-__global__ void __launch_bounds__(kBlock)
-energy_partial_kernel(int64_t n, const double4 *__restrict__ p4, const double4 *__restrict__ v4,
-                      const float4 *__restrict__ acc4, double *__restrict__ part)
-{
+    const Chunk ch = chunks[blockIdx.x];
     double s[5] = {0, 0, 0, 0, 0};
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    for (uint32_t i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) {
         const double m = p4[i].w;
         const double4 v = v4[i];
         s[0] += 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
@@ -87,28 +81,24 @@ energy_partial_kernel(int64_t n, const double4 *__restrict__ p4, const double4 *
         }
         __syncthreads();
     }
-    if (threadIdx.x < 5) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < 5) part[5 * (int64_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// Fixed-order sum of the block partials: strided per thread, then a tree.
+// One thread per cluster: its chunk partials in chunk order; out[5 cluster + k].
 __global__ void __launch_bounds__(kBlock)
-energy_final_kernel(const double *__restrict__ part, int nblk, double *__restrict__ out)
+energy_final_kernel(const DevCluster *__restrict__ clus, int64_t K, const double *__restrict__ part,
+                    double *__restrict__ out)
 {
-    __shared__ double sh[5][kBlock];
-    for (int k = 0; k < 5; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += kBlock) s += part[(int64_t)k * nblk + b];
-        sh[k][threadIdx.x] = s;
-    }
-    __syncthreads();
-    for (int d = kBlock / 2; d > 0; d >>= 1) {
-        if ((int)threadIdx.x < d) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= K) return;
+    const DevCluster &cl = clus[c];
+    double s[5] = {0, 0, 0, 0, 0};
+    for (uint32_t b = cl.chunk0; b < cl.chunk0 + cl.nchunk; ++b) {
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + d];
-        }
-        __syncthreads();
+        for (int k = 0; k < 5; ++k) s[k] += part[5 * (int64_t)b + k];
     }
-    if (threadIdx.x < 5) out[threadIdx.x] = sh[threadIdx.x][0];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) out[5 * c + k] = s[k];
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -158,44 +148,32 @@ state_out_kernel(int64_t n, const double4 *__restrict__ p4, const double4 *__res
 
 }  // namespace
 
-hipError_t launch_kick(bh_ctx *c, double h)
+hipError_t launch_kick(bh_ctx *c)
 {
-    hipLaunchKernelGGL(kick_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n, c->acc4,
-                       c->v4[c->cur], h);
+    hipLaunchKernelGGL(kick_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n, c->pcl,
+                       c->clus, c->acc4, c->v4[c->cur]);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_kick_drift(bh_ctx *c, double h, double dt)
+hipError_t launch_kick_drift(bh_ctx *c)
 {
     hipLaunchKernelGGL(kick_drift_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
-                       c->acc4, c->v4[c->cur], c->p4[c->cur], h, dt);
-    BH_LAUNCH_CHECK();
-    return hipSuccess;
-}
-
-hipError_t launch_drift(bh_ctx *c, double dt)
-{
-    hipLaunchKernelGGL(drift_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
-                       c->v4[c->cur], c->p4[c->cur], dt);
+                       c->pcl, c->clus, c->acc4, c->v4[c->cur], c->p4[c->cur]);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_energy(bh_ctx *c)
 {
-    int nblk = (int)grid_for(c->n);
-    if (nblk > kRedBlocks) nblk = kRedBlocks;
-    hipLaunchKernelGGL(energy_partial_kernel, dim3(nblk), dim3(kBlock), 0, c->stream, c->n,
-                       c->p4[c->cur], c->v4[c->cur], c->acc4, c->red);
+    hipLaunchKernelGGL(energy_partial_kernel, dim3((unsigned)c->nchunks), dim3(kBlock), 0, c->stream,
+                       c->chunks, c->p4[c->cur], c->v4[c->cur], c->acc4, c->e_part);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kBlock), 0, c->stream, c->red, nblk,
-                       c->red + 5 * kRedBlocks);
+    hipLaunchKernelGGL(energy_final_kernel, dim3(grid_for(c->K)), dim3(kBlock), 0, c->stream,
+                       c->clus, c->K, c->e_part, c->e_out);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
-
-int64_t energy_words() { return 5 * (int64_t)kRedBlocks + 8; }
 
 hipError_t launch_set_velocities(bh_ctx *c, const double *vel)
 {

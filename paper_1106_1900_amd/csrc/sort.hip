@@ -4,7 +4,10 @@
 //
 // The paper splits one bit per pass; here each pass places an 8-bit digit, which
 // is the same stable partition done for 256 buckets at once: 8 passes over the
-// 60-bit keys.  Each pass is reduce-then-scan (no inter-block waiting):
+// 60-bit keys.  For a batch of clusters, further stable passes on the cluster of
+// each element follow, so the keys end up sorted within each cluster and the
+// clusters keep their places.  Each pass is reduce-then-scan (no inter-block
+// waiting):
 //   1. hist:    per-block digit counts, stored digit-major;
 //   2. scan:    one block per digit scans that digit's counts over blocks;
 //   3. scatter: each block ranks its keys stably (wavefront match on the digit
@@ -15,9 +18,11 @@
 namespace bh {
 namespace {
 
-__device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift)
+// digit of an element: from its key, or (cl != NULL) from the cluster of the
+// position it came from
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t v, const uint32_t *cl, int shift)
 {
-    return (uint32_t)(k >> shift) & (kRadix - 1);
+    return cl ? ((cl[v] >> shift) & (kRadix - 1)) : ((uint32_t)(k >> shift) & (kRadix - 1));
 }
 
 // Exclusive scan of one value per thread over a 256-thread block.  Returns the
@@ -41,7 +46,8 @@ __device__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_tmp, uint32_t *t
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-hist_kernel(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t *__restrict__ hist,
+hist_kernel(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+            const uint32_t *__restrict__ cl, int64_t n, int shift, uint32_t *__restrict__ hist,
             int nblk)
 {
     __shared__ uint32_t cnt[kRadix];
@@ -52,7 +58,7 @@ hist_kernel(const uint64_t *__restrict__ keys, int64_t n, int shift, uint32_t *_
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         int64_t i = base + (int64_t)k * kSortThreads + t;
-        if (i < n) atomicAdd(&cnt[digit_of(keys[i], shift)], 1u);
+        if (i < n) atomicAdd(&cnt[digit_of(keys[i], cl ? vals[i] : 0u, cl, shift)], 1u);
     }
     __syncthreads();
     hist[(int64_t)t * nblk + blockIdx.x] = cnt[t];
@@ -78,7 +84,8 @@ scan_digit_kernel(uint32_t *__restrict__ hist, int nblk, uint32_t *__restrict__ 
 
 __global__ void __launch_bounds__(kSortThreads)
 scatter_kernel(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-               uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
+               uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+               const uint32_t *__restrict__ cl, int64_t n, int shift,
                const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot, int nblk)
 {
     __shared__ uint32_t s_wcnt[kSortThreads / kWave][kRadix];  // per-wave digit counts
@@ -113,7 +120,7 @@ scatter_kernel(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vi
         bool valid = p < tile_n;
         key[k] = valid ? kin[base + p] : 0ull;
         val[k] = valid ? vin[base + p] : 0u;
-        uint32_t d = digit_of(key[k], shift);
+        uint32_t d = valid ? digit_of(key[k], val[k], cl, shift) : 0u;
         unsigned long long peers = ballot(valid);
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
@@ -150,7 +157,7 @@ scatter_kernel(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vi
     for (int k = 0; k < kSortItems; ++k) {
         int p = wbase + k * kWave + l;
         if (p < tile_n) {
-            uint32_t d = digit_of(key[k], shift);
+            uint32_t d = digit_of(key[k], val[k], cl, shift);
             uint32_t lp = s_local[d] + s_wcnt[w][d] + rank[k];
             s_key[lp] = key[k];
             s_val[lp] = val[k];
@@ -160,10 +167,21 @@ scatter_kernel(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vi
 
     for (int p = t; p < tile_n; p += kSortThreads) {
         uint64_t k = s_key[p];
-        uint32_t d = digit_of(k, shift);
+        uint32_t d = digit_of(k, s_val[p], cl, shift);
         int64_t g = (int64_t)s_base[d] + hist[(int64_t)d * nblk + blockIdx.x] + (p - s_local[d]);
         kout[g] = k;
         vout[g] = s_val[p];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+copy_pairs_kernel(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                  uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        kout[i] = kin[i];
+        vout[i] = vin[i];
     }
 }
 
@@ -205,29 +223,6 @@ scan_partials_kernel(uint32_t *__restrict__ part, int nblk, uint32_t *__restrict
     if (threadIdx.x == 0 && total) *total = run;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kScanThreads)
-scan_down_kernel(const T *__restrict__ in, int64_t n, const uint32_t *__restrict__ part,
-                 uint32_t *__restrict__ out)
-{
-    __shared__ uint32_t s_tmp[4];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < n ? (uint32_t)in[base + k] : 0u;
-        s += v[k];
-    }
-    uint32_t sum;
-    uint32_t run = part[blockIdx.x] + block_excl_scan_256(s, s_tmp, &sum);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) out[base + k] = run;
-        run += v[k];
-    }
-}
-
 // Writes the positions of set flags, in order, to idx[0..count).
 __global__ void __launch_bounds__(kScanThreads)
 compact_down_kernel(const uint8_t *__restrict__ flags, int64_t n, const uint32_t *__restrict__ part,
@@ -252,42 +247,38 @@ compact_down_kernel(const uint8_t *__restrict__ flags, int64_t n, const uint32_t
 
 }  // namespace
 
-hipError_t radix_sort_pairs(bh_ctx *c, int64_t n)
+hipError_t radix_sort_pairs(bh_ctx *c)
 {
+    const int64_t n = c->n;
     const int nblk = (int)((n + kSortTile - 1) / kSortTile);
     uint32_t *hist = c->blk;                 // kRadix * nblk
     uint32_t *tot = c->blk + (int64_t)kRadix * nblk;
+    int cluster_passes = 0;
+    for (int64_t k = c->K - 1; k > 0; k >>= kRadixBits) ++cluster_passes;
+    const int passes = 8 + cluster_passes;
     int src = 0;
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = pass * kRadixBits;
+    for (int pass = 0; pass < passes; ++pass) {
+        const bool by_cluster = pass >= 8;
+        const int shift = by_cluster ? (pass - 8) * kRadixBits : pass * kRadixBits;
+        const uint32_t *cl = by_cluster ? c->pcl : nullptr;
         hipLaunchKernelGGL(hist_kernel, dim3(nblk), dim3(kSortThreads), 0, c->stream,
-                           c->key[src], n, shift, hist, nblk);
+                           c->key[src], c->val[src], cl, n, shift, hist, nblk);
         BH_LAUNCH_CHECK();
         hipLaunchKernelGGL(scan_digit_kernel, dim3(kRadix), dim3(256), 0, c->stream, hist, nblk,
                            tot);
         BH_LAUNCH_CHECK();
         hipLaunchKernelGGL(scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, c->stream,
-                           c->key[src], c->val[src], c->key[src ^ 1], c->val[src ^ 1], n, shift,
+                           c->key[src], c->val[src], c->key[src ^ 1], c->val[src ^ 1], cl, n, shift,
                            hist, tot, nblk);
         BH_LAUNCH_CHECK();
         src ^= 1;
     }
-    return hipSuccess;  // 8 passes: result back in key[0]/val[0]
-}
-
-hipError_t exclusive_scan_u32(bh_ctx *c, const uint32_t *in, uint32_t *out, int64_t n,
-                              uint32_t *total)
-{
-    const int nblk = (int)((n + kScanTile - 1) / kScanTile);
-    uint32_t *part = c->scan_tmp;
-    hipLaunchKernelGGL(scan_reduce_kernel<uint32_t>, dim3(nblk), dim3(kScanThreads), 0, c->stream,
-                       in, n, part);
-    BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(256), 0, c->stream, part, nblk, total);
-    BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(scan_down_kernel<uint32_t>, dim3(nblk), dim3(kScanThreads), 0, c->stream,
-                       in, n, part, out);
-    BH_LAUNCH_CHECK();
+    if (src != 0) {
+        // keep the result in buffer 0 whatever the number of passes
+        hipLaunchKernelGGL(copy_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           c->stream, c->key[1], c->val[1], c->key[0], c->val[0], n);
+        BH_LAUNCH_CHECK();
+    }
     return hipSuccess;
 }
 

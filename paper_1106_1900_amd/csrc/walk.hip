@@ -62,8 +62,8 @@ constexpr int kUnroll = BH_WALK_UNROLL;   // tile entries per loop trip
 #endif
 
 struct WalkArgs {
-    int64_t ngroups;
-    uint32_t ncells;
+    const uint32_t *pcl;      // cluster of each particle position
+    const DevCluster *clus;   // per-cluster softening
     const uint32_t *g_first;
     const uint32_t *g_count;
     const double4 *g_centre;
@@ -74,8 +74,7 @@ struct WalkArgs {
     uint32_t *g_npp;
     uint32_t *g_npc;
     uint32_t *spill;          // kSpillPerWave entries per wavefront of the grid
-    DevMisc *misc;
-    float eps2;
+    DevMisc *misc;            // group and cell counts, work counter, interaction totals
 };
 
 struct WaveLds {
@@ -293,9 +292,8 @@ __device__ __forceinline__ void run_pp(const WaveLds &L, int cnt, const Target &
 }
 
 // stage up to 64 cells of the cell list and evaluate them
-template <bool kEps0>
 __device__ __forceinline__ void eval_pc(const WalkArgs &a, WaveLds &L, const uint32_t *list, int cnt,
-                                        const double4 gc, const Target &t, Acc &acc)
+                                        const double4 gc, const Target &t, float eps2, Acc &acc)
 {
     const int lane = lane_id();
     if (lane < cnt) {
@@ -314,14 +312,16 @@ __device__ __forceinline__ void eval_pc(const WalkArgs &a, WaveLds &L, const uin
         L.tc[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     wave_sync();
-    if (t.sub < t.k) run_pc<kEps0>(L, cnt, t, a.eps2, acc);
+    if (t.sub < t.k) {
+        if (eps2 > 0.0f) run_pc<false>(L, cnt, t, eps2, acc);
+        else run_pc<true>(L, cnt, t, eps2, acc);
+    }
     wave_sync();
 }
 
 // stage up to 64 particles (lane j holds particle index idx) and evaluate them
-template <bool kEps0>
 __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t idx, int cnt,
-                                        const double4 gc, const Target &t, Acc &acc)
+                                        const double4 gc, const Target &t, float eps2, Acc &acc)
 {
     const int lane = lane_id();
     if (lane < cnt) {
@@ -331,23 +331,27 @@ __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t 
         L.ta[lane] = make_float4(kFar, kFar, kFar, 0.0f);
     }
     wave_sync();
-    if (t.sub < t.k) run_pp<kEps0>(L, cnt, t, a.eps2, acc);
+    if (t.sub < t.k) {
+        if (eps2 > 0.0f) run_pp<false>(L, cnt, t, eps2, acc);
+        else run_pp<true>(L, cnt, t, eps2, acc);
+    }
     wave_sync();
 }
 
 // next group from the device-wide counter (false when all are taken)
-__device__ __forceinline__ bool next_group(const WalkArgs &a, uint32_t &g)
+__device__ __forceinline__ bool next_group(const WalkArgs &a, uint32_t ngroups, uint32_t &g)
 {
     uint32_t v = 0;
     if (lane_id() == 0) v = atomicAdd(&a.misc->walk_next, 1u);
     g = readfirst(v);
-    return (int64_t)g < a.ngroups;
+    return g < ngroups;
 }
 
-template <bool kEps0>
 __global__ void __launch_bounds__(kWalkBlock)
 __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs a)
 {
+    const uint32_t ngroups = readfirst(a.misc->ngroups);
+    const uint32_t ncells = readfirst(a.misc->ncells);
     __shared__ WaveLds s_lds[kWalkWaves];
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -367,9 +371,12 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
     unsigned long long wave_pp = 0, wave_pc = 0;   // interaction totals of this wavefront
     bool wave_overflow = false;
     uint32_t g;
-    while (next_group(a, g)) {
+    while (next_group(a, ngroups, g)) {
         const uint32_t gs = a.g_first[g];
         const int gn = uniform((int)a.g_count[g]);
+        // the group's cluster: its root is the cluster's level-0 cell
+        const uint32_t cid = readfirst(a.pcl[gs]);
+        const float eps2 = a.clus[cid].eps2;
         const double4 gc = a.g_centre[g];
         const float4 gh = a.g_half[g];
         Target t;
@@ -388,7 +395,7 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
         Acc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
         int top = 1;
-        if (lane == 0) stack.set(0, 0u, 1u);   // the root
+        if (lane == 0) stack.set(0, cid, 1u);  // the cluster's root
         wave_sync();
         int pc_n = 0, pp_n = 0;
         uint32_t pend = 0, npp = 0, npc = 0;
@@ -397,13 +404,13 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
 
         while (top > 0) {
             // a correct tree visits each cell at most once per group
-            if (++iters > a.ncells + 1u) {
+            if (++iters > ncells + 1u) {
                 overflow = true;
                 break;
             }
             uint32_t cell;
             const int got = pop64(stack, top, L.mark, cell);
-            const bool has = lane < got && cell < a.ncells;
+            const bool has = lane < got && cell < ncells;
             bool acc_cell = false, leaf = false;
             uint32_t link = 0, info = 0;
             if (has) {
@@ -449,7 +456,7 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
             }
             stack.sync();
             while (pc_n >= kWave) {
-                eval_pc<kEps0>(a, L, L.pc + (pc_n - kWave), kWave, gc, t, acc);
+                eval_pc(a, L, L.pc + (pc_n - kWave), kWave, gc, t, eps2, acc);
                 pc_n -= kWave;
             }
             while (pend >= (uint32_t)kWave) {
@@ -460,12 +467,12 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
                     pend = 0;
                     break;
                 }
-                eval_pp<kEps0>(a, L, idx, n, gc, t, acc);
+                eval_pp(a, L, idx, n, gc, t, eps2, acc);
                 pend -= (uint32_t)n;
             }
             if (overflow) break;
         }
-        if (pc_n > 0) eval_pc<kEps0>(a, L, L.pc, pc_n, gc, t, acc);
+        if (pc_n > 0) eval_pc(a, L, L.pc, pc_n, gc, t, eps2, acc);
         while (pend > 0) {
             uint32_t idx;
             const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx) : 0;
@@ -473,7 +480,7 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
                 overflow = true;
                 break;
             }
-            eval_pp<kEps0>(a, L, idx, n, gc, t, acc);
+            eval_pp(a, L, idx, n, gc, t, eps2, acc);
             pend -= (uint32_t)n < pend ? (uint32_t)n : pend;
         }
 
@@ -499,7 +506,7 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
         if (t.sub == 0 && lane < gn) {
             // the particle met itself once in the particle list: with eps > 0 that
             // term added -m/eps to the potential and nothing to the acceleration
-            if (!kEps0) ph = ph + mi * __builtin_amdgcn_rsqf(a.eps2);
+            if (eps2 > 0.0f) ph = ph + mi * __builtin_amdgcn_rsqf(eps2);
             a.acc4[gs + lane] = make_float4(ax, ay, az, ph);
         }
         if (lane == 0) {
@@ -524,10 +531,15 @@ __global__ void walk_reset_kernel(DevMisc *m)
 {
     if (threadIdx.x == 0) {
         m->walk_next = 0;
-        m->walk_overflow = 0;
         m->sum_npp = 0;
         m->sum_npc = 0;
     }
+}
+
+__global__ void __launch_bounds__(256) zero_f4_kernel(int64_t n, float4 *__restrict__ p)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 __global__ void __launch_bounds__(256)
@@ -582,35 +594,30 @@ hipEvent_t *walk_timer_slot(bh_ctx *c)
     return &c->wev[2 * slot];
 }
 
-hipError_t launch_walk(bh_ctx *c, float theta, float eps)
+int64_t walk_spill_words(int64_t waves) { return waves * kSpillPerWave; }
+
+// wavefronts of the persistent walk grid
+int64_t walk_grid_waves(bh_ctx *c)
 {
-    (void)theta;
-    hipLaunchKernelGGL(walk_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
-    BH_LAUNCH_CHECK();
     int dev_cus = 256;
     if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
-        hipSuccess)
+        hipSuccess) {
+        (void)hipGetLastError();
         dev_cus = 256;
-    int64_t blocks = (int64_t)dev_cus * BH_WALK_BLOCKS_PER_CU;
-    const int64_t need = (c->ngroups + kWalkWaves - 1) / kWalkWaves;
-    if (blocks > need) blocks = need;
-    if (blocks < 1) blocks = 1;
-    const int64_t waves = blocks * kWalkWaves;
-    if (waves > c->walk_spill_waves) {
-        if (c->walk_spill) {
-            BH_HIP_TRY(hipStreamSynchronize(c->stream));
-            BH_HIP_TRY(hipFree(c->walk_spill));
-            c->bytes -= c->walk_spill_waves * kSpillPerWave * 4;
-            c->walk_spill = nullptr;
-            c->walk_spill_waves = 0;
-        }
-        BH_HIP_TRY(hipMalloc((void **)&c->walk_spill, (size_t)waves * kSpillPerWave * 4));
-        c->walk_spill_waves = waves;
-        c->bytes += waves * kSpillPerWave * 4;
     }
+    return (int64_t)dev_cus * BH_WALK_BLOCKS_PER_CU * kWalkWaves;
+}
+
+hipError_t launch_walk(bh_ctx *c, bool timed)
+{
+    hipLaunchKernelGGL(walk_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
+    BH_LAUNCH_CHECK();
+    int64_t blocks = walk_grid_waves(c) / kWalkWaves;
+    if (blocks * kWalkWaves > c->walk_spill_waves) blocks = c->walk_spill_waves / kWalkWaves;
+    if (blocks < 1) return hipErrorInvalidValue;
     WalkArgs a;
-    a.ngroups = c->ngroups;
-    a.ncells = (uint32_t)c->ncells;
+    a.pcl = c->pcl;
+    a.clus = c->clus;
     a.g_first = c->g_first;
     a.g_count = c->g_count;
     a.g_centre = c->g_centre;
@@ -622,15 +629,19 @@ hipError_t launch_walk(bh_ctx *c, float theta, float eps)
     a.g_npc = c->g_npc;
     a.spill = c->walk_spill;
     a.misc = c->misc;
-    a.eps2 = eps * eps;
-    hipEvent_t *ev = walk_timer_slot(c);
+    hipEvent_t *ev = timed ? walk_timer_slot(c) : nullptr;
     if (ev) BH_HIP_TRY(hipEventRecord(ev[0], c->stream));
-    if (a.eps2 > 0.0f)
-        hipLaunchKernelGGL(walk_kernel<false>, dim3((unsigned)blocks), dim3(kWalkBlock), 0, c->stream, a);
-    else
-        hipLaunchKernelGGL(walk_kernel<true>, dim3((unsigned)blocks), dim3(kWalkBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(walk_kernel, dim3((unsigned)blocks), dim3(kWalkBlock), 0, c->stream, a);
     BH_LAUNCH_CHECK();
     if (ev) BH_HIP_TRY(hipEventRecord(ev[1], c->stream));
+    return hipSuccess;
+}
+
+hipError_t launch_zero_acc(bh_ctx *c)
+{
+    hipLaunchKernelGGL(zero_f4_kernel, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, c->stream,
+                       c->n, c->acc4);
+    BH_LAUNCH_CHECK();
     return hipSuccess;
 }
 

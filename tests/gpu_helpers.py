@@ -87,3 +87,31 @@ def compare_forces(acc, pot, t, theta, eps, groups=None):
         med = float(np.median(da[nz] / na[nz]))
         assert med <= TOL_MEDIAN_REL, ("median relative", med)
     return float((da / np.maximum(aabs, 1e-300)).max())
+
+
+def split_forest(ex, sizes):
+    """Per-cluster views of a batch's exported forest: particle, cell and group
+    indices renumbered from 0 within each cluster (cells keep their relative
+    order, which is (level, key prefix) order within the cluster)."""
+    out = []
+    first = 0
+    for n in sizes:
+        lo, hi = first, first + n
+        cm = (ex["first"] >= lo) & (ex["first"] < hi)
+        idx = np.nonzero(cm)[0]
+        local = np.full(ex["first"].shape[0], -1, np.int64)
+        local[idx] = np.arange(idx.shape[0])
+        d = {"key": ex["key"][lo:hi], "perm": ex["perm"][lo:hi] - lo}
+        for k in ("level", "prefix", "count", "is_leaf", "nchild", "mass", "com", "S", "rcrit2"):
+            d[k] = ex[k][idx]
+        d["first"] = ex["first"][idx] - lo
+        for k in ("parent", "child"):
+            v = ex[k][idx]
+            d[k] = np.where(v < 0, -1, local[np.maximum(v, 0)])
+        gm = (ex["gfirst"] >= lo) & (ex["gfirst"] < hi)
+        d["gfirst"] = ex["gfirst"][gm] - lo
+        for k in ("gcount", "gcentre", "ghalf", "npp", "npc"):
+            d[k] = ex[k][gm]
+        out.append(d)
+        first = hi
+    return out

@@ -8,6 +8,12 @@ box, keys, radix sort, reorder, cells, groups, moments), opening radii, group wa
 kick, and the float64 energy/momentum sums.  Inputs are resident on the device
 before the timed region starts.  Prints one JSON line on stdout.
 
+The line also carries the batched form ("batch": 512 Plummer clusters of
+1024..65536 particles in one forest, one captured graph per step, against the same
+clusters stepped one context at a time) unless --no-batch is given, and the
+serving loop ("served": a Poisson trace of requests, each a force evaluation plus
+10 leapfrog steps, latency percentiles including queueing) unless --no-serve.
+
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 
@@ -124,6 +130,169 @@ def calib_copy():
     log("calib copy done: 1 GiB read + 1 GiB write per copy, 3 copies")
 
 
+def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4):
+    """Sum of N_i over a step of all k clusters, batched (one forest, graph replay)
+    against one context per cluster stepped in turn."""
+    import numpy as np
+    import torch
+
+    import paper_1106_1900_amd as bh
+    import workloads
+    log("generating %d clusters" % k)
+    cl = workloads.cluster_batch(k, seed)
+    ntot = int(sum(q["n"] for q in cl))
+    pos = torch.from_numpy(np.concatenate([q["pos"] for q in cl])).cuda()
+    vel = torch.from_numpy(np.concatenate([q["vel"] for q in cl])).cuda()
+    mass = torch.from_numpy(np.concatenate([q["mass"] for q in cl])).cuda()
+    table_in = [dict(n=q["n"], theta=q["theta"], eps=q["eps"], dt=dt) for q in cl]
+    ctx = bh.Context()
+    ctx.batch_build(table_in, pos, mass, vel)
+    ctx.batch_forces(want=False)
+    ctx.batch_run(warmup)
+    ctx.batch_energy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.batch_run(steps)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    en = ctx.batch_energy()
+    st = ctx.stats()
+
+    # leaf and group sizes tuned per class (floor(log2 N), theta), then the same
+    # clusters reloaded with the tuned sizes and timed again
+    log("autotuning leaf and group sizes")
+    tt0 = time.perf_counter()
+    table = ctx.autotune(reps=3)
+    t_tune = time.perf_counter() - tt0
+    tuned = [dict(q, nleaf=0, ncrit=0) for q in table_in]
+    ctx.batch_build(tuned, pos, mass, vel)
+    ctx.batch_forces(want=False)
+    ctx.batch_run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.batch_run(steps)
+    torch.cuda.synchronize()
+    t_tuned = (time.perf_counter() - t0) / steps
+    ctx.close()
+
+    log("stepping the %d clusters one context at a time" % k)
+    ones = []
+    first = 0
+    for q in cl:
+        n = q["n"]
+        c1 = bh.Context()
+        c1.build_tree(pos[first:first + n], mass[first:first + n])
+        c1.set_velocities(vel[first:first + n].contiguous())
+        c1.compute_forces(q["theta"], q["eps"], want=False)
+        ones.append(c1)
+        first += n
+    for _ in range(warmup):
+        for c1 in ones:
+            c1.leapfrog_step(dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c1 in ones:
+            c1.leapfrog_step(dt)
+    torch.cuda.synchronize()
+    t_one = (time.perf_counter() - t0) / steps
+    for c1 in ones:
+        c1.close()
+    return {
+        "workload": "%d Plummer clusters, N log-uniform in [1024, 65536] (sum %d), theta 0.75, "
+                    "eps 0.04 N^-1/3, dt %g, nleaf 16, group 64" % (k, ntot, dt),
+        "clusters": k, "particles": ntot, "steps": steps,
+        "value": ntot / t_batch, "unit": "particles/s",
+        "ms_per_step": 1e3 * t_batch,
+        "one_at_a_time_particles_per_s": ntot / t_one,
+        "one_at_a_time_ms_per_step": 1e3 * t_one,
+        "speedup_vs_one_at_a_time": t_one / t_batch,
+        "max_abs_energy_error": float(np.abs(en[:, 6]).max()),
+        "graph_launches": int(st.graph_launches),
+        "tuned_value": ntot / t_tuned,
+        "tuned_ms_per_step": 1e3 * t_tuned,
+        "autotune_seconds": t_tune,
+        "tuning": [{"log2n": t["log2n"], "theta": round(t["theta"], 6), "nleaf": t["nleaf"],
+                    "ncrit": t["ncrit"], "ms": round(t["ms"], 4),
+                    "ms_default": round(t["ms_default"], 4)} for t in table],
+    }
+
+
+def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
+    """The serving loop on a Poisson trace: latency (completion - arrival, with
+    queueing) percentiles, offered and served particle-force-evaluation rates."""
+    import numpy as np
+    import torch
+
+    import paper_1106_1900_amd as bh
+    import workloads
+    trace = workloads.request_trace(count, rate, seed, steps=steps)
+    nmax = max(q["n"] for q in trace)
+    # Input pools: one Plummer and one Hernquist sphere of nmax particles on the
+    # device.  A request of n particles takes n consecutive particles of its
+    # model at a seeded offset (the draws are independent, so the window is itself
+    # a sample of the model) with masses 1/n.
+    log("generating request pools of %d particles" % nmax)
+    pools = {}
+    for name, gen in (("plummer", workloads.plummer), ("hernquist", workloads.hernquist)):
+        p, v, _ = gen(2 * nmax, 51 if name == "plummer" else 52)
+        pools[name] = (torch.from_numpy(p).cuda(), torch.from_numpy(v).cuda())
+    rng = np.random.default_rng(seed + 1)
+    offsets = [int(rng.integers(0, nmax)) for _ in trace]
+    srv = bh.Server(budget, max_requests=max_requests)
+    cap = srv.stats()["capacity_particles"]
+    torch.cuda.synchronize()
+    t0 = srv.now()
+    i = 0
+    open_t = []
+    last_poll = 0
+    while True:
+        now = srv.now() - t0
+        while i < count and trace[i]["arrival"] <= now:
+            q = trace[i]
+            n = q["n"]
+            pp, pv = pools[q["shape"]]
+            o = offsets[i]
+            m = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+            out_pos = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+            out_acc = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+            tk = srv.submit(pp[o:o + n], m, pv[o:o + n], q["theta"], q["eps"], q["dt"], q["steps"],
+                            arrival=t0 + q["arrival"], out_pos=out_pos, out_acc=out_acc)
+            open_t.append(tk)
+            i += 1
+        st = srv.stats()
+        if st["completed"] + st["rejected"] == count:
+            break
+        if st["resident_requests"] == 0 and st["queued"] == 0:
+            time.sleep(max(0.0, min(0.002, trace[i]["arrival"] - (srv.now() - t0))))
+            continue
+        srv.step()
+        if st["iterations"] - last_poll >= 16:
+            # release the arrays of finished requests
+            open_t = [t for t in open_t if srv.poll(t)["state"] < 2]
+            last_poll = st["iterations"]
+    t_end = srv.now() - t0
+    st = srv.stats()
+    done = [srv.poll(t) for t in range(1, count + 1)]
+    first_arrival = trace[0]["arrival"]
+    work = sum(q["n"] * (1 + q["steps"]) for q in trace)
+    dE = [abs(d["energy"][6]) for d in done if d["state"] == 2]
+    srv.close()
+    return {
+        "workload": "%d requests, Poisson arrivals at %g/s; Plummer or Hernquist (even odds), "
+                    "N log-uniform in [1024, 2097152], theta 0.5 or 0.75, eps 0.01, 1 force "
+                    "evaluation + %d leapfrog steps of dt 1/128" % (count, rate, steps),
+        "hbm_budget_bytes": int(budget), "capacity_particles": int(cap),
+        "latency_p50_s": st["latency_p50"], "latency_p99_s": st["latency_p99"],
+        "latency_max_s": st["latency_max"],
+        "queue_wait_p50_s": st["queue_wait_p50"], "queue_wait_p99_s": st["queue_wait_p99"],
+        "offered_particle_evals_per_s": work / (trace[-1]["arrival"] - first_arrival),
+        "served_particle_evals_per_s": st["particle_evals"] / (t_end - first_arrival),
+        "completed": st["completed"], "rejected": st["rejected"], "iterations": st["iterations"],
+        "wall_s": t_end, "max_abs_energy_error": max(dE) if dE else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +306,15 @@ def main():
                     help="seconds of oracle evaluation for the CPU baseline (0: skip)")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
+    ap.add_argument("--batch-clusters", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests of the served trace (2000: the full 10 s trace)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=0.0,
+                    help="device memory for the server (0: 60%% of the free memory)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -171,20 +349,29 @@ def main():
 
     for _ in range(args.warmup):
         ctx.leapfrog_step(args.dt)
-        ctx.energy()
+    ctx.energy()
     torch.cuda.synchronize()
     s0 = ctx.stats()
 
     log("timing %d steps" % args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # each step computes the energy sums on the device; they are read back once
+    # at the end
     for _ in range(args.steps):
         ctx.leapfrog_step(args.dt)
-        ctx.energy()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s1 = ctx.stats()
     e1 = ctx.energy()
+    # the same steps replayed from a captured graph (no per-kernel host launches)
+    gsteps = min(args.steps, 20)
+    ctx.batch_run(1)
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    ctx.batch_run(gsteps)
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - tg0) / gsteps
 
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -226,17 +413,26 @@ def main():
         "roofline": roofline,
         "interactions_per_s": (pp + pc) * launches / elapsed,
         "phases_ms_last_step": {k: round(v, 4) for k, v in phases.items()},
+        "graph_replay_ms_per_step": graph_ms,
         "energy_error_over_timed_steps": float((e0[2] - e1[2]) / e0[2]),
         "tree": {"ncells": s1.ncells, "ngroups": s1.ngroups, "depth": s1.depth},
         "paper_reference": {"value": PAPER_TRAVERSE_RATE, "unit": "particles/s",
                             "what": "tree traverse only, 1x GTX480, N=2^20 Plummer, theta=0.75"},
     }
+    ctx.close()
+    if not args.no_batch:
+        out["batch"] = bench_batch(args.batch_clusters, args.batch_steps, 2)
+    if not args.no_serve:
+        budget = int(args.serve_budget_gib * (1 << 30))
+        if budget <= 0:
+            budget = int(0.6 * torch.cuda.mem_get_info()[0])
+        log("serving %d requests" % args.serve_requests)
+        out["served"] = bench_serve(args.serve_requests, args.serve_rate, budget)
     if not args.no_accuracy:
         out["accuracy_vs_direct"] = accuracy_sample(pos, mass, acc0_h, args.eps)
     if args.cpu_budget > 0 and rank == 0:
         log("timing the oracle on the host (%.0f s budget)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(pos, mass, args.theta, args.eps, args.cpu_budget)
-    ctx.close()
     if rank == 0:
         print(json.dumps(out), flush=True)
 

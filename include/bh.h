@@ -225,6 +225,131 @@ int bh_batch_run(bh_ctx *ctx, int32_t nsteps);
  * Synchronous. */
 int bh_batch_energy(bh_ctx *ctx, double *out);
 
+/* ---------------------------------------------------------------------------
+ * Autotuning of the leaf size (Sect. 2.1) and group size (Sect. 2.2) per class of
+ * cluster.  A class is (floor(log2 n), theta).  Clusters given nleaf = 0 or
+ * ncrit = 0 take the tuned value of their class when the context holds one, else
+ * the context's default.
+ */
+typedef struct {
+    int32_t log2n;      /* class: floor(log2 n) */
+    float theta;        /* class: opening angle */
+    int32_t nleaf;      /* chosen leaf size */
+    int32_t ncrit;      /* chosen group size */
+    double ms;          /* device time of one step of the class's clusters with the choice */
+    double ms_default;  /* the same with the context's defaults */
+} bh_tune_entry;
+
+/* Times one leapfrog step of dt = 0 (rebuild and forces, no motion) of the loaded
+ * batch's clusters, class by class in a private context, for every nleaf in
+ * {8, 16, 32} and ncrit in {16, 32, 64}, reps steps each, and keeps the fastest
+ * pair per class in the context (replacing an earlier table).  out: host
+ * [cap] entries (may be NULL); *count: classes found.  Synchronous.  The loaded
+ * batch is not changed. */
+int bh_autotune(bh_ctx *ctx, int32_t reps, bh_tune_entry *out, int64_t cap, int64_t *count);
+
+/* Install a tuning table (host [count], copied); count 0 clears it. */
+int bh_set_tuning(bh_ctx *ctx, const bh_tune_entry *entries, int64_t count);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a loop that keeps many independent requests resident on one device
+ * and advances them together.  A request is one system: a force evaluation
+ * followed by nsteps leapfrog steps.  Admission is first come, first served,
+ * while the resident particles and requests fit the capacity derived from the
+ * memory budget; every iteration (bh_server_step) advances each resident request
+ * by one unit (its force evaluation, then one step), so requests join and leave
+ * the batch between iterations (continuous batching at iteration level).
+ */
+
+typedef struct bh_server bh_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes;   /* device memory the server's batch may hold (> 0) */
+    int64_t max_requests;       /* most resident requests (>= 1) */
+    int32_t nleaf;              /* defaults for requests that give 0 */
+    int32_t ncrit;
+    int32_t min_nleaf;          /* smallest leaf size a request may use (1..nleaf; the
+                                   cell storage is sized for it; 0: min(8, nleaf)) */
+    int32_t pad;
+} bh_server_params;
+
+typedef struct {
+    int64_t n;                  /* particles, >= 1 */
+    const double *pos;          /* device [n][3] float64 */
+    const double *mass;         /* device [n] float64, > 0 */
+    const double *vel;          /* device [n][3] float64, or NULL (zero) */
+    float theta;                /* (0, 1] */
+    float eps;                  /* >= 0 */
+    double dt;                  /* leapfrog step, finite */
+    int32_t nsteps;             /* steps after the force evaluation, >= 0 */
+    int32_t nleaf;              /* 1..64, or 0: the server's */
+    int32_t ncrit;              /* 1..64, or 0: the server's */
+    double arrival;             /* arrival time on the server clock (seconds, see
+                                   bh_server_now); a negative value: the time of
+                                   the submit call */
+    double *out_pos;            /* device [n][3] float64, final positions, or NULL */
+    double *out_vel;            /* device [n][3] float64, final velocities, or NULL */
+    float *out_acc;             /* device [n][3] float32, final accelerations, or NULL */
+    float *out_pot;             /* device [n] float32, final potentials, or NULL */
+} bh_request;
+
+#define BH_REQ_QUEUED  0
+#define BH_REQ_RUNNING 1
+#define BH_REQ_DONE    2
+#define BH_REQ_FAILED  3   /* rejected at admission: non-finite data or a mass <= 0 */
+
+typedef struct {
+    int32_t state;              /* BH_REQ_* */
+    int32_t units_done;         /* force evaluation + steps completed */
+    double arrival;             /* server clock, seconds */
+    double admitted;            /* when its data was copied in (-1 while queued) */
+    double completed;           /* when its outputs were written (-1 before) */
+    double energy[7];           /* T, W, E, Px, Py, Pz, (E0 - E) / E0 of its last unit;
+                                   E0 after its force evaluation */
+} bh_request_status;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected;
+    int64_t queued, resident_requests, resident_particles;
+    int64_t capacity_particles;   /* resident particles the budget allows */
+    int64_t iterations;
+    int64_t particle_evals;       /* sum over completed requests of n (1 + nsteps) */
+    double busy_seconds;          /* wall time spent inside bh_server_step */
+    double latency_p50, latency_p99, latency_max;   /* completed - arrival, seconds */
+    double queue_wait_p50, queue_wait_p99;          /* admitted - arrival, seconds */
+} bh_server_stats;
+
+/* Create a server on the current device, its work enqueued on hip_stream (may be
+ * NULL).  BH_ENOMEM if the budget cannot hold one particle. */
+int bh_server_create(bh_server **out, const bh_server_params *p, void *hip_stream);
+
+int bh_server_destroy(bh_server *srv);
+
+/* Queue a request (copied: the struct, not the arrays).  The device arrays pos,
+ * mass and vel must stay valid until the request is admitted (its state leaves
+ * BH_REQ_QUEUED); the out arrays until it is done.  *ticket identifies it.
+ * BH_ENOMEM if the request alone exceeds the capacity. */
+int bh_server_submit(bh_server *srv, const bh_request *req, int64_t *ticket);
+
+/* One iteration: admit queued requests that fit, repack the resident batch if
+ * its membership changed, advance every resident request by one unit, write the
+ * outputs of the requests that finish and retire them.  Waits for the device.
+ * *resident (may be NULL): requests resident during the iteration. */
+int bh_server_step(bh_server *srv, int64_t *resident);
+
+int bh_server_poll(bh_server *srv, int64_t ticket, bh_request_status *out);
+
+int bh_server_stats_get(bh_server *srv, bh_server_stats *out);
+
+/* Install a tuning table (see bh_autotune) for requests given nleaf or ncrit 0. */
+int bh_server_set_tuning(bh_server *srv, const bh_tune_entry *entries, int64_t count);
+
+/* Seconds on the server clock (a monotonic clock started at creation). */
+int bh_server_now(bh_server *srv, double *t);
+
+/* Message for the last non-zero status of this server (never NULL). */
+const char *bh_server_last_error(bh_server *srv);
+
 /* Message for the last non-zero status of this context (never NULL). */
 const char *bh_last_error(bh_ctx *ctx);
 

@@ -11,10 +11,11 @@ from .binding import (  # noqa: F401
     BHError,
     Cluster,
     Context,
+    Server,
     Stats,
     library_path,
     load_library,
     declared_functions,
 )
 
-__all__ = ["BHError", "Cluster", "Context", "Stats", "library_path", "load_library", "declared_functions"]
+__all__ = ["BHError", "Cluster", "Context", "Server", "Stats", "library_path", "load_library", "declared_functions"]

@@ -36,6 +36,14 @@ class Cluster(ctypes.Structure):
                 ("dt", ctypes.c_double), ("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("log2n", ctypes.c_int32), ("theta", ctypes.c_float), ("nleaf", ctypes.c_int32),
+                ("ncrit", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("ncells", ctypes.c_int64), ("nleaves", ctypes.c_int64),
                 ("ngroups", ctypes.c_int64), ("depth", ctypes.c_int32),
@@ -104,6 +112,9 @@ def load_library():
         "bh_batch_forces": (i32, [_vp, _vp, _vp]),
         "bh_batch_run": (i32, [_vp, ctypes.c_int32]),
         "bh_batch_energy": (i32, [_vp, _vp]),
+        "bh_autotune": (i32, [_vp, ctypes.c_int32, ctypes.POINTER(TuneEntry), i64,
+                              ctypes.POINTER(i64)]),
+        "bh_set_tuning": (i32, [_vp, ctypes.POINTER(TuneEntry), i64]),
         "bh_last_error": (ctypes.c_char_p, [_vp]),
     }
     for name, (res, args) in sig.items():
@@ -233,6 +244,22 @@ class Context:
         self._check(self._L.bh_batch_energy(self._h, out.ctypes.data_as(_vp)))
         return out
 
+    def autotune(self, reps=3):
+        """Tune (nleaf, ncrit) per class (floor(log2 n), theta) of the loaded batch;
+        returns the table (list of dicts) the context now holds."""
+        cap = 64
+        arr = (TuneEntry * cap)()
+        cnt = ctypes.c_int64()
+        self._check(self._L.bh_autotune(self._h, int(reps), arr, cap, ctypes.byref(cnt)))
+        return [arr[i].as_dict() for i in range(min(cap, cnt.value))]
+
+    def set_tuning(self, table):
+        arr = (TuneEntry * max(1, len(table)))()
+        for a, t in zip(arr, table):
+            for k, _ in TuneEntry._fields_:
+                setattr(a, k, t[k])
+        self._check(self._L.bh_set_tuning(self._h, arr, len(table)))
+
     def set_velocities(self, vel):
         import torch
         self._check(self._L.bh_set_velocities(self._h, _dev_ptr(vel, torch.float64, (self.n, 3),
@@ -310,3 +337,147 @@ class Context:
     def _device(self):
         import torch
         return torch.device("cuda", torch.cuda.current_device())
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_requests", ctypes.c_int64),
+                ("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
+                ("min_nleaf", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("pos", _vp), ("mass", _vp), ("vel", _vp),
+                ("theta", ctypes.c_float), ("eps", ctypes.c_float), ("dt", ctypes.c_double),
+                ("nsteps", ctypes.c_int32), ("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
+                ("arrival", ctypes.c_double), ("out_pos", _vp), ("out_vel", _vp),
+                ("out_acc", _vp), ("out_pot", _vp)]
+
+
+class RequestStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("units_done", ctypes.c_int32),
+                ("arrival", ctypes.c_double), ("admitted", ctypes.c_double),
+                ("completed", ctypes.c_double), ("energy", ctypes.c_double * 7)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "admitted", "completed", "rejected",
+                                              "queued", "resident_requests", "resident_particles",
+                                              "capacity_particles", "iterations",
+                                              "particle_evals")] + \
+               [(k, ctypes.c_double) for k in ("busy_seconds", "latency_p50", "latency_p99",
+                                               "latency_max", "queue_wait_p50", "queue_wait_p99")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
+def _server_sigs(L):
+    i32, i64 = ctypes.c_int, ctypes.c_int64
+    sig = {
+        "bh_server_create": (i32, [ctypes.POINTER(_vp), ctypes.POINTER(ServerParams), _vp]),
+        "bh_server_destroy": (i32, [_vp]),
+        "bh_server_submit": (i32, [_vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]),
+        "bh_server_step": (i32, [_vp, ctypes.POINTER(i64)]),
+        "bh_server_poll": (i32, [_vp, i64, ctypes.POINTER(RequestStatus)]),
+        "bh_server_stats_get": (i32, [_vp, ctypes.POINTER(ServerStats)]),
+        "bh_server_now": (i32, [_vp, ctypes.POINTER(ctypes.c_double)]),
+        "bh_server_set_tuning": (i32, [_vp, ctypes.POINTER(TuneEntry), i64]),
+        "bh_server_last_error": (ctypes.c_char_p, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+class Server:
+    """The serving loop (bh_server): requests of one system each, admitted by the
+    memory budget and advanced together one unit per iteration."""
+
+    def __init__(self, hbm_budget_bytes, max_requests=256, nleaf=16, ncrit=64, min_nleaf=0,
+                 stream=None):
+        import torch
+        self._L = load_library()
+        _server_sigs(self._L)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        p = ServerParams(int(hbm_budget_bytes), int(max_requests), int(nleaf), int(ncrit),
+                         int(min_nleaf), 0)
+        h = _vp()
+        st = self._L.bh_server_create(ctypes.byref(h), ctypes.byref(p), _vp(stream.cuda_stream))
+        if st:
+            raise BHError(st, "bh_server_create failed")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.bh_server_destroy(self._h)
+        self._h = None
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st:
+            raise BHError(st, self._L.bh_server_last_error(self._h).decode())
+
+    def now(self):
+        t = ctypes.c_double()
+        self._check(self._L.bh_server_now(self._h, ctypes.byref(t)))
+        return t.value
+
+    def submit(self, pos, mass, vel=None, theta=0.75, eps=0.01, dt=1.0 / 128, nsteps=10,
+               nleaf=0, ncrit=0, arrival=-1.0, out_pos=None, out_vel=None, out_acc=None,
+               out_pot=None):
+        """Queue a request; the tensors are kept alive until it is done."""
+        import torch
+        n = int(pos.shape[0])
+        r = Request()
+        r.n = n
+        r.pos = _dev_ptr(pos, torch.float64, (n, 3), "pos")
+        r.mass = _dev_ptr(mass, torch.float64, (n,), "mass")
+        r.vel = _dev_ptr(vel, torch.float64, (n, 3), "vel")
+        r.theta, r.eps, r.dt, r.nsteps = float(theta), float(eps), float(dt), int(nsteps)
+        r.nleaf, r.ncrit, r.arrival = int(nleaf), int(ncrit), float(arrival)
+        r.out_pos = _dev_ptr(out_pos, torch.float64, (n, 3), "out_pos")
+        r.out_vel = _dev_ptr(out_vel, torch.float64, (n, 3), "out_vel")
+        r.out_acc = _dev_ptr(out_acc, torch.float32, (n, 3), "out_acc")
+        r.out_pot = _dev_ptr(out_pot, torch.float32, (n,), "out_pot")
+        t = ctypes.c_int64()
+        self._check(self._L.bh_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = (pos, mass, vel, out_pos, out_vel, out_acc, out_pot)
+        return t.value
+
+    def set_tuning(self, table):
+        arr = (TuneEntry * max(1, len(table)))()
+        for a, t in zip(arr, table):
+            for k, _ in TuneEntry._fields_:
+                setattr(a, k, t[k])
+        self._check(self._L.bh_server_set_tuning(self._h, arr, len(table)))
+
+    def step(self):
+        k = ctypes.c_int64()
+        self._check(self._L.bh_server_step(self._h, ctypes.byref(k)))
+        return k.value
+
+    def poll(self, ticket):
+        s = RequestStatus()
+        self._check(self._L.bh_server_poll(self._h, int(ticket), ctypes.byref(s)))
+        if s.state in (REQ_DONE, REQ_FAILED):
+            self._keep.pop(int(ticket), None)
+        return {"state": s.state, "units_done": s.units_done, "arrival": s.arrival,
+                "admitted": s.admitted, "completed": s.completed, "energy": list(s.energy)}
+
+    def stats(self):
+        s = ServerStats()
+        self._check(self._L.bh_server_stats_get(self._h, ctypes.byref(s)))
+        return s.as_dict()

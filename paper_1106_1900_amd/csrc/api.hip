@@ -226,6 +226,12 @@ int ensure_capacity(bh_ctx *c, int64_t n, int64_t K, int nleaf_min)
         if (bytes_for(c, z) > c->p.hbm_budget_bytes)
             return fail(c, BH_ENOMEM, "particle count exceeds the context's memory budget");
     }
+    // the walk stack packs a cell index into 29 bits
+    if (z.cells >= (int64_t)1 << 29) {
+        z = sizes_for(c, n, K, nleaf_min);
+        if (z.cells >= (int64_t)1 << 29)
+            return fail(c, BH_ENOMEM, "too many particles for 2^29 cells");
+    }
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_buffers(c);
     hipError_t e = each_buffer(c, z, [&](auto **pp, size_t sz, int64_t cnt) {
@@ -278,7 +284,26 @@ int upload_clusters(bh_ctx *c)
 bool bad_theta(float theta) { return !(theta > 0.0f && theta <= 1.0f); }
 bool bad_eps(float eps) { return !(eps >= 0.0f) || !std::isfinite(eps); }
 
-// Checks a cluster table and resolves leaf / group sizes of 0 to the context's.
+int log2_floor(int64_t n)
+{
+    int b = 0;
+    while (n > 1) {
+        n >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+const bh_tune_entry *tuned_for(bh_ctx *c, int64_t n, float theta)
+{
+    const int b = log2_floor(n);
+    for (const auto &t : c->tuning)
+        if (t.log2n == b && t.theta == theta) return &t;
+    return nullptr;
+}
+
+// Checks a cluster table and resolves leaf / group sizes of 0 to the tuned
+// values of the cluster's class, else the context's.
 int check_clusters(bh_ctx *c, const bh_cluster *cl, int64_t K, std::vector<bh_cluster> &out,
                    int64_t *total)
 {
@@ -287,8 +312,11 @@ int check_clusters(bh_ctx *c, const bh_cluster *cl, int64_t K, std::vector<bh_cl
     out.assign(cl, cl + K);
     int64_t n = 0;
     for (auto &q : out) {
-        if (q.nleaf == 0) q.nleaf = c->p.nleaf;
-        if (q.ncrit == 0) q.ncrit = c->p.ncrit;
+        if ((q.nleaf == 0 || q.ncrit == 0) && q.n >= 1) {
+            const bh_tune_entry *t = tuned_for(c, q.n, q.theta);
+            if (q.nleaf == 0) q.nleaf = t ? t->nleaf : c->p.nleaf;
+            if (q.ncrit == 0) q.ncrit = t ? t->ncrit : c->p.ncrit;
+        }
         if (q.n < 1) return fail(c, BH_EINVAL, "every cluster needs n >= 1");
         if (q.nleaf < 1 || q.nleaf > 64 || q.ncrit < 1 || q.ncrit > 64)
             return fail(c, BH_EINVAL, "cluster nleaf and ncrit must be in 1..64");
@@ -427,13 +455,15 @@ hipError_t enqueue_forces(bh_ctx *c, float *acc, float *pot)
     return hipSuccess;
 }
 
-// kick-drift-kick with each cluster's dt
+// kick-drift-kick with each cluster's dt, then the energy and momentum sums of
+// the new state (kept on the device until an energy call reads them)
 hipError_t enqueue_step(bh_ctx *c)
 {
     BH_HIP_TRY(launch_kick_drift(c));
     BH_HIP_TRY(enqueue_rebuild(c));
     BH_HIP_TRY(enqueue_forces(c, nullptr, nullptr));
     BH_HIP_TRY(launch_kick(c));
+    BH_HIP_TRY(launch_energy(c));
     return hipSuccess;
 }
 
@@ -529,6 +559,7 @@ int load(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n, const double *
     TRY_ST(ensure_capacity(c, n, (int64_t)cl.size(), lmin));
     c->built = false;
     c->have_forces = false;
+    c->energy_current = false;
     TRY_ST(load_table(c, cl, n));
     reset_e0(c);
     TRY_HIP(c, enqueue_load(c, pos, mass, vel));
@@ -541,13 +572,15 @@ int run_forces(bh_ctx *c, float *acc, float *pot)
     if (!c->built) return fail(c, BH_ESTATE, "forces need a built tree");
     TRY_HIP(c, enqueue_forces(c, acc, pot));
     c->have_forces = true;
+    c->energy_current = false;
     return BH_OK;
 }
 
 int energies(bh_ctx *c)
 {
     if (!c->have_forces) return fail(c, BH_ESTATE, "energy needs potentials from a force call");
-    TRY_HIP(c, launch_energy(c));
+    if (!c->energy_current) TRY_HIP(c, launch_energy(c));
+    c->energy_current = true;
     TRY_HIP(c, hipMemcpyAsync(c->e_out_h, c->e_out, sizeof(double) * 5 * (size_t)c->K,
                               hipMemcpyDeviceToHost, c->stream));
     return sync_check(c);
@@ -570,6 +603,59 @@ void fill_energy(double *out, const double *s, double *e0, bool *have)
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// entry points for the serving loop (serve.hip)
+
+namespace bh {
+
+int ctx_fail(bh_ctx *c, int code, const char *msg) { return fail(c, code, msg); }
+
+int ctx_hip_fail(bh_ctx *c, hipError_t e, const char *where) { return hip_fail(c, e, where); }
+
+int64_t ctx_bytes_for(bh_ctx *c, int64_t n, int64_t K, int nleaf_min)
+{
+    return bytes_for(c, sizes_for(c, n, K, nleaf_min));
+}
+
+int ctx_reserve(bh_ctx *c, int64_t n, int64_t K, int nleaf_min)
+{
+    return ensure_capacity(c, n, K, nleaf_min);
+}
+
+int ctx_check_clusters(bh_ctx *c, const bh_cluster *cl, int64_t K, std::vector<bh_cluster> &out,
+                       int64_t *total)
+{
+    return check_clusters(c, cl, K, out, total);
+}
+
+// Installs a new cluster table for particles already placed in the buffers of
+// parity c->cur (a repacked batch); the next step rebuilds every tree.
+int ctx_set_layout(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n)
+{
+    TRY_ST(load_table(c, cl, n));
+    TRY_HIP(c, launch_cluster_ids(c));
+    c->built = true;
+    c->have_forces = true;
+    c->energy_current = false;
+    return BH_OK;
+}
+
+int ctx_update_params(bh_ctx *c, const std::vector<bh_cluster> &cl) { return update_params(c, cl); }
+
+int ctx_step(bh_ctx *c, bool graph)
+{
+    if (graph) TRY_ST(step_graph(c));
+    else TRY_HIP(c, enqueue_step(c));
+    c->energy_current = true;
+    return BH_OK;
+}
+
+int ctx_sync_check(bh_ctx *c) { return sync_check(c); }
+
+int ctx_log2_floor(int64_t n) { return log2_floor(n); }
+
+}  // namespace bh
 
 extern "C" {
 
@@ -705,6 +791,7 @@ int bh_set_velocities(bh_ctx *c, const double *vel)
     if (!c->built) return fail(c, BH_ESTATE, "no particles loaded");
     TRY_HIP(c, launch_set_velocities(c, vel));
     reset_e0(c);
+    c->energy_current = false;
     return BH_OK;
 }
 
@@ -739,6 +826,7 @@ int bh_leapfrog_step(bh_ctx *c, double dt)
     for (auto &q : cl) q.dt = dt;
     TRY_ST(update_params(c, cl));
     TRY_HIP(c, enqueue_step(c));
+    c->energy_current = true;
     return BH_OK;
 }
 
@@ -748,7 +836,10 @@ int bh_batch_run(bh_ctx *c, int32_t nsteps)
     if (nsteps < 0) return fail(c, BH_EINVAL, "nsteps must be >= 0");
     if (!c->built || !c->have_forces)
         return fail(c, BH_ESTATE, "batch_run needs a prior force evaluation");
-    for (int32_t s = 0; s < nsteps; ++s) TRY_ST(step_graph(c));
+    for (int32_t s = 0; s < nsteps; ++s) {
+        TRY_ST(step_graph(c));
+        c->energy_current = true;
+    }
     return BH_OK;
 }
 
@@ -769,6 +860,7 @@ int bh_set_state(bh_ctx *c, const double *pos, const double *vel)
     TRY_HIP(c, launch_set_positions(c, pos, vel));
     reset_e0(c);
     c->have_forces = false;
+    c->energy_current = false;
     TRY_HIP(c, enqueue_rebuild(c));
     return sync_check(c);
 }

@@ -121,6 +121,7 @@ struct bh_ctx {
     bool built = false;
     bool have_forces = false;
     bool have_e0 = false;
+    bool energy_current = false;  // e_out holds the sums of the current state
     int64_t layout = 0;     // changes whenever buffers or the cluster table change
 
     // host copies of counts, refreshed at synchronisation points
@@ -139,6 +140,7 @@ struct bh_ctx {
     std::vector<uint8_t> have_e0_k;
     double e0 = 0.0;                         // the same for the whole batch (bh_energy)
     std::vector<bh_cluster> host_clusters;   // the loaded cluster table as given
+    std::vector<bh_tune_entry> tuning;       // leaf / group sizes per class of cluster
     bool capturing = false;                  // enqueueing into a graph: no event records
 
     // ---- particle buffers (sorted order) ----
@@ -233,6 +235,19 @@ hipError_t launch_scatter(bh_ctx *c, float *acc, float *pot);
 hipError_t launch_zero_acc(bh_ctx *c);
 int64_t walk_spill_words(int64_t waves);
 int64_t walk_grid_waves(bh_ctx *c);
+
+// api.hip: context operations used by the serving loop (serve.hip)
+int ctx_fail(bh_ctx *c, int code, const char *msg);
+int ctx_hip_fail(bh_ctx *c, hipError_t e, const char *where);
+int64_t ctx_bytes_for(bh_ctx *c, int64_t n, int64_t K, int nleaf_min);
+int ctx_reserve(bh_ctx *c, int64_t n, int64_t K, int nleaf_min);
+int ctx_check_clusters(bh_ctx *c, const bh_cluster *cl, int64_t K, std::vector<bh_cluster> &out,
+                       int64_t *total);
+int ctx_set_layout(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n);
+int ctx_update_params(bh_ctx *c, const std::vector<bh_cluster> &cl);
+int ctx_step(bh_ctx *c, bool graph);
+int ctx_sync_check(bh_ctx *c);
+int ctx_log2_floor(int64_t n);
 
 // integrate.hip (per-cluster dt from the cluster table)
 hipError_t launch_kick(bh_ctx *c);

@@ -35,20 +35,29 @@ def test_library_exports_every_declared_symbol():
         assert getattr(lib, f) is not None
 
 
+STRUCTS = [("bh_params", "Params"), ("bh_stats", "Stats"), ("bh_tree_host", "TreeHost"),
+           ("bh_cluster", "Cluster"), ("bh_server_params", "ServerParams"),
+           ("bh_request", "Request"), ("bh_request_status", "RequestStatus"),
+           ("bh_server_stats", "ServerStats"), ("bh_tune_entry", "TuneEntry")]
+
+
 def test_struct_layouts_match_the_header(tmp_path):
+    # size and every field offset of each ctypes structure against the C compiler
+    lines, want = [], []
+    for cname, pyname in STRUCTS:
+        cls = getattr(binding, pyname)
+        lines.append('printf("%%zu\\n", sizeof(%s));' % cname)
+        want.append(ctypes.sizeof(cls))
+        for f, _ in cls._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (cname, f))
+            want.append(getattr(cls, f).offset)
     src = tmp_path / "sizes.c"
-    src.write_text(
-        '#include <stdio.h>\n#include <stddef.h>\n#include "bh.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(bh_params), sizeof(bh_stats),'
-        ' sizeof(bh_tree_host), offsetof(bh_stats, ms_keys), offsetof(bh_stats, device_bytes));'
-        'return 0;}\n')
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "bh.h"\n'
+                   "int main(void){" + "".join(lines) + "return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
                            str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
-    want = [ctypes.sizeof(binding.Params), ctypes.sizeof(binding.Stats),
-            ctypes.sizeof(binding.TreeHost), binding.Stats.ms_keys.offset,
-            binding.Stats.device_bytes.offset]
     assert got == want
 
 
@@ -56,9 +65,12 @@ def test_default_params_without_a_device():
     lib = bh.load_library()
     p = binding.Params()
     assert lib.bh_default_params(ctypes.byref(p)) == 0
-    assert (p.nleaf, p.ncrit, p.max_n, p.hbm_budget_bytes) == (16, 64, 0, 0)
+    assert (p.nleaf, p.ncrit, p.max_n, p.hbm_budget_bytes, p.max_clusters) == (16, 64, 0, 0, 0)
     assert lib.bh_default_params(None) == binding.BH_EINVAL
     assert lib.bh_last_error(None) == b"null context"
+    binding._server_sigs(lib)
+    assert lib.bh_server_last_error(None) == b"null server"
+    assert lib.bh_server_create(None, None, None) == binding.BH_EINVAL
 
 
 def test_binding_refuses_to_run_without_the_library(monkeypatch):

@@ -216,3 +216,43 @@ def test_batch_errors():
     ctx.batch_run(2)
     assert np.all(np.isfinite(ctx.batch_energy()))
     ctx.close()
+
+
+def test_autotune_table_and_tuned_build():
+    # two classes of cluster (log2 n = 10 and 12 at theta 0.75, plus theta 0.5);
+    # the table holds one entry per class with candidates from the grid, and a
+    # batch loaded with nleaf = ncrit = 0 takes the tuned values, checked against
+    # the oracle tree built with them
+    import paper_1106_1900_amd as bh
+    import torch
+    parts = []
+    for i, (n, theta) in enumerate([(1100, 0.75), (1500, 0.75), (4500, 0.75), (6000, 0.75),
+                                    (1300, 0.5)]):
+        p, v, m = workloads.plummer(n, 40 + i)
+        parts.append((p, v, m, dict(theta=theta, eps=0.01, nleaf=16, ncrit=64)))
+    pos, vel, mass, clusters = _concat(parts)
+    ctx = bh.Context()
+    ctx.batch_build(clusters, to_dev(pos), to_dev(mass), to_dev(vel))
+    tab = ctx.autotune(reps=2)
+    say("tuning", tab)
+    got = sorted((t["log2n"], round(t["theta"], 6)) for t in tab)
+    assert got == [(10, 0.5), (10, 0.75), (12, 0.75)]
+    for t in tab:
+        assert t["nleaf"] in (8, 16, 32) and t["ncrit"] in (16, 32, 64)
+        assert 0 < t["ms"] <= t["ms_default"]
+    zero = [dict(q, nleaf=0, ncrit=0) for q in clusters]
+    for c in (ctx, None):
+        if c is None:
+            c = bh.Context()
+            c.set_tuning(tab)
+        c.batch_build(zero, to_dev(pos), to_dev(mass), to_dev(vel))
+        c.batch_forces(want=False)
+        torch.cuda.synchronize()
+        views = split_forest(c.export_tree(), [q["n"] for q in clusters])
+        for (cp, _, cm, prm), d in zip(parts, views):
+            t = [e for e in tab if e["log2n"] == int(np.log2(cp.shape[0]))
+                 and abs(e["theta"] - prm["theta"]) < 1e-6][0]
+            tree = oracle.Tree(cp, cm, t["nleaf"], t["ncrit"])
+            compare_tree(d, tree)
+            compare_walk(d, tree, prm["theta"])
+        c.close()

@@ -1,0 +1,148 @@
+"""GPU tests of the serving loop: requests admitted by the memory budget and
+advanced together one unit per iteration must end bit-identical to the same
+request run alone; admission respects the capacity; bad requests are rejected
+without disturbing the others."""
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    reqs = []
+    shapes = [("plummer", 3000, 0.5, 3), ("hernquist", 1500, 0.75, 0), ("plummer", 20000, 0.75, 4),
+              ("hernquist", 700, 0.5, 2), ("plummer", 64, 0.6, 5), ("hernquist", 9000, 0.75, 1),
+              ("plummer", 2, 0.9, 3), ("plummer", 12000, 0.5, 2)]
+    for i, (shape, n, theta, nsteps) in enumerate(shapes):
+        if shape == "plummer":
+            p, v, m = workloads.plummer(n, 100 + i)
+        else:
+            p, v, m = workloads.hernquist(n, 100 + i)
+        reqs.append(dict(pos=p, vel=v, mass=m, theta=theta, eps=0.01, dt=1 / 128, nsteps=nsteps,
+                         nleaf=(16, 8, 32)[i % 3], ncrit=(64, 32, 16)[i % 3]))
+    return reqs
+
+
+def _alone(q):
+    import paper_1106_1900_amd as bh
+    ctx = bh.Context(nleaf=q["nleaf"], ncrit=q["ncrit"])
+    ctx.build_tree(to_dev(q["pos"]), to_dev(q["mass"]))
+    ctx.set_velocities(to_dev(q["vel"]))
+    ctx.compute_forces(q["theta"], q["eps"], want=False)
+    for _ in range(q["nsteps"]):
+        ctx.leapfrog_step(q["dt"])
+    out = [t.cpu().numpy() for t in ctx.get_state()]
+    e = ctx.energy()
+    ctx.close()
+    return out, e
+
+
+def _serve(reqs, budget, max_requests=16, stagger=False):
+    import torch
+
+    import paper_1106_1900_amd as bh
+    srv = bh.Server(budget, max_requests=max_requests)
+    outs, tickets = [], []
+    pending = list(range(len(reqs)))
+    steps = 0
+    cap = None
+    while pending or any(srv.poll(t)["state"] < 2 for t in tickets):
+        # with stagger, one new request joins every other iteration
+        take = pending[:1] if stagger and steps % 2 == 0 else ([] if stagger else pending)
+        for i in list(take):
+            q = reqs[i]
+            n = q["pos"].shape[0]
+            o = (torch.empty((n, 3), dtype=torch.float64, device="cuda"),
+                 torch.empty((n, 3), dtype=torch.float64, device="cuda"),
+                 torch.empty((n, 3), dtype=torch.float32, device="cuda"),
+                 torch.empty((n,), dtype=torch.float32, device="cuda"))
+            t = srv.submit(to_dev(q["pos"]), to_dev(q["mass"]), to_dev(q["vel"]), q["theta"],
+                           q["eps"], q["dt"], q["nsteps"], q["nleaf"], q["ncrit"],
+                           out_pos=o[0], out_vel=o[1], out_acc=o[2], out_pot=o[3])
+            outs.append(o)
+            tickets.append(t)
+            pending.remove(i)
+        srv.step()
+        st = srv.stats()
+        cap = st["capacity_particles"]
+        assert st["resident_particles"] <= cap
+        steps += 1
+        assert steps < 500
+    torch.cuda.synchronize()
+    return srv, tickets, outs, cap
+
+
+@pytest.mark.parametrize("stagger", [False, True])
+def test_served_requests_equal_requests_run_alone(stagger):
+    reqs = _requests()
+    say("case serve", len(reqs), "stagger", stagger)
+    srv, tickets, outs, _ = _serve(reqs, 1 << 30, stagger=stagger)
+    for q, t, o in zip(reqs, tickets, outs):
+        st = srv.poll(t)
+        assert st["state"] == 2 and st["units_done"] == 1 + q["nsteps"]
+        (x, v, a, p), e = _alone(q)
+        got = [z.cpu().numpy() for z in o]
+        for g, w, name in zip(got, (x, v, a, p), ("pos", "vel", "acc", "pot")):
+            assert np.array_equal(g, w), (q["pos"].shape[0], q["nsteps"], name)
+        assert st["energy"][2] == pytest.approx(e[2], rel=1e-12)
+        assert st["energy"][6] == pytest.approx(e[6], rel=1e-9, abs=1e-15)
+    s = srv.stats()
+    assert s["completed"] == len(reqs) and s["rejected"] == 0
+    assert s["particle_evals"] == sum(q["pos"].shape[0] * (1 + q["nsteps"]) for q in reqs)
+    assert s["latency_p99"] >= s["latency_p50"] > 0
+    srv.close()
+
+
+def test_admission_waits_for_the_budget():
+    # a budget of about 30,000 resident particles: the requests cannot all be
+    # resident at once, so some wait in the queue, and all complete
+    import paper_1106_1900_amd as bh
+    from paper_1106_1900_amd.binding import BH_ENOMEM
+    reqs = _requests()
+    caps = []
+    for b in (128 << 20, 256 << 20):
+        probe = bh.Server(b, max_requests=16)
+        caps.append(probe.stats()["capacity_particles"])
+        probe.close()
+    slope = (128 << 20) / (caps[1] - caps[0])       # bytes per resident particle
+    budget = int((128 << 20) + (30_000 - caps[0]) * slope)
+    srv, tickets, outs, cap = _serve(reqs, budget)
+    say("capacity", cap)
+    assert 20_000 <= cap < 40_000
+    s = srv.stats()
+    assert s["completed"] == len(reqs)
+    waits = [srv.poll(t)["admitted"] - srv.poll(t)["arrival"] for t in tickets]
+    assert max(waits) > 0
+    for q, o in zip(reqs[:3], outs[:3]):
+        (x, v, a, p), _ = _alone(q)
+        assert np.array_equal(o[0].cpu().numpy(), x) and np.array_equal(o[2].cpu().numpy(), a)
+    # a request larger than the capacity is refused at once
+    big, _, mb = workloads.plummer(cap + 1, 5)
+    with pytest.raises(bh.BHError) as e:
+        srv.submit(to_dev(big), to_dev(mb))
+    assert e.value.code == BH_ENOMEM
+    srv.close()
+
+
+def test_bad_request_is_rejected_alone():
+    import paper_1106_1900_amd as bh
+    reqs = _requests()[:3]
+    bad = dict(reqs[0])
+    bad["pos"] = bad["pos"].copy()
+    bad["pos"][11, 2] = np.nan
+    srv, tickets, outs, _ = _serve([reqs[0], bad, reqs[1], reqs[2]], 1 << 30)
+    states = [srv.poll(t)["state"] for t in tickets]
+    assert states == [2, 3, 2, 2]
+    for q, o in zip([reqs[0], None, reqs[1], reqs[2]], outs):
+        if q is None:
+            continue
+        (x, v, a, p), _ = _alone(q)
+        assert np.array_equal(o[0].cpu().numpy(), x) and np.array_equal(o[3].cpu().numpy(), p)
+    assert srv.stats()["rejected"] == 1
+    with pytest.raises(bh.BHError):
+        srv.submit(to_dev(reqs[0]["pos"]), to_dev(reqs[0]["mass"]), theta=0.0)
+    srv.close()

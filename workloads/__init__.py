@@ -8,6 +8,7 @@ All arrays are float64 NumPy arrays: positions and velocities of shape (n, 3), m
 of shape (n,).
 """
 
+from .batches import cluster_batch, cluster_sizes, hernquist, request_trace
 from .galaxy import galaxy
 from .plummer import plummer, plummer_radii
 from .shapes import (
@@ -20,6 +21,10 @@ from .shapes import (
 )
 
 __all__ = [
+    "cluster_batch",
+    "cluster_sizes",
+    "hernquist",
+    "request_trace",
     "galaxy",
     "plummer",
     "plummer_radii",

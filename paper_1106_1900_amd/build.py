@@ -35,8 +35,10 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False, extra_flags=(), out=None, objdir=None):
-    """Compile every source to an object (in parallel) and link libbh.so (or out)."""
+def build(verbose=False, extra_flags=(), out=None, objdir=None, srcdir=None):
+    """Compile every source (from srcdir, default the package's csrc/) to an object
+    (in parallel) and link libbh.so (or out)."""
+    srcdir = srcdir or CSRC
     objdir = objdir or os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     lib = out or LIB
@@ -46,7 +48,7 @@ def build(verbose=False, extra_flags=(), out=None, objdir=None):
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [cc, *HIPFLAGS, *extra_flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *HIPFLAGS, *extra_flags, "-c", os.path.join(srcdir, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

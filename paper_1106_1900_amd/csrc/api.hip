@@ -330,6 +330,13 @@ int check_clusters(bh_ctx *c, const bh_cluster *cl, int64_t K, std::vector<bh_cl
     return BH_OK;
 }
 
+bool any_zero_eps(const std::vector<bh_cluster> &cl)
+{
+    for (const auto &q : cl)
+        if (!(q.eps > 0.0f) || !(q.eps * q.eps > 0.0f)) return true;
+    return false;
+}
+
 void fill_params(DevCluster &d, const bh_cluster &q)
 {
     d.dt = q.dt;
@@ -374,6 +381,7 @@ int load_table(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n)
     c->nchunks = nch;
     c->max_nleaf = lmax;
     c->host_clusters = cl;
+    c->any_eps0 = any_zero_eps(cl);
     c->layout += 1;
     TRY_HIP(c, hipMemcpyAsync(c->chunks, c->chunks_h, sizeof(Chunk) * (size_t)nch,
                               hipMemcpyHostToDevice, c->stream));
@@ -393,6 +401,11 @@ int update_params(bh_ctx *c, const std::vector<bh_cluster> &cl)
     TRY_ST(staging_ready(c));
     for (int64_t k = 0; k < c->K; ++k) fill_params(c->clus_h[k], cl[k]);
     c->host_clusters = cl;
+    const bool z = any_zero_eps(cl);
+    if (z != c->any_eps0) {
+        c->any_eps0 = z;
+        c->layout += 1;     // the captured step holds the other walk variant
+    }
     return upload_clusters(c);
 }
 
@@ -533,6 +546,7 @@ int sync_check(bh_ctx *c)
         if (bits & 1u) return fail(c, BH_EINVAL, "non-finite particle coordinate");
         if (bits & 2u) return fail(c, BH_EINVAL, "particle mass must be finite and > 0");
         if (bits & 4u) return fail(c, BH_EDEVICE, "cell capacity exceeded");
+        if (bits & 8u) return fail(c, BH_EDEVICE, "internal error: particle index out of range");
         return fail(c, BH_EDEVICE, "walk list overflow");
     }
     if (c->built && (c->ncells < c->K || c->ncells > c->cap_c || c->ngroups < c->K ||

@@ -83,7 +83,7 @@ constexpr int kChunk = 4096;           // particles per chunk
 // Small device-side scalars shared by the build and walk kernels.
 struct DevMisc {
     // error bits, kept until the host reads and clears them: bit 0 non-finite
-    // coordinate, bit 1 bad mass, bit 2 cell capacity
+    // coordinate, bit 1 bad mass, bit 2 cell capacity, bit 3 index out of range
     uint32_t nonfinite;
     uint32_t pad0;
     uint32_t level_count[kLevels];
@@ -122,6 +122,7 @@ struct bh_ctx {
     bool have_forces = false;
     bool have_e0 = false;
     bool energy_current = false;  // e_out holds the sums of the current state
+    bool any_eps0 = false;        // some cluster has zero softening (walk variant)
     int64_t layout = 0;     // changes whenever buffers or the cluster table change
 
     // host copies of counts, refreshed at synchronisation points

@@ -160,20 +160,43 @@ bbox_kernel(Src src, const Chunk *__restrict__ chunks, double *__restrict__ part
     }
 }
 
-// One thread per cluster: reduce its chunk partials; cube side = largest extent
+// One block per cluster: reduce its chunk partials; cube side = largest extent
 // (1 if all extents vanish); scale = 2^20 / side.
 __global__ void __launch_bounds__(kBlock)
 domain_kernel(const double *__restrict__ part, const DevCluster *__restrict__ clus,
-              DevDomain *__restrict__ dom, int64_t K)
+              DevDomain *__restrict__ dom)
 {
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= K) return;
-    const DevCluster cl = clus[c];
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (uint32_t b = cl.chunk0; b < cl.chunk0 + cl.nchunk; ++b) {
+    const DevCluster &cl = clus[blockIdx.x];
+    const uint32_t b0 = cl.chunk0, b1 = cl.chunk0 + cl.nchunk;
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t b = b0 + threadIdx.x; b < b1; b += kBlock) {
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
-            lo[k] = fmin(lo[k], part[6 * (int64_t)b + k]);
-            hi[k] = fmax(hi[k], part[6 * (int64_t)b + 3 + k]);
+            v[k] = fmin(v[k], part[6 * (int64_t)b + k]);
+            v[3 + k] = fmax(v[3 + k], part[6 * (int64_t)b + 3 + k]);
+        }
+    }
+    __shared__ double s_v[6][kBlock / kWave];
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double a = v[k];
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const double o = __shfl_xor(a, d, kWave);
+            a = k < 3 ? fmin(a, o) : fmax(a, o);
+        }
+        if (l == 0) s_v[k][w] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = s_v[k][0];
+        hi[k] = s_v[3 + k][0];
+        for (int i = 1; i < kBlock / kWave; ++i) {
+            lo[k] = fmin(lo[k], s_v[k][i]);
+            hi[k] = fmax(hi[k], s_v[3 + k][i]);
         }
     }
     DevDomain d;
@@ -181,13 +204,13 @@ domain_kernel(const double *__restrict__ part, const DevCluster *__restrict__ cl
     for (int k = 0; k < 3; ++k) {
         d.lo[k] = lo[k];
         d.pad[k] = 0.0;
-        double e = hi[k] - lo[k];
+        const double e = hi[k] - lo[k];
         if (e > side) side = e;
     }
     if (side == 0.0) side = 1.0;
     d.L = side;
     d.scale = 1048576.0 / side;
-    dom[c] = d;
+    dom[blockIdx.x] = d;
 }
 
 template <typename Src>
@@ -489,8 +512,9 @@ cell_ends_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__ 
 // counted on the device
 __global__ void __launch_bounds__(kBlock)
 group_boxes_kernel(const uint32_t *__restrict__ g_first, const DevMisc *__restrict__ m, int64_t n,
-                   const double4 *__restrict__ p4, uint32_t *__restrict__ g_count,
-                   double4 *__restrict__ g_centre, float4 *__restrict__ g_half)
+                   const double4 *__restrict__ p4, const uint32_t *__restrict__ pcl,
+                   uint32_t *__restrict__ g_count, double4 *__restrict__ g_centre,
+                   float4 *__restrict__ g_half)
 {
     constexpr int kSeg = 16;                       // lanes per group
     const int64_t ngroups = m->ngroups;
@@ -518,8 +542,9 @@ group_boxes_kernel(const uint32_t *__restrict__ g_first, const DevMisc *__restri
         }
         if (valid && l == 0) {
             g_count[g] = e - s;
+            // w: the group's cluster, whose root is the level-0 cell of that index
             g_centre[g] = make_double4(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]),
-                                       0.5 * (lo[2] + hi[2]), 0.0);
+                                       0.5 * (lo[2] + hi[2]), (double)pcl[s]);
             g_half[g] = make_float4((float)(0.5 * (hi[0] - lo[0])), (float)(0.5 * (hi[1] - lo[1])),
                                     (float)(0.5 * (hi[2] - lo[2])), 0.0f);
         }
@@ -686,8 +711,8 @@ hipError_t launch_domain(bh_ctx *c, const double *pos_aos)
         hipLaunchKernelGGL(bbox_kernel<P4Src>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
                            c->stream, P4Src{c->p4[c->cur]}, c->chunks, c->bb_part, c->misc);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(domain_kernel, dim3(grid_for(c->K, kBlock)), dim3(kBlock), 0, c->stream,
-                       c->bb_part, c->clus, c->dom, c->K);
+    hipLaunchKernelGGL(domain_kernel, dim3((unsigned)c->K), dim3(kBlock), 0, c->stream, c->bb_part,
+                       c->clus, c->dom);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -766,7 +791,7 @@ hipError_t launch_group_boxes(bh_ctx *c)
     int g = grid_for(c->n, kBlock / 16);
     if (g > kFixedGrid) g = kFixedGrid;
     hipLaunchKernelGGL(group_boxes_kernel, dim3(g), dim3(kBlock), 0, c->stream, c->g_first, c->misc,
-                       c->n, c->p4[c->cur], c->g_count, c->g_centre, c->g_half);
+                       c->n, c->p4[c->cur], c->pcl, c->g_count, c->g_centre, c->g_half);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -84,21 +84,30 @@ energy_partial_kernel(const Chunk *__restrict__ chunks, const double4 *__restric
     if (threadIdx.x < 5) part[5 * (int64_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// One thread per cluster: its chunk partials in chunk order; out[5 cluster + k].
+// One block per cluster: its chunk partials, strided per thread then a tree
+// (a fixed order); out[5 cluster + k].
 __global__ void __launch_bounds__(kBlock)
-energy_final_kernel(const DevCluster *__restrict__ clus, int64_t K, const double *__restrict__ part,
+energy_final_kernel(const DevCluster *__restrict__ clus, const double *__restrict__ part,
                     double *__restrict__ out)
 {
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= K) return;
-    const DevCluster &cl = clus[c];
+    const DevCluster &cl = clus[blockIdx.x];
     double s[5] = {0, 0, 0, 0, 0};
-    for (uint32_t b = cl.chunk0; b < cl.chunk0 + cl.nchunk; ++b) {
+    for (uint32_t b = cl.chunk0 + threadIdx.x; b < cl.chunk0 + cl.nchunk; b += kBlock) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) s[k] += part[5 * (int64_t)b + k];
     }
+    __shared__ double sh[5][kBlock];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) out[5 * c + k] = s[k];
+    for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int d = kBlock / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) out[5 * (int64_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -169,8 +178,8 @@ hipError_t launch_energy(bh_ctx *c)
     hipLaunchKernelGGL(energy_partial_kernel, dim3((unsigned)c->nchunks), dim3(kBlock), 0, c->stream,
                        c->chunks, c->p4[c->cur], c->v4[c->cur], c->acc4, c->e_part);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(energy_final_kernel, dim3(grid_for(c->K)), dim3(kBlock), 0, c->stream,
-                       c->clus, c->K, c->e_part, c->e_out);
+    hipLaunchKernelGGL(energy_final_kernel, dim3((unsigned)c->K), dim3(kBlock), 0, c->stream,
+                       c->clus, c->e_part, c->e_out);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

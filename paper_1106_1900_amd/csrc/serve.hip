@@ -30,13 +30,17 @@ __global__ void __launch_bounds__(kBlock)
 move_kernel(const double4 *__restrict__ p4s, const double4 *__restrict__ v4s,
             const uint32_t *__restrict__ pids, const float4 *__restrict__ accs, uint32_t src,
             double4 *__restrict__ p4d, double4 *__restrict__ v4d, uint32_t *__restrict__ pidd,
-            float4 *__restrict__ accd, uint32_t dst, uint32_t n)
+            float4 *__restrict__ accd, uint32_t dst, uint32_t n, DevMisc *m)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
+    const uint32_t q = pids[src + i];
+    // a cluster's caller indices are its own positions; anything else is an
+    // internal error (bit 3), reported by the next check
+    if (q < src || q - src >= n) atomicOr(&m->nonfinite, 8u);
     p4d[dst + i] = p4s[src + i];
     v4d[dst + i] = v4s[src + i];
-    pidd[dst + i] = pids[src + i] - src + dst;
+    pidd[dst + i] = (q < src || q - src >= n) ? dst + i : q - src + dst;
     accd[dst + i] = accs[src + i];
 }
 
@@ -94,12 +98,17 @@ __global__ void __launch_bounds__(kBlock)
 cluster_out_kernel(const double4 *__restrict__ p4, const double4 *__restrict__ v4,
                    const uint32_t *__restrict__ pid, const float4 *__restrict__ acc4,
                    uint32_t first, uint32_t n, double *__restrict__ pos, double *__restrict__ vel,
-                   float *__restrict__ acc, float *__restrict__ pot)
+                   float *__restrict__ acc, float *__restrict__ pot, DevMisc *m)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const size_t s = first + i;
-    const size_t o = pid[s] - first;
+    const uint32_t q = pid[s];
+    if (q < first || q - first >= n) {     // internal error (bit 3): never write outside
+        atomicOr(&m->nonfinite, 8u);
+        return;
+    }
+    const size_t o = q - first;
     if (pos) {
         const double4 p = p4[s];
         pos[3 * o] = p.x;
@@ -126,6 +135,8 @@ struct Req {
     int64_t ticket;
     int state = BH_REQ_QUEUED;
     int units_done = 0;
+    bool placed = false;     // its particles are in the batch buffers
+    uint32_t first = 0;      // then its first position there
     double arrival = 0, admitted = -1, completed = -1;
     double e0 = 0;
     double energy[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -259,9 +270,9 @@ int admit(bh_server *s, double t)
 }
 
 // Places the resident requests contiguously in cluster order in the other
-// buffer parity: survivors move from their old ranges, new ones load from their
-// arrays.  old_first maps tickets to their first position before the repack.
-int repack(bh_server *s, const std::unordered_map<int64_t, uint32_t> &old_first)
+// buffer parity: survivors move from the ranges they hold, new ones load from
+// their arrays.
+int repack(bh_server *s)
 {
     bh_ctx *c = s->ctx;
     const int src = c->cur, dst = src ^ 1;
@@ -271,17 +282,18 @@ int repack(bh_server *s, const std::unordered_map<int64_t, uint32_t> &old_first)
     for (int64_t t : s->resident) {
         Req &q = s->reqs[t];
         const uint32_t n = (uint32_t)q.r.n;
-        auto it = old_first.find(t);
-        if (it != old_first.end()) {
+        if (q.placed) {
             hipLaunchKernelGGL(move_kernel, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, c->p4[src],
-                               c->v4[src], c->pid[src], c->acc4, it->second, c->p4[dst], c->v4[dst],
-                               c->pid[dst], acc_stage, pos, n);
+                               c->v4[src], c->pid[src], c->acc4, q.first, c->p4[dst], c->v4[dst],
+                               c->pid[dst], acc_stage, pos, n, c->misc);
         } else {
             hipLaunchKernelGGL(load_kernel, dim3(grid_for(n)), dim3(kBlock), 0, c->stream, q.r.pos,
                                q.r.mass, q.r.vel, c->p4[dst], c->v4[dst], c->pid[dst], acc_stage,
                                pos, n);
         }
         S_HIP(s, hipGetLastError());
+        q.placed = true;
+        q.first = pos;
         pos += n;
     }
     if (pos > 0) {
@@ -398,15 +410,6 @@ int bh_server_step(bh_server *s, int64_t *resident)
     if (!s) return BH_EINVAL;
     const double t_in = s->now();
     bh_ctx *c = s->ctx;
-    // positions before this iteration's repack
-    std::unordered_map<int64_t, uint32_t> old_first;
-    {
-        uint32_t f = 0;
-        for (int64_t t : s->resident) {
-            old_first[t] = f;
-            f += (uint32_t)s->reqs[t].r.n;
-        }
-    }
     {
         const int st = admit(s, t_in);
         if (st) return st;
@@ -422,7 +425,7 @@ int bh_server_step(bh_server *s, int64_t *resident)
     bool graph = false;
     if (s->layout_dirty) {
         S_TRY(s, ctx_sync_check(c));
-        int st = repack(s, old_first);
+        int st = repack(s);
         if (st) return st;
         S_TRY(s, ctx_set_layout(c, table, s->resident_n));
         s->layout_dirty = false;
@@ -435,21 +438,20 @@ int bh_server_step(bh_server *s, int64_t *resident)
     }
     S_TRY(s, ctx_step(c, graph));
     // outputs of the requests that finish with this unit
-    uint32_t first = 0;
     std::vector<int64_t> finishing;
     for (int64_t t : s->resident) {
         Req &q = s->reqs[t];
         const uint32_t n = (uint32_t)q.r.n;
+        const uint32_t first = q.first;
         if (q.units_done + 1 >= 1 + q.r.nsteps) {
             finishing.push_back(t);
             if (q.r.out_pos || q.r.out_vel || q.r.out_acc || q.r.out_pot) {
                 hipLaunchKernelGGL(cluster_out_kernel, dim3(grid_for(n)), dim3(kBlock), 0, c->stream,
                                    c->p4[c->cur], c->v4[c->cur], c->pid[c->cur], c->acc4, first, n,
-                                   q.r.out_pos, q.r.out_vel, q.r.out_acc, q.r.out_pot);
+                                   q.r.out_pos, q.r.out_vel, q.r.out_acc, q.r.out_pot, c->misc);
                 S_HIP(s, hipGetLastError());
             }
         }
-        first += n;
     }
     const int64_t K = (int64_t)s->resident.size();
     S_HIP(s, hipMemcpyAsync(c->e_out_h, c->e_out, sizeof(double) * 5 * (size_t)K,

@@ -16,14 +16,18 @@
 //           last-in first-out.  A pop takes up to 64 cells from the top; each pop
 //           pushes at most 64 ranges, all deeper than anything popped before them
 //           that is still held, so at most 64 ranges per level (21 levels, 1344)
-//           can be on it.  The first 256 entries live in LDS; deeper entries go to
-//           a per-wavefront region in device memory (rare: a Plummer sphere of 2^20
+//           can be on it.  The first 128 entries live in LDS; deeper entries go to
+//           a per-wavefront region in device memory (a Plummer sphere of 2^20
 //           particles needs about 50 at theta = 0.75 and 140 at theta = 0.4).
-//   pc    : accepted cells (< 64 between evaluations, 128 entries).
+//   cells : the cell list, already staged as float32 tiles (offset from the
+//           group centre, mass, second moment): a lane that accepts a cell writes
+//           its entry from the record it just read for the opening test, so no
+//           cell record is read twice.  Fewer than 64 entries between
+//           evaluations, plus padding (far away, zero mass) behind the evaluated
+//           tile so that every lane runs the same number of iterations.
 //   pp    : opened leaves as (first particle, count) ranges (< 64 particles
 //           pending between evaluations, so < 128 ranges).
-//   tile  : 64 staged sources plus padding (far away, zero mass) so that every
-//           lane runs the same number of iterations.
+//   tile  : 64 staged particles plus padding.
 //
 // Every pair goes through float32 arithmetic on group-centred offsets; each tile
 // is summed in plain float32 and the tile sums are added to the particle's
@@ -42,13 +46,16 @@ namespace bh {
 namespace {
 
 constexpr int kWalkBlock = kWalkWaves * kWave;
-constexpr int kPcCap = 128;
 constexpr int kPpCap = 128;
-constexpr int kLdsStack = 256;
+constexpr int kLdsStack = 128;
 constexpr int kSpillPerWave = kStackCap - kLdsStack;
-// Lane (p, s) reads tile entries s + t k for t < ceil(cnt / k): at most index 83
-// for k = floor(64 / g); the tail is padding.
-constexpr int kTileCap = 96;
+// Lane (p, s) reads tile entries s + t k for t < ceil(cnt / k): at most 83 past
+// the tile's first entry for k = floor(64 / g); the tail is padding.
+constexpr int kTileReach = 84;
+// The cell list holds fewer than 64 entries between evaluations plus at most 64
+// from one pop; a tile of its last 64 entries is read up to kTileReach past its
+// start.
+constexpr int kPcCap = 63 + kTileReach + 1;
 constexpr float kFar = 1.0e30f;
 #ifndef BH_WALK_UNROLL
 #define BH_WALK_UNROLL 4
@@ -62,11 +69,10 @@ constexpr int kUnroll = BH_WALK_UNROLL;   // tile entries per loop trip
 #endif
 
 struct WalkArgs {
-    const uint32_t *pcl;      // cluster of each particle position
     const DevCluster *clus;   // per-cluster softening
     const uint32_t *g_first;
     const uint32_t *g_count;
-    const double4 *g_centre;
+    const double4 *g_centre;  // box centre; w: the group's cluster (its root cell)
     const float4 *g_half;
     const double4 *p4;        // sources and targets: x, y, z, mass (sorted order)
     const WalkCell *rec;      // per-cell walk records
@@ -79,13 +85,17 @@ struct WalkArgs {
 
 struct WaveLds {
     uint32_t stack[kLdsStack];
-    uint32_t pc[kPcCap];
     uint2 pp[kPpCap];
-    int mark[kWave];
-    float4 ta[kTileCap];      // offset x, y, z; mass
-    float4 tb[kTileCap];      // 3Sxx, 3Syy, 3Szz, 3Sxy
-    float4 tc[kTileCap];      // 3Sxz, 3Syz, tr(S)/2, 3 tr(S)/2
+    // the cell list, staged as it is built
+    float4 ca[kPcCap];        // offset x, y, z; mass
+    float4 cb[kPcCap];        // 3Sxx, 3Syy, 3Szz, 3Sxy
+    float4 cc[kPcCap];        // 3Sxz, 3Syz, tr(S)/2, 3 tr(S)/2
+    union {
+        float4 ta[kTileReach];  // particle tile: offset x, y, z; mass
+        int mark[kWave];        // scratch of pop64 (never live during a particle tile)
+    };
 };
+static_assert(4 * sizeof(WaveLds) * 4 <= 160 * 1024, "four blocks of four wavefronts per CU");
 
 struct Acc {
     float ax, ay, az, ph;     // running sums
@@ -233,21 +243,21 @@ struct Target {
 };
 
 template <bool kEps0>
-__device__ __forceinline__ void run_pc(const WaveLds &L, int cnt, const Target &t, float eps2,
-                                       Acc &acc)
+__device__ __forceinline__ void run_pc(const WaveLds &L, int base, int cnt, const Target &t,
+                                       float eps2, Acc &acc)
 {
     float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
     const int k = t.k;
     const int T = uniform((cnt + k - 1) / k);
-    int j = t.sub;
+    int j = base + t.sub;
     int it = 0;
     for (; it + kUnroll <= T; it += kUnroll) {
         float4 A[kUnroll], B[kUnroll], C[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            A[u] = L.ta[j + u * k];
-            B[u] = L.tb[j + u * k];
-            C[u] = L.tc[j + u * k];
+            A[u] = L.ca[j + u * k];
+            B[u] = L.cb[j + u * k];
+            C[u] = L.cc[j + u * k];
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
@@ -255,7 +265,7 @@ __device__ __forceinline__ void run_pc(const WaveLds &L, int cnt, const Target &
         j += kUnroll * k;
     }
     for (; it < T; ++it) {
-        pc_term<kEps0>(L.ta[j], L.tb[j], L.tc[j], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
+        pc_term<kEps0>(L.ca[j], L.cb[j], L.cc[j], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
         j += k;
     }
     comp_add(acc.ax, acc.cx, ax);
@@ -291,35 +301,25 @@ __device__ __forceinline__ void run_pp(const WaveLds &L, int cnt, const Target &
     comp_add(acc.ph, acc.cp, ph);
 }
 
-// stage up to 64 cells of the cell list and evaluate them
-__device__ __forceinline__ void eval_pc(const WalkArgs &a, WaveLds &L, const uint32_t *list, int cnt,
-                                        const double4 gc, const Target &t, float eps2, Acc &acc)
+// evaluate cnt <= 64 cells of the staged cell list from entry base: the entries
+// a lane may read past them are set to padding (far away, zero mass) first
+template <bool kEps0>
+__device__ __forceinline__ void eval_pc(WaveLds &L, int base, int cnt, const Target &t, float eps2,
+                                        Acc &acc)
 {
     const int lane = lane_id();
-    if (lane < cnt) {
-        const WalkCell *r = a.rec + list[lane];
-        const double4 c0 = *reinterpret_cast<const double4 *>(r);       // cx, cy, cz, (mass, rcrit2)
-        const float2 sa = *reinterpret_cast<const float2 *>(&r->s3[0]);
-        const float4 sb = *reinterpret_cast<const float4 *>(&r->s3[2]);
-        const float mass = r->mass;
-        const float tr3 = (sa.x + sa.y) + sb.x;      // 3 tr(S)
-        L.ta[lane] = make_float4((float)(c0.x - gc.x), (float)(c0.y - gc.y), (float)(c0.z - gc.z), mass);
-        L.tb[lane] = make_float4(sa.x, sa.y, sb.x, sb.y);
-        L.tc[lane] = make_float4(sb.z, sb.w, tr3 * (1.0f / 6.0f), tr3 * 0.5f);
-    } else {
-        L.ta[lane] = make_float4(kFar, kFar, kFar, 0.0f);
-        L.tb[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-        L.tc[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = base + cnt + lane; i < base + kTileReach; i += kWave) {
+        L.ca[i] = make_float4(kFar, kFar, kFar, 0.0f);
+        L.cb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        L.cc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     wave_sync();
-    if (t.sub < t.k) {
-        if (eps2 > 0.0f) run_pc<false>(L, cnt, t, eps2, acc);
-        else run_pc<true>(L, cnt, t, eps2, acc);
-    }
+    if (t.sub < t.k) run_pc<kEps0>(L, base, cnt, t, eps2, acc);
     wave_sync();
 }
 
 // stage up to 64 particles (lane j holds particle index idx) and evaluate them
+template <bool kEps0>
 __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t idx, int cnt,
                                         const double4 gc, const Target &t, float eps2, Acc &acc)
 {
@@ -331,10 +331,7 @@ __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t 
         L.ta[lane] = make_float4(kFar, kFar, kFar, 0.0f);
     }
     wave_sync();
-    if (t.sub < t.k) {
-        if (eps2 > 0.0f) run_pp<false>(L, cnt, t, eps2, acc);
-        else run_pp<true>(L, cnt, t, eps2, acc);
-    }
+    if (t.sub < t.k) run_pp<kEps0>(L, cnt, t, eps2, acc);
     wave_sync();
 }
 
@@ -347,6 +344,9 @@ __device__ __forceinline__ bool next_group(const WalkArgs &a, uint32_t ngroups, 
     return g < ngroups;
 }
 
+// kEps0: some cluster of the launch has zero softening, so pairs at zero
+// distance (a particle with itself) must be skipped explicitly.
+template <bool kEps0>
 __global__ void __launch_bounds__(kWalkBlock)
 __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs a)
 {
@@ -360,12 +360,8 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
     CellStack stack{L.stack, a.spill + wave_global * kSpillPerWave};
     LeafList leaves{L.pp};
 
-    // tile padding beyond the 64 staged entries: far away, zero mass
-    for (int i = kWave + lane; i < kTileCap; i += kWave) {
-        L.ta[i] = make_float4(kFar, kFar, kFar, 0.0f);
-        L.tb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        L.tc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    // particle tile padding beyond its 64 staged entries: far away, zero mass
+    for (int i = kWave + lane; i < kTileReach; i += kWave) L.ta[i] = make_float4(kFar, kFar, kFar, 0.0f);
     wave_sync();
 
     unsigned long long wave_pp = 0, wave_pc = 0;   // interaction totals of this wavefront
@@ -374,11 +370,11 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
     while (next_group(a, ngroups, g)) {
         const uint32_t gs = a.g_first[g];
         const int gn = uniform((int)a.g_count[g]);
-        // the group's cluster: its root is the cluster's level-0 cell
-        const uint32_t cid = readfirst(a.pcl[gs]);
-        const float eps2 = a.clus[cid].eps2;
         const double4 gc = a.g_centre[g];
         const float4 gh = a.g_half[g];
+        // the group's cluster: its root is the cluster's level-0 cell
+        const uint32_t cid = readfirst((uint32_t)gc.w);
+        const float eps2 = a.clus[cid].eps2;
         Target t;
         t.k = uniform(kWave / gn);
         const int p = lane % gn;
@@ -413,26 +409,35 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
             const bool has = lane < got && cell < ncells;
             bool acc_cell = false, leaf = false;
             uint32_t link = 0, info = 0;
+            WalkCell w;
+            float ox = 0.f, oy = 0.f, oz = 0.f;
             if (has) {
-                const WalkCell *r = a.rec + cell;
-                const double4 cm = *reinterpret_cast<const double4 *>(r);
-                const uint2 li = *reinterpret_cast<const uint2 *>(&r->link);
-                const float rc2 = r->rcrit2;
-                link = li.x;
-                info = li.y;
-                const float dx = fabsf((float)(cm.x - gc.x)) - gh.x;
-                const float dy = fabsf((float)(cm.y - gc.y)) - gh.y;
-                const float dz = fabsf((float)(cm.z - gc.z)) - gh.z;
+                w = a.rec[cell];
+                link = w.link;
+                info = w.info;
+                ox = (float)(w.cx - gc.x);
+                oy = (float)(w.cy - gc.y);
+                oz = (float)(w.cz - gc.z);
+                const float dx = fabsf(ox) - gh.x;
+                const float dy = fabsf(oy) - gh.y;
+                const float dz = fabsf(oz) - gh.z;
                 const float ux = dx > 0.0f ? dx : 0.0f;
                 const float uy = dy > 0.0f ? dy : 0.0f;
                 const float uz = dz > 0.0f ? dz : 0.0f;
                 const float d2 = (ux * ux + uy * uy) + uz * uz;
-                acc_cell = d2 > rc2;
+                acc_cell = d2 > w.rcrit2;
                 leaf = (info >> 31) != 0u;
             }
-            // accepted cells -> cell list
+            // accepted cells -> cell list, staged for evaluation at once (offset
+            // from the group centre, mass, 3 S and the trace terms)
             const unsigned long long bpc = ballot(has && acc_cell);
-            if (has && acc_cell) L.pc[pc_n + mask_rank(bpc)] = cell;
+            if (has && acc_cell) {
+                const int i = pc_n + mask_rank(bpc);
+                const float tr3 = (w.s3[0] + w.s3[1]) + w.s3[2];     // 3 tr(S)
+                L.ca[i] = make_float4(ox, oy, oz, w.mass);
+                L.cb[i] = make_float4(w.s3[0], w.s3[1], w.s3[2], w.s3[3]);
+                L.cc[i] = make_float4(w.s3[4], w.s3[5], tr3 * (1.0f / 6.0f), tr3 * 0.5f);
+            }
             pc_n += __popcll(bpc);
             npc += (uint32_t)__popcll(bpc);
             // opened leaves -> particle list
@@ -455,8 +460,8 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
                 top += nn;
             }
             stack.sync();
-            while (pc_n >= kWave) {
-                eval_pc(a, L, L.pc + (pc_n - kWave), kWave, gc, t, eps2, acc);
+            if (pc_n >= kWave) {     // pc_n < 128: one tile of the last 64 entries
+                eval_pc<kEps0>(L, pc_n - kWave, kWave, t, eps2, acc);
                 pc_n -= kWave;
             }
             while (pend >= (uint32_t)kWave) {
@@ -467,12 +472,12 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
                     pend = 0;
                     break;
                 }
-                eval_pp(a, L, idx, n, gc, t, eps2, acc);
+                eval_pp<kEps0>(a, L, idx, n, gc, t, eps2, acc);
                 pend -= (uint32_t)n;
             }
             if (overflow) break;
         }
-        if (pc_n > 0) eval_pc(a, L, L.pc, pc_n, gc, t, eps2, acc);
+        if (pc_n > 0) eval_pc<kEps0>(L, 0, pc_n, t, eps2, acc);
         while (pend > 0) {
             uint32_t idx;
             const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx) : 0;
@@ -480,7 +485,7 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
                 overflow = true;
                 break;
             }
-            eval_pp(a, L, idx, n, gc, t, eps2, acc);
+            eval_pp<kEps0>(a, L, idx, n, gc, t, eps2, acc);
             pend -= (uint32_t)n < pend ? (uint32_t)n : pend;
         }
 
@@ -506,7 +511,7 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
         if (t.sub == 0 && lane < gn) {
             // the particle met itself once in the particle list: with eps > 0 that
             // term added -m/eps to the potential and nothing to the acceleration
-            if (eps2 > 0.0f) ph = ph + mi * __builtin_amdgcn_rsqf(eps2);
+            if (!kEps0 || eps2 > 0.0f) ph = ph + mi * __builtin_amdgcn_rsqf(eps2);
             a.acc4[gs + lane] = make_float4(ax, ay, az, ph);
         }
         if (lane == 0) {
@@ -616,7 +621,6 @@ hipError_t launch_walk(bh_ctx *c, bool timed)
     if (blocks * kWalkWaves > c->walk_spill_waves) blocks = c->walk_spill_waves / kWalkWaves;
     if (blocks < 1) return hipErrorInvalidValue;
     WalkArgs a;
-    a.pcl = c->pcl;
     a.clus = c->clus;
     a.g_first = c->g_first;
     a.g_count = c->g_count;
@@ -631,7 +635,10 @@ hipError_t launch_walk(bh_ctx *c, bool timed)
     a.misc = c->misc;
     hipEvent_t *ev = timed ? walk_timer_slot(c) : nullptr;
     if (ev) BH_HIP_TRY(hipEventRecord(ev[0], c->stream));
-    hipLaunchKernelGGL(walk_kernel, dim3((unsigned)blocks), dim3(kWalkBlock), 0, c->stream, a);
+    if (c->any_eps0)
+        hipLaunchKernelGGL(walk_kernel<true>, dim3((unsigned)blocks), dim3(kWalkBlock), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL(walk_kernel<false>, dim3((unsigned)blocks), dim3(kWalkBlock), 0, c->stream, a);
     BH_LAUNCH_CHECK();
     if (ev) BH_HIP_TRY(hipEventRecord(ev[1], c->stream));
     return hipSuccess;

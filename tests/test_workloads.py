@@ -39,3 +39,44 @@ def test_plummer_is_seeded_and_reproducible():
     c = workloads.plummer(1000, 5)
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
     assert not np.array_equal(a[0], c[0])
+
+
+def test_hernquist_follows_its_mass_profile():
+    pos, vel, m = workloads.hernquist(200_000, 9, a=1.0)
+    assert m.sum() == pytest.approx(1.0)
+    r = np.linalg.norm(pos, axis=1)
+    for r0 in (0.3, 1.0, 3.0, 10.0):      # M(<r) = r^2 / (r + a)^2, truncated at 99%
+        assert np.mean(r < r0) == pytest.approx((r0 / (r0 + 1.0)) ** 2 / 0.99, abs=0.01)
+    # isotropic Jeans dispersions: virial ratio 2T/|W| near 1 for the whole sphere
+    # (truncation and sampling noise allowed); W from the analytic potential energy
+    # -1/(6a) of the untruncated model
+    T = 0.5 * np.sum(m * np.sum(vel * vel, axis=1))
+    assert 2 * T / (1.0 / 6.0) == pytest.approx(1.0, abs=0.1)
+
+
+def test_cluster_batch_sizes_and_softening():
+    sizes = workloads.cluster_sizes(512, 4)
+    assert sizes.min() >= 1024 and sizes.max() < 65536
+    # log-uniform: E[N] = (65536 - 1024) / ln 64 = 15,512
+    assert sizes.mean() == pytest.approx(15512, rel=0.15)
+    b = workloads.cluster_batch(8, 4)
+    assert [q["n"] for q in b] == list(sizes[:8])
+    for q in b:
+        assert q["pos"].shape == (q["n"], 3) and q["theta"] == 0.75
+        assert q["eps"] == pytest.approx(0.04 * q["n"] ** (-1 / 3))
+    # clusters are independent draws
+    assert not np.array_equal(b[0]["pos"][:10], b[1]["pos"][:10])
+
+
+def test_request_trace_is_poisson():
+    tr = workloads.request_trace(4000, 200.0, 5)
+    t = np.array([q["arrival"] for q in tr])
+    gaps = np.diff(t)
+    assert np.all(gaps > 0)
+    assert gaps.mean() == pytest.approx(1 / 200, rel=0.05)
+    assert np.std(gaps) == pytest.approx(1 / 200, rel=0.1)       # exponential: sd = mean
+    n = np.array([q["n"] for q in tr])
+    assert n.min() >= 1024 and n.max() <= 2097152
+    assert np.mean(np.log(n)) == pytest.approx((np.log(1024) + np.log(2097152)) / 2, rel=0.02)
+    assert {q["shape"] for q in tr} == {"plummer", "hernquist"}
+    assert {q["theta"] for q in tr} == {0.5, 0.75}

@@ -103,7 +103,7 @@ def cpu_baseline(pos, mass, theta, eps, budget_s):
     }
 
 
-def accuracy_sample(pos, mass, acc_gpu, eps, ntarget=256):
+def accuracy_sample(pos, mass, acc_gpu, eps, ntarget=1024):
     """Relative acceleration error (Eq. (2)) of the GPU forces against the oracle's
     float64 direct summation on seeded targets."""
     import numpy as np
@@ -130,7 +130,7 @@ def calib_copy():
     log("calib copy done: 1 GiB read + 1 GiB write per copy, 3 copies")
 
 
-def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4):
+def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4, alone=True):
     """Sum of N_i over a step of all k clusters, batched (one forest, graph replay)
     against one context per cluster stepped in turn."""
     import numpy as np
@@ -175,6 +175,23 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4):
     t_tuned = (time.perf_counter() - t0) / steps
     ctx.close()
 
+    out = {
+        "workload": "%d Plummer clusters, N log-uniform in [1024, 65536] (sum %d), theta 0.75, "
+                    "eps 0.04 N^-1/3, dt %g, nleaf 16, group 64" % (k, ntot, dt),
+        "clusters": k, "particles": ntot, "steps": steps,
+        "value": ntot / t_batch, "unit": "particles/s",
+        "ms_per_step": 1e3 * t_batch,
+        "max_abs_energy_error": float(np.abs(en[:, 6]).max()),
+        "graph_launches": int(st.graph_launches),
+        "tuned_value": ntot / t_tuned,
+        "tuned_ms_per_step": 1e3 * t_tuned,
+        "autotune_seconds": t_tune,
+        "tuning": [{"log2n": t["log2n"], "theta": round(t["theta"], 6), "nleaf": t["nleaf"],
+                    "ncrit": t["ncrit"], "ms": round(t["ms"], 4),
+                    "ms_default": round(t["ms_default"], 4)} for t in table],
+    }
+    if not alone:
+        return out
     log("stepping the %d clusters one context at a time" % k)
     ones = []
     first = 0
@@ -198,24 +215,12 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4):
     t_one = (time.perf_counter() - t0) / steps
     for c1 in ones:
         c1.close()
-    return {
-        "workload": "%d Plummer clusters, N log-uniform in [1024, 65536] (sum %d), theta 0.75, "
-                    "eps 0.04 N^-1/3, dt %g, nleaf 16, group 64" % (k, ntot, dt),
-        "clusters": k, "particles": ntot, "steps": steps,
-        "value": ntot / t_batch, "unit": "particles/s",
-        "ms_per_step": 1e3 * t_batch,
+    out.update({
         "one_at_a_time_particles_per_s": ntot / t_one,
         "one_at_a_time_ms_per_step": 1e3 * t_one,
         "speedup_vs_one_at_a_time": t_one / t_batch,
-        "max_abs_energy_error": float(np.abs(en[:, 6]).max()),
-        "graph_launches": int(st.graph_launches),
-        "tuned_value": ntot / t_tuned,
-        "tuned_ms_per_step": 1e3 * t_tuned,
-        "autotune_seconds": t_tune,
-        "tuning": [{"log2n": t["log2n"], "theta": round(t["theta"], 6), "nleaf": t["nleaf"],
-                    "ncrit": t["ncrit"], "ms": round(t["ms"], 4),
-                    "ms_default": round(t["ms_default"], 4)} for t in table],
-    }
+    })
+    return out
 
 
 def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
@@ -315,6 +320,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gib", type=float, default=0.0,
                     help="device memory for the server (0: 60%% of the free memory)")
+    ap.add_argument("--serve-small-budget-gib", type=float, default=4.0,
+                    help="a second, constrained budget for the same trace (0: skip)")
+    ap.add_argument("--only", choices=("batch", "serve"),
+                    help="run only that form and print its JSON (for profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -331,6 +340,13 @@ def main():
 
     if args.calib_copy:
         calib_copy()
+    if args.only == "batch":
+        print(json.dumps(bench_batch(args.batch_clusters, args.batch_steps, 2, alone=False)), flush=True)
+        return
+    if args.only == "serve":
+        budget = int(args.serve_budget_gib * (1 << 30)) or int(0.6 * torch.cuda.mem_get_info()[0])
+        print(json.dumps(bench_serve(args.serve_requests, args.serve_rate, budget)), flush=True)
+        return
 
     n = args.n
     log("generating Plummer N=%d" % n)
@@ -354,14 +370,20 @@ def main():
     s0 = ctx.stats()
 
     log("timing %d steps" % args.steps)
+    # one event between consecutive steps on the context's stream (the current
+    # stream at its creation) for the per-step distribution
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     # each step computes the energy sums on the device; they are read back once
     # at the end
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         ctx.leapfrog_step(args.dt)
+        evs[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     s1 = ctx.stats()
     e1 = ctx.energy()
     # the same steps replayed from a captured graph (no per-kernel host launches)
@@ -413,6 +435,7 @@ def main():
         "roofline": roofline,
         "interactions_per_s": (pp + pc) * launches / elapsed,
         "phases_ms_last_step": {k: round(v, 4) for k, v in phases.items()},
+        "step_ms_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
         "graph_replay_ms_per_step": graph_ms,
         "energy_error_over_timed_steps": float((e0[2] - e1[2]) / e0[2]),
         "tree": {"ncells": s1.ncells, "ngroups": s1.ngroups, "depth": s1.depth},
@@ -428,6 +451,11 @@ def main():
             budget = int(0.6 * torch.cuda.mem_get_info()[0])
         log("serving %d requests" % args.serve_requests)
         out["served"] = bench_serve(args.serve_requests, args.serve_rate, budget)
+        # the same trace under a budget that makes requests wait for admission
+        small = int(args.serve_small_budget_gib * (1 << 30))
+        if small > 0:
+            log("serving %d requests in %.1f GiB" % (args.serve_requests, args.serve_small_budget_gib))
+            out["served_constrained"] = bench_serve(args.serve_requests, args.serve_rate, small)
     if not args.no_accuracy:
         out["accuracy_vs_direct"] = accuracy_sample(pos, mass, acc0_h, args.eps)
     if args.cpu_budget > 0 and rank == 0:

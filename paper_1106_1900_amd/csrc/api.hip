@@ -632,6 +632,11 @@ int64_t ctx_bytes_for(bh_ctx *c, int64_t n, int64_t K, int nleaf_min)
     return bytes_for(c, sizes_for(c, n, K, nleaf_min));
 }
 
+bool ctx_cells_fit(int64_t n, int64_t K, int nleaf_min)
+{
+    return cell_bound(n, K, nleaf_min) < ((int64_t)1 << 29);
+}
+
 int ctx_reserve(bh_ctx *c, int64_t n, int64_t K, int nleaf_min)
 {
     return ensure_capacity(c, n, K, nleaf_min);

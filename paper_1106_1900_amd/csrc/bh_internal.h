@@ -242,6 +242,7 @@ int ctx_fail(bh_ctx *c, int code, const char *msg);
 int ctx_hip_fail(bh_ctx *c, hipError_t e, const char *where);
 int64_t ctx_bytes_for(bh_ctx *c, int64_t n, int64_t K, int nleaf_min);
 int ctx_reserve(bh_ctx *c, int64_t n, int64_t K, int nleaf_min);
+bool ctx_cells_fit(int64_t n, int64_t K, int nleaf_min);   // cell indices fit 29 bits
 int ctx_check_clusters(bh_ctx *c, const bh_cluster *cl, int64_t K, std::vector<bh_cluster> &out,
                        int64_t *total);
 int ctx_set_layout(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n);

@@ -334,12 +334,15 @@ int bh_server_create(bh_server **out, const bh_server_params *p, void *hip_strea
         return st;
     }
     // the largest resident particle count whose buffers fit the budget, with the
-    // smallest leaf size a request may choose
+    // smallest leaf size a request may choose, and whose cell indices fit the walk
     int64_t lo = 0, hi = 0x7fffffffLL;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo + 1) / 2;
-        if (ctx_bytes_for(s->ctx, mid, p->max_requests, lmin) <= p->hbm_budget_bytes) lo = mid;
-        else hi = mid - 1;
+        if (ctx_cells_fit(mid, p->max_requests, lmin) &&
+            ctx_bytes_for(s->ctx, mid, p->max_requests, lmin) <= p->hbm_budget_bytes)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
     if (lo < 1) {
         bh_destroy(s->ctx);

@@ -89,14 +89,15 @@ def compare_forces(acc, pot, t, theta, eps, groups=None):
     return float((da / np.maximum(aabs, 1e-300)).max())
 
 
-def split_forest(ex, sizes):
+def split_forest(ex, sizes, selected=None):
     """Per-cluster views of a batch's exported forest: particle, cell and group
     indices renumbered from 0 within each cluster (cells keep their relative
-    order, which is (level, key prefix) order within the cluster)."""
+    order, which is (level, key prefix) order within the cluster).  selected:
+    indices of the clusters to return (default all)."""
     out = []
-    first = 0
-    for n in sizes:
-        lo, hi = first, first + n
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    for c in (range(len(sizes)) if selected is None else selected):
+        lo, hi = int(starts[c]), int(starts[c] + sizes[c])
         cm = (ex["first"] >= lo) & (ex["first"] < hi)
         idx = np.nonzero(cm)[0]
         local = np.full(ex["first"].shape[0], -1, np.int64)
@@ -113,5 +114,4 @@ def split_forest(ex, sizes):
         for k in ("gcount", "gcentre", "ghalf", "npp", "npc"):
             d[k] = ex[k][gm]
         out.append(d)
-        first = hi
     return out

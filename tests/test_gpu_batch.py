@@ -256,3 +256,48 @@ def test_autotune_table_and_tuned_build():
             compare_tree(d, tree)
             compare_walk(d, tree, prm["theta"])
         c.close()
+
+
+def test_batch_512_full_size_sampled_clusters():
+    # the full batched workload (512 clusters, 8.8 M particles) through the
+    # captured step with dt = 0 (rebuild and forces at the same positions), as the
+    # bench runs it; sampled clusters against their oracle trees, and properties
+    # of the whole forest
+    import paper_1106_1900_amd as bh
+    import torch
+    cl = workloads.cluster_batch(512, 4)
+    sizes = [q["n"] for q in cl]
+    say("case batch512", sum(sizes))
+    table = [dict(n=q["n"], theta=q["theta"], eps=q["eps"], dt=0.0) for q in cl]
+    ctx = bh.Context()
+    ctx.batch_build(table, to_dev(np.concatenate([q["pos"] for q in cl])),
+                    to_dev(np.concatenate([q["mass"] for q in cl])),
+                    to_dev(np.concatenate([q["vel"] for q in cl])))
+    ctx.batch_forces(want=False)
+    ctx.batch_run(2)
+    x, v, a, p = [t.cpu().numpy() for t in ctx.get_state()]
+    torch.cuda.synchronize()
+    ex = ctx.export_tree()
+    K = len(cl)
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    assert np.array_equal(ex["level"][:K], np.zeros(K)) and np.array_equal(ex["first"][:K], starts)
+    assert np.array_equal(ex["count"][:K], sizes)
+    # groups partition every cluster's range and never cross a cluster boundary
+    gend = ex["gfirst"] + ex["gcount"]
+    assert np.array_equal(ex["gfirst"][1:], gend[:-1]) and gend[-1] == sum(sizes)
+    assert np.all(np.searchsorted(starts, ex["gfirst"], "right") ==
+                  np.searchsorted(starts, gend - 1, "right"))
+    rng = np.random.default_rng(44)
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))} |
+                  set(rng.choice(K, 4, replace=False).tolist()))
+    views = split_forest(ex, sizes, pick)
+    for c, d in zip(pick, views):
+        q = cl[c]
+        s = slice(int(starts[c]), int(starts[c] + q["n"]))
+        assert np.array_equal(x[s], q["pos"])     # dt = 0 leaves positions as they are
+        say("cluster", c, q["n"])
+        t = oracle.Tree(q["pos"], q["mass"])
+        compare_tree(d, t)
+        compare_walk(d, t, q["theta"])
+        compare_forces(a[s], p[s], t, q["theta"], q["eps"])
+    ctx.close()

@@ -33,6 +33,7 @@ def _alone(q):
     ctx.build_tree(to_dev(q["pos"]), to_dev(q["mass"]))
     ctx.set_velocities(to_dev(q["vel"]))
     ctx.compute_forces(q["theta"], q["eps"], want=False)
+    ctx.energy()        # E0 after the force evaluation, as the server takes it
     for _ in range(q["nsteps"]):
         ctx.leapfrog_step(q["dt"])
     out = [t.cpu().numpy() for t in ctx.get_state()]
@@ -145,4 +146,20 @@ def test_bad_request_is_rejected_alone():
     assert srv.stats()["rejected"] == 1
     with pytest.raises(bh.BHError):
         srv.submit(to_dev(reqs[0]["pos"]), to_dev(reqs[0]["mass"]), theta=0.0)
+    srv.close()
+
+
+def test_largest_request_alone_and_in_the_mix():
+    # a request at the largest size of the served workload (2^21 particles)
+    # served beside two small ones ends bit-identical to the same request alone
+    reqs = _requests()[:2]
+    p, v, m = workloads.hernquist(1 << 21, 7)
+    big = dict(pos=p, vel=v, mass=m, theta=0.5, eps=0.01, dt=1 / 128, nsteps=1, nleaf=16, ncrit=64)
+    say("case serve-large", 1 << 21)
+    srv, tickets, outs, _ = _serve([reqs[0], big, reqs[1]], 8 << 30)
+    assert [srv.poll(t)["state"] for t in tickets] == [2, 2, 2]
+    (x, vv, a, pp), _ = _alone(big)
+    got = [z.cpu().numpy() for z in outs[1]]
+    for g, w in zip(got, (x, vv, a, pp)):
+        assert np.array_equal(g, w)
     srv.close()

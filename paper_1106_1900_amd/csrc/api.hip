@@ -475,8 +475,7 @@ hipError_t enqueue_step(bh_ctx *c)
     BH_HIP_TRY(launch_kick_drift(c));
     BH_HIP_TRY(enqueue_rebuild(c));
     BH_HIP_TRY(enqueue_forces(c, nullptr, nullptr));
-    BH_HIP_TRY(launch_kick(c));
-    BH_HIP_TRY(launch_energy(c));
+    BH_HIP_TRY(launch_kick_energy(c));
     return hipSuccess;
 }
 

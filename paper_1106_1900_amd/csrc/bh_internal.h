@@ -93,6 +93,8 @@ struct DevMisc {
     uint32_t ngroups;
     uint32_t depth;
     uint32_t walk_next;                // group work counter of the walk
+    uint32_t levels_done;              // levels scanned in the current build (self-clearing)
+    uint32_t pad1;
     uint32_t walk_overflow;            // set if a per-wave list would overflow
     unsigned long long sum_npp;
     unsigned long long sum_npc;
@@ -252,9 +254,9 @@ int ctx_sync_check(bh_ctx *c);
 int ctx_log2_floor(int64_t n);
 
 // integrate.hip (per-cluster dt from the cluster table)
-hipError_t launch_kick(bh_ctx *c);
 hipError_t launch_kick_drift(bh_ctx *c);
 hipError_t launch_energy(bh_ctx *c);
+hipError_t launch_kick_energy(bh_ctx *c);          // closing kick fused with the energy sums
 hipError_t launch_set_velocities(bh_ctx *c, const double *vel);
 hipError_t launch_get_state(bh_ctx *c, double *pos, double *vel, float *acc, float *pot);
 hipError_t launch_set_positions(bh_ctx *c, const double *pos, const double *vel);

@@ -77,15 +77,6 @@ inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block
 
 // ---------------------------------------------------------------------------
 
-// counts of the build; the error bits stay until the host clears them
-__global__ void misc_reset_kernel(DevMisc *m)
-{
-    if (threadIdx.x == 0) {
-        m->nleaves = 0;
-        m->ngroups = 0;
-        m->ncells = 0;
-    }
-}
 
 struct AosSrc {
     const double *p;
@@ -121,6 +112,14 @@ template <typename Src>
 __global__ void __launch_bounds__(kBlock)
 bbox_kernel(Src src, const Chunk *__restrict__ chunks, double *__restrict__ part, DevMisc *m)
 {
+    // the first kernel of a build also clears the build's counts (the error bits
+    // stay until the host reads and clears them)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        m->nleaves = 0;
+        m->ngroups = 0;
+        m->ncells = 0;
+        m->levels_done = 0;
+    }
     const Chunk ch = chunks[blockIdx.x];
     double lo[3] = {INFINITY, INFINITY, INFINITY};
     double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -280,8 +279,8 @@ __device__ __forceinline__ uint8_t split_level(uint64_t a, uint64_t b)
 __global__ void __launch_bounds__(kTreeTile)
 split_leaf_kernel(const uint64_t *__restrict__ key, const uint32_t *__restrict__ pcl, int64_t n,
                   int H, const DevCluster *__restrict__ clus, uint8_t *__restrict__ split,
-                  uint8_t *__restrict__ lam, uint32_t *__restrict__ blk, int nblk,
-                  DevMisc *__restrict__ m)
+                  uint8_t *__restrict__ lam, uint8_t *__restrict__ gflag, uint32_t *__restrict__ blk,
+                  int nblk, DevMisc *__restrict__ m)
 {
     extern __shared__ uint8_t s_dyn[];
     const int W = kTreeTile + 2 * H;              // split values held in LDS
@@ -332,6 +331,7 @@ split_leaf_kernel(const uint64_t *__restrict__ key, const uint32_t *__restrict__
         lm = best > kMaxLevel ? (uint8_t)kMaxLevel : best;
         split[i] = sp;
         lam[i] = lm;
+        gflag[i] = 0;       // group starts are flagged later by cell_ends_kernel
     }
     // count starts per level
     const int l = t % kWave;
@@ -348,8 +348,34 @@ split_leaf_kernel(const uint64_t *__restrict__ key, const uint32_t *__restrict__
     if (t == 0 && s_leaves) atomicAdd(&m->nleaves, s_leaves);
 }
 
-// one block per level: exclusive scan of the level's block counts in place
-__global__ void scan_levels_kernel(uint32_t *__restrict__ blk, int nblk, uint32_t *__restrict__ tot)
+// level counts -> level offsets (level-major order), total cells, depth.
+__device__ void level_finalize(const uint32_t *__restrict__ tot, DevMisc *m, int64_t cap_c)
+{
+    uint64_t off = 0;
+    uint32_t depth = 0;
+    uint32_t cnt[kLevels];
+    for (int l = 0; l < kLevels; ++l) {
+        cnt[l] = __hip_atomic_load(&tot[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        m->level_offset[l] = (uint32_t)off;
+        m->level_count[l] = cnt[l];
+        if (cnt[l]) depth = (uint32_t)l;
+        off += cnt[l];
+    }
+    if (off > (uint64_t)cap_c) {
+        // cannot happen for a consistent tree; keep every later write in bounds
+        m->nonfinite |= 4u;
+        for (int l = 0; l < kLevels; ++l) m->level_count[l] = 0;
+        off = 0;
+    }
+    m->level_offset[kLevels] = (uint32_t)off;
+    m->ncells = (uint32_t)off;
+    m->depth = depth;
+}
+
+// one block per level: exclusive scan of the level's block counts in place; the
+// last block to finish derives the level offsets
+__global__ void scan_levels_kernel(uint32_t *__restrict__ blk, int nblk, uint32_t *__restrict__ tot,
+                                   DevMisc *m, int64_t cap_c)
 {
     __shared__ uint32_t s_tmp[4];
     uint32_t *row = blk + (int64_t)blockIdx.x * nblk;
@@ -370,30 +396,16 @@ __global__ void scan_levels_kernel(uint32_t *__restrict__ blk, int nblk, uint32_
         if (b < nblk) row[b] = run + off + inc - v;
         run += tot4;
     }
-    if (t == 0) tot[blockIdx.x] = run;
-}
-
-// level counts -> level offsets (level-major order), total cells, depth.
-__global__ void level_finalize_kernel(const uint32_t *__restrict__ tot, DevMisc *m, int64_t cap_c)
-{
-    if (threadIdx.x != 0) return;
-    uint64_t off = 0;
-    uint32_t depth = 0;
-    for (int l = 0; l < kLevels; ++l) {
-        m->level_offset[l] = (uint32_t)off;
-        m->level_count[l] = tot[l];
-        if (tot[l]) depth = (uint32_t)l;
-        off += tot[l];
+    if (t == 0) {
+        __hip_atomic_store(&tot[blockIdx.x], run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // release this level's total, then count the finished levels
+        const uint32_t done = __hip_atomic_fetch_add(&m->levels_done, 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {
+            level_finalize(tot, m, cap_c);
+            m->levels_done = 0;      // ready for the next build
+        }
     }
-    if (off > (uint64_t)cap_c) {
-        // cannot happen for a consistent tree; keep every later write in bounds
-        m->nonfinite |= 4u;
-        for (int l = 0; l < kLevels; ++l) m->level_count[l] = 0;
-        off = 0;
-    }
-    m->level_offset[kLevels] = (uint32_t)off;
-    m->ncells = (uint32_t)off;
-    m->depth = depth;
 }
 
 // For every level, the index of the cell of that level holding particle i
@@ -566,6 +578,65 @@ __device__ __forceinline__ void store_walk_multipole(uint32_t c, const double *S
                         (float)(1.5 * tr));
 }
 
+// Moments of cell c: a leaf from its particles, a node from its children (one
+// level deeper, already done), both in array order.
+template <bool kLeaf>
+__device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restrict__ c_first,
+                                             const uint32_t *__restrict__ c_count,
+                                             const uint32_t *__restrict__ c_child,
+                                             const uint32_t *__restrict__ c_nchild,
+                                             const double4 *__restrict__ p4,
+                                             double4 *__restrict__ c_com, double *__restrict__ c_S,
+                                             float4 *__restrict__ q0, float4 *__restrict__ q1)
+{
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    double S[6] = {0, 0, 0, 0, 0, 0};
+    double cx, cy, cz;
+    if (kLeaf) {
+        const uint32_t s = c_first[c], e = s + c_count[c];
+        for (uint32_t j = s; j < e; ++j) M = M + p4[j].w;
+        for (uint32_t j = s; j < e; ++j) {
+            const double4 p = p4[j];
+            sx = sx + p.w * p.x;
+            sy = sy + p.w * p.y;
+            sz = sz + p.w * p.z;
+        }
+        cx = sx / M;
+        cy = sy / M;
+        cz = sz / M;
+        for (uint32_t j = s; j < e; ++j) {
+            const double4 p = p4[j];
+            const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+            S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
+            S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
+        }
+    } else {
+        const uint32_t s = c_child[c], e = s + c_nchild[c];
+        for (uint32_t k = s; k < e; ++k) M = M + c_com[k].w;
+        for (uint32_t k = s; k < e; ++k) {
+            const double4 q = c_com[k];
+            sx = sx + q.w * q.x;
+            sy = sy + q.w * q.y;
+            sz = sz + q.w * q.z;
+        }
+        cx = sx / M;
+        cy = sy / M;
+        cz = sz / M;
+        for (uint32_t k = s; k < e; ++k) {
+            const double4 q = c_com[k];
+            const double ex = q.x - cx, ey = q.y - cy, ez = q.z - cz;
+            const double *Sk = c_S + 6 * (int64_t)k;
+            S[0] += Sk[0] + q.w * ex * ex; S[1] += Sk[1] + q.w * ey * ey;
+            S[2] += Sk[2] + q.w * ez * ez; S[3] += Sk[3] + q.w * ex * ey;
+            S[4] += Sk[4] + q.w * ex * ez; S[5] += Sk[5] + q.w * ey * ez;
+        }
+    }
+    c_com[c] = make_double4(cx, cy, cz, M);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)c + k] = S[k];
+    store_walk_multipole(c, S, q0, q1);
+}
+
 // kLeaves: every leaf of the tree (any level); otherwise the nodes of one level.
 template <bool kLeaves>
 __global__ void __launch_bounds__(kBlock)
@@ -581,52 +652,32 @@ moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restri
         const uint32_t c = begin + t;
         const bool leaf = c_leaf[c] != 0;
         if (leaf != kLeaves) continue;
-        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-        double S[6] = {0, 0, 0, 0, 0, 0};
-        double cx, cy, cz;
-        if (kLeaves) {
-            const uint32_t s = c_first[c], e = s + c_count[c];
-            for (uint32_t j = s; j < e; ++j) M = M + p4[j].w;
-            for (uint32_t j = s; j < e; ++j) {
-                const double4 p = p4[j];
-                sx = sx + p.w * p.x;
-                sy = sy + p.w * p.y;
-                sz = sz + p.w * p.z;
-            }
-            cx = sx / M;
-            cy = sy / M;
-            cz = sz / M;
-            for (uint32_t j = s; j < e; ++j) {
-                const double4 p = p4[j];
-                const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
-                S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
-                S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
-            }
-        } else {
-            const uint32_t s = c_child[c], e = s + c_nchild[c];
-            for (uint32_t k = s; k < e; ++k) M = M + c_com[k].w;
-            for (uint32_t k = s; k < e; ++k) {
-                const double4 q = c_com[k];
-                sx = sx + q.w * q.x;
-                sy = sy + q.w * q.y;
-                sz = sz + q.w * q.z;
-            }
-            cx = sx / M;
-            cy = sy / M;
-            cz = sz / M;
-            for (uint32_t k = s; k < e; ++k) {
-                const double4 q = c_com[k];
-                const double ex = q.x - cx, ey = q.y - cy, ez = q.z - cz;
-                const double *Sk = c_S + 6 * (int64_t)k;
-                S[0] += Sk[0] + q.w * ex * ex; S[1] += Sk[1] + q.w * ey * ey;
-                S[2] += Sk[2] + q.w * ez * ez; S[3] += Sk[3] + q.w * ex * ey;
-                S[4] += Sk[4] + q.w * ex * ez; S[5] += Sk[5] + q.w * ey * ez;
-            }
+        cell_moments<kLeaves>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S, q0, q1);
+    }
+}
+
+// The nodes of levels hi down to lo in one workgroup, a barrier between levels:
+// for runs of levels holding few cells, where a launch per level would cost more
+// than the work.
+constexpr int kLevelsBlock = 1024;
+
+__global__ void __launch_bounds__(kLevelsBlock)
+moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
+                      const uint8_t *__restrict__ c_leaf, const uint32_t *__restrict__ c_first,
+                      const uint32_t *__restrict__ c_count, const uint32_t *__restrict__ c_child,
+                      const uint32_t *__restrict__ c_nchild, const double4 *__restrict__ p4,
+                      double4 *__restrict__ c_com, double *__restrict__ c_S,
+                      float4 *__restrict__ q0, float4 *__restrict__ q1)
+{
+    for (int level = hi; level >= lo; --level) {
+        const uint32_t begin = m->level_offset[level];
+        const uint32_t count = m->level_count[level];
+        for (uint32_t t = threadIdx.x; t < count; t += kLevelsBlock) {
+            const uint32_t c = begin + t;
+            if (c_leaf[c] == 0)
+                cell_moments<false>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S, q0, q1);
         }
-        c_com[c] = make_double4(cx, cy, cz, M);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)c + k] = S[k];
-        store_walk_multipole(c, S, q0, q1);
+        __syncthreads();
     }
 }
 
@@ -635,7 +686,7 @@ moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restri
 // together with the rest of the cell's walk record.  theta and the domain are
 // those of the cell's cluster.
 __global__ void __launch_bounds__(kBlock)
-rcrit_kernel(const DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
+rcrit_kernel(DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
              const DevDomain *__restrict__ dom, const uint32_t *__restrict__ pcl, const uint8_t *__restrict__ c_level,
              const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
              const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
@@ -643,6 +694,12 @@ rcrit_kernel(const DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
              const double4 *__restrict__ c_com, const float4 *__restrict__ q0,
              const float4 *__restrict__ q1, float *__restrict__ rcrit2, WalkCell *__restrict__ rec)
 {
+    // the walk that follows takes its groups from a counter cleared here
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        m->walk_next = 0;
+        m->sum_npp = 0;
+        m->sum_npc = 0;
+    }
     const uint32_t ncells = m->ncells;
     for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < ncells; c += gridDim.x * kBlock) {
         const uint32_t f = c_first[c];
@@ -681,12 +738,6 @@ rcrit_kernel(const DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
     }
 }
 
-__global__ void fill_u8_kernel(uint8_t *p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
-}
 
 }  // namespace
 
@@ -702,8 +753,6 @@ hipError_t launch_cluster_ids(bh_ctx *c)
 
 hipError_t launch_domain(bh_ctx *c, const double *pos_aos)
 {
-    hipLaunchKernelGGL(misc_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
-    BH_LAUNCH_CHECK();
     if (pos_aos)
         hipLaunchKernelGGL(bbox_kernel<AosSrc>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
                            c->stream, AosSrc{pos_aos}, c->chunks, c->bb_part, c->misc);
@@ -759,20 +808,14 @@ hipError_t launch_tree(bh_ctx *c)
     const int H = c->max_nleaf;
     const size_t lds = (size_t)((kTreeTile + 2 * H + 15) & ~15) + (size_t)kTreeTile * H;
     hipLaunchKernelGGL(split_leaf_kernel, dim3(nblk), dim3(kTreeTile), lds, c->stream, c->key[0],
-                       c->pcl, n, H, c->clus, c->split, c->lam, blk, nblk, c->misc);
+                       c->pcl, n, H, c->clus, c->split, c->lam, c->gflag, blk, nblk, c->misc);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(scan_levels_kernel, dim3(kLevels), dim3(256), 0, c->stream, blk, nblk, tot);
-    BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(level_finalize_kernel, dim3(1), dim3(64), 0, c->stream, tot, c->misc,
-                       c->cap_c);
+    hipLaunchKernelGGL(scan_levels_kernel, dim3(kLevels), dim3(256), 0, c->stream, blk, nblk, tot,
+                       c->misc, c->cap_c);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(emit_cells_kernel, dim3(nblk), dim3(kTreeTile), 0, c->stream, c->split,
                        c->lam, n, blk, nblk, c->misc, c->c_first, c->c_level, c->c_leaf,
                        c->c_parent, c->c_child, c->c_nchild);
-    BH_LAUNCH_CHECK();
-    int fg = grid_for(n, 256);
-    if (fg > 4096) fg = 4096;
-    hipLaunchKernelGGL(fill_u8_kernel, dim3(fg), dim3(256), 0, c->stream, c->gflag, n);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(cell_ends_kernel, dim3(nblk), dim3(kTreeTile), 0, c->stream, c->split,
                        c->lam, n, c->pcl, c->clus, blk, nblk, c->misc, c->c_first, c->c_parent,
@@ -805,13 +848,29 @@ hipError_t launch_moments(bh_ctx *c)
                        c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild, c->p4[c->cur],
                        c->c_com, c->c_S, c->c_q0, c->c_q1);
     BH_LAUNCH_CHECK();
-    // nodes from their children, deepest level first (level 20 holds only leaves);
-    // levels below the tree's depth have no cells and return at once
-    for (int lev = kMaxLevel - 1; lev >= 0; --lev) {
-        hipLaunchKernelGGL(moments_kernel<false>, dim3(g), dim3(kBlock), 0, c->stream, lev,
-                           c->misc, c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild,
-                           c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
-        BH_LAUNCH_CHECK();
+    // nodes from their children, deepest level first (level 20 holds only leaves).
+    // The level sizes are known on the device only; the host uses the sizes seen
+    // at its last synchronisation as a hint: a level that held more than
+    // kSmallLevel cells gets a launch of its own, runs of the others share one
+    // workgroup.  Any tree is handled correctly whatever the hint.
+    constexpr uint32_t kSmallLevel = 2048;
+    const uint32_t *hint = c->misc_h->level_count;
+    int lev = kMaxLevel - 1;
+    while (lev >= 0) {
+        if (hint[lev] > kSmallLevel) {
+            hipLaunchKernelGGL(moments_kernel<false>, dim3(g), dim3(kBlock), 0, c->stream, lev,
+                               c->misc, c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild,
+                               c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
+            BH_LAUNCH_CHECK();
+            --lev;
+        } else {
+            const int hi = lev;
+            while (lev >= 0 && hint[lev] <= kSmallLevel) --lev;
+            hipLaunchKernelGGL(moments_levels_kernel, dim3(1), dim3(kLevelsBlock), 0, c->stream, hi,
+                               lev + 1, c->misc, c->c_leaf, c->c_first, c->c_count, c->c_child,
+                               c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
+            BH_LAUNCH_CHECK();
+        }
     }
     return hipSuccess;
 }

@@ -13,22 +13,6 @@ constexpr int kRedBlocks = 1024;
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// v += a h with h = dt / 2 of the particle's cluster
-__global__ void __launch_bounds__(kBlock)
-kick_kernel(int64_t n, const uint32_t *__restrict__ pcl, const DevCluster *__restrict__ clus,
-            const float4 *__restrict__ acc4, double4 *__restrict__ v4)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const double h = 0.5 * clus[pcl[i]].dt;
-    const float4 a = acc4[i];
-    double4 v = v4[i];
-    v.x = v.x + (double)a.x * h;
-    v.y = v.y + (double)a.y * h;
-    v.z = v.z + (double)a.z * h;
-    v4[i] = v;
-}
-
 // v += a h; x += v dt in one pass (the first half of a kick-drift-kick step)
 __global__ void __launch_bounds__(kBlock)
 kick_drift_kernel(int64_t n, const uint32_t *__restrict__ pcl, const DevCluster *__restrict__ clus,
@@ -50,6 +34,44 @@ kick_drift_kernel(int64_t n, const uint32_t *__restrict__ pcl, const DevCluster 
     p.y = p.y + v.y * dt;
     p.z = p.z + v.z * dt;
     p4[i] = p;
+}
+
+// Per chunk: the closing kick v += a dt/2 of the chunk's cluster, then the T, W,
+// Px, Py, Pz partial sums of the new state (same order as energy_partial_kernel).
+__global__ void __launch_bounds__(kBlock)
+kick_energy_kernel(const Chunk *__restrict__ chunks, const DevCluster *__restrict__ clus,
+                   const double4 *__restrict__ p4, double4 *__restrict__ v4,
+                   const float4 *__restrict__ acc4, double *__restrict__ part)
+{
+    const Chunk ch = chunks[blockIdx.x];
+    const double h = 0.5 * clus[ch.cluster].dt;
+    double s[5] = {0, 0, 0, 0, 0};
+    for (uint32_t i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) {
+        const float4 a = acc4[i];
+        double4 v = v4[i];
+        v.x = v.x + (double)a.x * h;
+        v.y = v.y + (double)a.y * h;
+        v.z = v.z + (double)a.z * h;
+        v4[i] = v;
+        const double m = p4[i].w;
+        s[0] += 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
+        s[1] += 0.5 * m * (double)a.w;
+        s[2] += m * v.x;
+        s[3] += m * v.y;
+        s[4] += m * v.z;
+    }
+    __shared__ double sh[5][kBlock];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] = s[k];
+    __syncthreads();
+    for (int d = kBlock / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) part[5 * (int64_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // Per chunk: T, W, Px, Py, Pz partial sums (fixed order: strided per thread,
@@ -157,18 +179,21 @@ state_out_kernel(int64_t n, const double4 *__restrict__ p4, const double4 *__res
 
 }  // namespace
 
-hipError_t launch_kick(bh_ctx *c)
-{
-    hipLaunchKernelGGL(kick_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n, c->pcl,
-                       c->clus, c->acc4, c->v4[c->cur]);
-    BH_LAUNCH_CHECK();
-    return hipSuccess;
-}
-
 hipError_t launch_kick_drift(bh_ctx *c)
 {
     hipLaunchKernelGGL(kick_drift_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
                        c->pcl, c->clus, c->acc4, c->v4[c->cur], c->p4[c->cur]);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_kick_energy(bh_ctx *c)
+{
+    hipLaunchKernelGGL(kick_energy_kernel, dim3((unsigned)c->nchunks), dim3(kBlock), 0, c->stream,
+                       c->chunks, c->clus, c->p4[c->cur], c->v4[c->cur], c->acc4, c->e_part);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(energy_final_kernel, dim3((unsigned)c->K), dim3(kBlock), 0, c->stream,
+                       c->clus, c->e_part, c->e_out);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

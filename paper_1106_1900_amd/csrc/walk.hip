@@ -532,14 +532,6 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
     }
 }
 
-__global__ void walk_reset_kernel(DevMisc *m)
-{
-    if (threadIdx.x == 0) {
-        m->walk_next = 0;
-        m->sum_npp = 0;
-        m->sum_npc = 0;
-    }
-}
 
 __global__ void __launch_bounds__(256) zero_f4_kernel(int64_t n, float4 *__restrict__ p)
 {
@@ -613,10 +605,10 @@ int64_t walk_grid_waves(bh_ctx *c)
     return (int64_t)dev_cus * BH_WALK_BLOCKS_PER_CU * kWalkWaves;
 }
 
+// The work counter and interaction sums are cleared by launch_rcrit, which
+// always precedes the walk.
 hipError_t launch_walk(bh_ctx *c, bool timed)
 {
-    hipLaunchKernelGGL(walk_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
-    BH_LAUNCH_CHECK();
     int64_t blocks = walk_grid_waves(c) / kWalkWaves;
     if (blocks * kWalkWaves > c->walk_spill_waves) blocks = c->walk_spill_waves / kWalkWaves;
     if (blocks < 1) return hipErrorInvalidValue;

@@ -97,9 +97,11 @@ struct WaveLds {
 };
 static_assert(4 * sizeof(WaveLds) * 4 <= 160 * 1024, "four blocks of four wavefronts per CU");
 
+// Running sums of the M particles a lane carries, with their compensations.
+template <int M>
 struct Acc {
-    float ax, ay, az, ph;     // running sums
-    float cx, cy, cz, cp;     // running compensations
+    float ax[M], ay[M], az[M], ph[M];
+    float cx[M], cy[M], cz[M], cp[M];
 };
 
 // s + t with the rounding error of the addition carried in c (two-sum).
@@ -237,75 +239,112 @@ __device__ __forceinline__ void pc_term(const float4 A, const float4 B, const fl
     az = __builtin_fmaf(rho5, sz, az);
 }
 
+// The lane's share of a group of g particles: P = ceil(g / M) particle slots,
+// k = floor(64 / P) lanes per slot; lane = slot + sub P.  Slot p carries the
+// particles p, p + P, ..., p + (M - 1) P that exist (offsets from the group
+// centre); lane (p, sub) takes sources sub, sub + k, sub + 2k, ... of a tile.
+template <int M>
 struct Target {
-    float ox, oy, oz;
+    float ox[M], oy[M], oz[M];
     int sub, k;
 };
 
-template <bool kEps0>
-__device__ __forceinline__ void run_pc(const WaveLds &L, int base, int cnt, const Target &t,
-                                       float eps2, Acc &acc)
+// sources per loop trip: fewer when the lane carries more particles (registers)
+#ifndef BH_WALK_UNROLL2
+#define BH_WALK_UNROLL2 2
+#endif
+template <int M>
+constexpr int unroll_for() { return M == 1 ? kUnroll : (M == 2 ? BH_WALK_UNROLL2 : 1); }
+
+template <int M>
+__device__ __forceinline__ void acc_tile(Acc<M> &acc, const float *ax, const float *ay,
+                                         const float *az, const float *ph)
 {
-    float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        comp_add(acc.ax[m], acc.cx[m], ax[m]);
+        comp_add(acc.ay[m], acc.cy[m], ay[m]);
+        comp_add(acc.az[m], acc.cz[m], az[m]);
+        comp_add(acc.ph[m], acc.cp[m], ph[m]);
+    }
+}
+
+template <bool kEps0, int M>
+__device__ __forceinline__ void run_pc(const WaveLds &L, int base, int cnt, const Target<M> &t,
+                                       float eps2, Acc<M> &acc)
+{
+    constexpr int U = unroll_for<M>();
+    float ax[M], ay[M], az[M], ph[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) ax[m] = ay[m] = az[m] = ph[m] = 0.f;
     const int k = t.k;
     const int T = uniform((cnt + k - 1) / k);
     int j = base + t.sub;
     int it = 0;
-    for (; it + kUnroll <= T; it += kUnroll) {
-        float4 A[kUnroll], B[kUnroll], C[kUnroll];
+    for (; it + U <= T; it += U) {
+        float4 A[U], B[U], C[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
             A[u] = L.ca[j + u * k];
             B[u] = L.cb[j + u * k];
             C[u] = L.cc[j + u * k];
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-            pc_term<kEps0>(A[u], B[u], C[u], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
-        j += kUnroll * k;
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                pc_term<kEps0>(A[u], B[u], C[u], t.ox[m], t.oy[m], t.oz[m], eps2, ax[m], ay[m],
+                               az[m], ph[m]);
+        j += U * k;
     }
     for (; it < T; ++it) {
-        pc_term<kEps0>(L.ca[j], L.cb[j], L.cc[j], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
+        const float4 A = L.ca[j], B = L.cb[j], C = L.cc[j];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            pc_term<kEps0>(A, B, C, t.ox[m], t.oy[m], t.oz[m], eps2, ax[m], ay[m], az[m], ph[m]);
         j += k;
     }
-    comp_add(acc.ax, acc.cx, ax);
-    comp_add(acc.ay, acc.cy, ay);
-    comp_add(acc.az, acc.cz, az);
-    comp_add(acc.ph, acc.cp, ph);
+    acc_tile<M>(acc, ax, ay, az, ph);
 }
 
-template <bool kEps0>
-__device__ __forceinline__ void run_pp(const WaveLds &L, int cnt, const Target &t, float eps2,
-                                       Acc &acc)
+template <bool kEps0, int M>
+__device__ __forceinline__ void run_pp(const WaveLds &L, int cnt, const Target<M> &t, float eps2,
+                                       Acc<M> &acc)
 {
-    float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+    constexpr int U = unroll_for<M>();
+    float ax[M], ay[M], az[M], ph[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) ax[m] = ay[m] = az[m] = ph[m] = 0.f;
     const int k = t.k;
     const int T = uniform((cnt + k - 1) / k);
     int j = t.sub;
     int it = 0;
-    for (; it + kUnroll <= T; it += kUnroll) {
-        float4 S[kUnroll];
+    for (; it + U <= T; it += U) {
+        float4 S[U];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) S[u] = L.ta[j + u * k];
+        for (int u = 0; u < U; ++u) S[u] = L.ta[j + u * k];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) pp_term<kEps0>(S[u], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
-        j += kUnroll * k;
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                pp_term<kEps0>(S[u], t.ox[m], t.oy[m], t.oz[m], eps2, ax[m], ay[m], az[m], ph[m]);
+        j += U * k;
     }
     for (; it < T; ++it) {
-        pp_term<kEps0>(L.ta[j], t.ox, t.oy, t.oz, eps2, ax, ay, az, ph);
+        const float4 S = L.ta[j];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            pp_term<kEps0>(S, t.ox[m], t.oy[m], t.oz[m], eps2, ax[m], ay[m], az[m], ph[m]);
         j += k;
     }
-    comp_add(acc.ax, acc.cx, ax);
-    comp_add(acc.ay, acc.cy, ay);
-    comp_add(acc.az, acc.cz, az);
-    comp_add(acc.ph, acc.cp, ph);
+    acc_tile<M>(acc, ax, ay, az, ph);
 }
 
 // evaluate cnt <= 64 cells of the staged cell list from entry base: the entries
 // a lane may read past them are set to padding (far away, zero mass) first
-template <bool kEps0>
-__device__ __forceinline__ void eval_pc(WaveLds &L, int base, int cnt, const Target &t, float eps2,
-                                        Acc &acc)
+template <bool kEps0, int M>
+__device__ __forceinline__ void eval_pc(WaveLds &L, int base, int cnt, const Target<M> &t,
+                                        float eps2, Acc<M> &acc)
 {
     const int lane = lane_id();
     for (int i = base + cnt + lane; i < base + kTileReach; i += kWave) {
@@ -314,14 +353,15 @@ __device__ __forceinline__ void eval_pc(WaveLds &L, int base, int cnt, const Tar
         L.cc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     wave_sync();
-    if (t.sub < t.k) run_pc<kEps0>(L, base, cnt, t, eps2, acc);
+    if (t.sub < t.k) run_pc<kEps0, M>(L, base, cnt, t, eps2, acc);
     wave_sync();
 }
 
 // stage up to 64 particles (lane j holds particle index idx) and evaluate them
-template <bool kEps0>
+template <bool kEps0, int M>
 __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t idx, int cnt,
-                                        const double4 gc, const Target &t, float eps2, Acc &acc)
+                                        const double4 gc, const Target<M> &t, float eps2,
+                                        Acc<M> &acc)
 {
     const int lane = lane_id();
     if (lane < cnt) {
@@ -331,7 +371,7 @@ __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t 
         L.ta[lane] = make_float4(kFar, kFar, kFar, 0.0f);
     }
     wave_sync();
-    if (t.sub < t.k) run_pp<kEps0>(L, cnt, t, eps2, acc);
+    if (t.sub < t.k) run_pp<kEps0, M>(L, cnt, t, eps2, acc);
     wave_sync();
 }
 
@@ -342,6 +382,209 @@ __device__ __forceinline__ bool next_group(const WalkArgs &a, uint32_t ngroups, 
     if (lane_id() == 0) v = atomicAdd(&a.misc->walk_next, 1u);
     g = readfirst(v);
     return g < ngroups;
+}
+
+// One group: walk its cluster's tree from the root, evaluate its lists, and
+// write its particles' accelerations and potentials.  M: particles per lane.
+template <bool kEps0, int M>
+__device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellStack &stack,
+                                           LeafList &leaves, uint32_t ncells, uint32_t gs, int gn,
+                                           const double4 gc, const float4 gh, uint32_t cid,
+                                           float eps2, uint32_t &npp_out, uint32_t &npc_out,
+                                           bool &overflow_out)
+{
+    const int lane = lane_id();
+    const int P = (gn + M - 1) / M;
+    Target<M> t;
+    t.k = uniform(kWave / P);
+    const int p = lane % P;
+    t.sub = lane / P;
+    float mi[M];
+    Acc<M> acc;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        t.ox[m] = t.oy[m] = t.oz[m] = 0.f;
+        mi[m] = 0.f;
+        acc.ax[m] = acc.ay[m] = acc.az[m] = acc.ph[m] = 0.f;
+        acc.cx[m] = acc.cy[m] = acc.cz[m] = acc.cp[m] = 0.f;
+        const int q = p + m * P;
+        if (t.sub < t.k && q < gn) {
+            const double4 x = a.p4[gs + q];
+            t.ox[m] = (float)(x.x - gc.x);
+            t.oy[m] = (float)(x.y - gc.y);
+            t.oz[m] = (float)(x.z - gc.z);
+            mi[m] = (float)x.w;
+        }
+    }
+
+    int top = 1;
+    if (lane == 0) stack.set(0, cid, 1u);  // the cluster's root
+    wave_sync();
+    int pc_n = 0, pp_n = 0;
+    uint32_t pend = 0, npp = 0, npc = 0;
+    bool overflow = false;
+    uint32_t iters = 0;
+
+    while (top > 0) {
+        // a correct tree visits each cell at most once per group
+        if (++iters > ncells + 1u) {
+            overflow = true;
+            break;
+        }
+        uint32_t cell;
+        const int got = pop64(stack, top, L.mark, cell);
+        const bool has = lane < got && cell < ncells;
+        bool acc_cell = false, leaf = false;
+        uint32_t link = 0, info = 0;
+        WalkCell w;
+        float ox = 0.f, oy = 0.f, oz = 0.f;
+        if (has) {
+            w = a.rec[cell];
+            link = w.link;
+            info = w.info;
+            ox = (float)(w.cx - gc.x);
+            oy = (float)(w.cy - gc.y);
+            oz = (float)(w.cz - gc.z);
+            const float dx = fabsf(ox) - gh.x;
+            const float dy = fabsf(oy) - gh.y;
+            const float dz = fabsf(oz) - gh.z;
+            const float ux = dx > 0.0f ? dx : 0.0f;
+            const float uy = dy > 0.0f ? dy : 0.0f;
+            const float uz = dz > 0.0f ? dz : 0.0f;
+            const float d2 = (ux * ux + uy * uy) + uz * uz;
+            acc_cell = d2 > w.rcrit2;
+            leaf = (info >> 31) != 0u;
+        }
+        // accepted cells -> cell list, staged for evaluation at once (offset
+        // from the group centre, mass, 3 S and the trace terms)
+        const unsigned long long bpc = ballot(has && acc_cell);
+        if (has && acc_cell) {
+            const int i = pc_n + mask_rank(bpc);
+            const float tr3 = (w.s3[0] + w.s3[1]) + w.s3[2];     // 3 tr(S)
+            L.ca[i] = make_float4(ox, oy, oz, w.mass);
+            L.cb[i] = make_float4(w.s3[0], w.s3[1], w.s3[2], w.s3[3]);
+            L.cc[i] = make_float4(w.s3[4], w.s3[5], tr3 * (1.0f / 6.0f), tr3 * 0.5f);
+        }
+        pc_n += __popcll(bpc);
+        npc += (uint32_t)__popcll(bpc);
+        // opened leaves -> particle list
+        const bool isl = has && !acc_cell && leaf;
+        const unsigned long long bpp = ballot(isl);
+        const uint32_t lc = isl ? (info & 0x7fffffffu) : 0u;
+        if (isl) L.pp[pp_n + mask_rank(bpp)] = make_uint2(link, lc);
+        pp_n += __popcll(bpp);
+        const uint32_t lsum = wave_sum_u32(lc);
+        pend += lsum;
+        npp += lsum;
+        // opened nodes -> children onto the stack
+        const bool isn = has && !acc_cell && !leaf;
+        const unsigned long long bn = ballot(isn);
+        const int nn = __popcll(bn);
+        if (top + nn > kStackCap) {
+            overflow = true;
+        } else {
+            if (isn) stack.set(top + mask_rank(bn), link, info);
+            top += nn;
+        }
+        stack.sync();
+        if (pc_n >= kWave) {     // pc_n < 128: one tile of the last 64 entries
+            eval_pc<kEps0, M>(L, pc_n - kWave, kWave, t, eps2, acc);
+            pc_n -= kWave;
+        }
+        while (pend >= (uint32_t)kWave) {
+            uint32_t idx;
+            const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx) : 0;
+            if (n <= 0) {   // inconsistent bookkeeping: never spin
+                overflow = true;
+                pend = 0;
+                break;
+            }
+            eval_pp<kEps0, M>(a, L, idx, n, gc, t, eps2, acc);
+            pend -= (uint32_t)n;
+        }
+        if (overflow) break;
+    }
+    if (pc_n > 0) eval_pc<kEps0, M>(L, 0, pc_n, t, eps2, acc);
+    while (pend > 0) {
+        uint32_t idx;
+        const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx) : 0;
+        if (n <= 0) {
+            overflow = true;
+            break;
+        }
+        eval_pp<kEps0, M>(a, L, idx, n, gc, t, eps2, acc);
+        pend -= (uint32_t)n < pend ? (uint32_t)n : pend;
+    }
+
+    // add the k partial sums of each particle: halving steps over the sub-lane
+    // index, in a fixed order
+    float ax[M], ay[M], az[M], ph[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        ax[m] = acc.ax[m] + acc.cx[m];
+        ay[m] = acc.ay[m] + acc.cy[m];
+        az[m] = acc.az[m] + acc.cz[m];
+        ph[m] = acc.ph[m] + acc.cp[m];
+    }
+    for (int kk = t.k; kk > 1;) {
+        const int h = (kk + 1) >> 1;
+        const int src = lane + h * P;
+        const int srcl = src < kWave ? src : lane;
+        const bool take = t.sub + h < kk;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float bx = __shfl(ax[m], srcl, kWave);
+            const float by = __shfl(ay[m], srcl, kWave);
+            const float bz = __shfl(az[m], srcl, kWave);
+            const float bp = __shfl(ph[m], srcl, kWave);
+            if (take) {
+                ax[m] += bx;
+                ay[m] += by;
+                az[m] += bz;
+                ph[m] += bp;
+            }
+        }
+        kk = h;
+    }
+    if (t.sub == 0 && lane < P) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int q = p + m * P;
+            if (q >= gn) continue;
+            // the particle met itself once in the particle list: with eps > 0
+            // that term added -m/eps to the potential and nothing to the
+            // acceleration
+            float phm = ph[m];
+            if (!kEps0 || eps2 > 0.0f) phm = phm + mi[m] * __builtin_amdgcn_rsqf(eps2);
+            a.acc4[gs + q] = make_float4(ax[m], ay[m], az[m], phm);
+        }
+    }
+    npp_out = npp;
+    npc_out = npc;
+    overflow_out = overflow;
+}
+
+// Particles per lane for a group of g: the M in {1, .., kMaxPerLane} with the
+// fewest loop trips per 64-source tile, M ceil(64 / floor(64 / ceil(g / M)));
+// ties go to the smaller M.
+#ifndef BH_WALK_MAX_PER_LANE
+#define BH_WALK_MAX_PER_LANE 2
+#endif
+constexpr int kMaxPerLane = BH_WALK_MAX_PER_LANE;
+
+__device__ __forceinline__ int lanes_mode(int g)
+{
+    int best = 1, cost = 1 << 30;
+    for (int m = 1; m <= kMaxPerLane; ++m) {
+        const int P = (g + m - 1) / m;
+        const int k = kWave / P;
+        const int c = m * ((kWave + k - 1) / k);
+        if (c < cost) {
+            cost = c;
+            best = m;
+        }
+    }
+    return best;
 }
 
 // kEps0: some cluster of the launch has zero softening, so pairs at zero
@@ -375,144 +618,22 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
         // the group's cluster: its root is the cluster's level-0 cell
         const uint32_t cid = readfirst((uint32_t)gc.w);
         const float eps2 = a.clus[cid].eps2;
-        Target t;
-        t.k = uniform(kWave / gn);
-        const int p = lane % gn;
-        t.sub = lane / gn;
-        float mi = 0.f;
-        t.ox = t.oy = t.oz = 0.f;
-        if (t.sub < t.k) {
-            const double4 q = a.p4[gs + p];
-            t.ox = (float)(q.x - gc.x);
-            t.oy = (float)(q.y - gc.y);
-            t.oz = (float)(q.z - gc.z);
-            mi = (float)q.w;
-        }
-        Acc acc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-
-        int top = 1;
-        if (lane == 0) stack.set(0, cid, 1u);  // the cluster's root
-        wave_sync();
-        int pc_n = 0, pp_n = 0;
-        uint32_t pend = 0, npp = 0, npc = 0;
+        uint32_t npp = 0, npc = 0;
         bool overflow = false;
-        uint32_t iters = 0;
-
-        while (top > 0) {
-            // a correct tree visits each cell at most once per group
-            if (++iters > ncells + 1u) {
-                overflow = true;
-                break;
-            }
-            uint32_t cell;
-            const int got = pop64(stack, top, L.mark, cell);
-            const bool has = lane < got && cell < ncells;
-            bool acc_cell = false, leaf = false;
-            uint32_t link = 0, info = 0;
-            WalkCell w;
-            float ox = 0.f, oy = 0.f, oz = 0.f;
-            if (has) {
-                w = a.rec[cell];
-                link = w.link;
-                info = w.info;
-                ox = (float)(w.cx - gc.x);
-                oy = (float)(w.cy - gc.y);
-                oz = (float)(w.cz - gc.z);
-                const float dx = fabsf(ox) - gh.x;
-                const float dy = fabsf(oy) - gh.y;
-                const float dz = fabsf(oz) - gh.z;
-                const float ux = dx > 0.0f ? dx : 0.0f;
-                const float uy = dy > 0.0f ? dy : 0.0f;
-                const float uz = dz > 0.0f ? dz : 0.0f;
-                const float d2 = (ux * ux + uy * uy) + uz * uz;
-                acc_cell = d2 > w.rcrit2;
-                leaf = (info >> 31) != 0u;
-            }
-            // accepted cells -> cell list, staged for evaluation at once (offset
-            // from the group centre, mass, 3 S and the trace terms)
-            const unsigned long long bpc = ballot(has && acc_cell);
-            if (has && acc_cell) {
-                const int i = pc_n + mask_rank(bpc);
-                const float tr3 = (w.s3[0] + w.s3[1]) + w.s3[2];     // 3 tr(S)
-                L.ca[i] = make_float4(ox, oy, oz, w.mass);
-                L.cb[i] = make_float4(w.s3[0], w.s3[1], w.s3[2], w.s3[3]);
-                L.cc[i] = make_float4(w.s3[4], w.s3[5], tr3 * (1.0f / 6.0f), tr3 * 0.5f);
-            }
-            pc_n += __popcll(bpc);
-            npc += (uint32_t)__popcll(bpc);
-            // opened leaves -> particle list
-            const bool isl = has && !acc_cell && leaf;
-            const unsigned long long bpp = ballot(isl);
-            const uint32_t lc = isl ? (info & 0x7fffffffu) : 0u;
-            if (isl) L.pp[pp_n + mask_rank(bpp)] = make_uint2(link, lc);
-            pp_n += __popcll(bpp);
-            const uint32_t lsum = wave_sum_u32(lc);
-            pend += lsum;
-            npp += lsum;
-            // opened nodes -> children onto the stack
-            const bool isn = has && !acc_cell && !leaf;
-            const unsigned long long bn = ballot(isn);
-            const int nn = __popcll(bn);
-            if (top + nn > kStackCap) {
-                overflow = true;
-            } else {
-                if (isn) stack.set(top + mask_rank(bn), link, info);
-                top += nn;
-            }
-            stack.sync();
-            if (pc_n >= kWave) {     // pc_n < 128: one tile of the last 64 entries
-                eval_pc<kEps0>(L, pc_n - kWave, kWave, t, eps2, acc);
-                pc_n -= kWave;
-            }
-            while (pend >= (uint32_t)kWave) {
-                uint32_t idx;
-                const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx) : 0;
-                if (n <= 0) {   // inconsistent bookkeeping: never spin
-                    overflow = true;
-                    pend = 0;
-                    break;
-                }
-                eval_pp<kEps0>(a, L, idx, n, gc, t, eps2, acc);
-                pend -= (uint32_t)n;
-            }
-            if (overflow) break;
-        }
-        if (pc_n > 0) eval_pc<kEps0>(L, 0, pc_n, t, eps2, acc);
-        while (pend > 0) {
-            uint32_t idx;
-            const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx) : 0;
-            if (n <= 0) {
-                overflow = true;
-                break;
-            }
-            eval_pp<kEps0>(a, L, idx, n, gc, t, eps2, acc);
-            pend -= (uint32_t)n < pend ? (uint32_t)n : pend;
-        }
-
-        // add the k partial sums of each particle: halving steps over the
-        // sub-lane index, in a fixed order
-        float ax = acc.ax + acc.cx, ay = acc.ay + acc.cy, az = acc.az + acc.cz, ph = acc.ph + acc.cp;
-        for (int kk = t.k; kk > 1;) {
-            const int h = (kk + 1) >> 1;
-            const int src = lane + h * gn;
-            const int srcl = src < kWave ? src : lane;
-            const float bx = __shfl(ax, srcl, kWave);
-            const float by = __shfl(ay, srcl, kWave);
-            const float bz = __shfl(az, srcl, kWave);
-            const float bp = __shfl(ph, srcl, kWave);
-            if (t.sub + h < kk) {
-                ax += bx;
-                ay += by;
-                az += bz;
-                ph += bp;
-            }
-            kk = h;
-        }
-        if (t.sub == 0 && lane < gn) {
-            // the particle met itself once in the particle list: with eps > 0 that
-            // term added -m/eps to the potential and nothing to the acceleration
-            if (!kEps0 || eps2 > 0.0f) ph = ph + mi * __builtin_amdgcn_rsqf(eps2);
-            a.acc4[gs + lane] = make_float4(ax, ay, az, ph);
+        switch (uniform(lanes_mode(gn))) {
+        case 1:
+            walk_group<kEps0, 1>(a, L, stack, leaves, ncells, gs, gn, gc, gh, cid, eps2, npp, npc,
+                                 overflow);
+            break;
+        case 2:
+            walk_group<kEps0, 2>(a, L, stack, leaves, ncells, gs, gn, gc, gh, cid, eps2, npp, npc,
+                                 overflow);
+            break;
+        default:
+            if (kMaxPerLane >= 3)
+                walk_group<kEps0, (kMaxPerLane >= 3 ? 3 : 1)>(a, L, stack, leaves, ncells, gs, gn,
+                                                              gc, gh, cid, eps2, npp, npc, overflow);
+            break;
         }
         if (lane == 0) {
             a.g_npp[g] = npp;

@@ -9,7 +9,9 @@
 // lane accumulates them on its particle.  A group of g particles uses
 // k = floor(64 / g) lanes per particle (the paper uses up to 4 threads per
 // particle); lane (p, s) takes sources s, s + k, s + 2k, ... of each tile and
-// the k partial sums are added at the end.
+// the k partial sums are added at the end.  Groups of 22-25 and 33-48 particles
+// would leave many lanes idle that way; there a lane carries two particles of
+// the group (k = floor(64 / ceil(g / 2))) and evaluates each source on both.
 //
 // Per wavefront, in LDS:
 //   stack : pending cell ranges (first cell, count <= 8) packed in 32 bits, used

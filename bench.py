@@ -118,6 +118,27 @@ def accuracy_sample(pos, mass, acc_gpu, eps, ntarget=1024):
             "p99": float(np.percentile(err, 99)), "reference": "oracle float64 direct summation"}
 
 
+def pooled_accuracy(systems, ntarget, seed):
+    """Δa/a against float64 direct summation pooled over several systems: each
+    entry (pos, mass, acc, eps) contributes ntarget seeded targets."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(seed)
+    errs = []
+    for pos, mass, acc, eps in systems:
+        k = min(ntarget, pos.shape[0])
+        tgt = np.sort(rng.choice(pos.shape[0], k, replace=False))
+        ad, _ = oracle.direct(pos, mass, eps, tgt)
+        na = np.linalg.norm(ad, axis=1)
+        ok = na > 0
+        e = np.linalg.norm(acc[tgt].astype(np.float64) - ad, axis=1)
+        errs.append(e[ok] / na[ok])
+    err = np.concatenate(errs)
+    return {"systems": len(systems), "targets": int(err.size), "median": float(np.median(err)),
+            "p99": float(np.percentile(err, 99)), "reference": "oracle float64 direct summation"}
+
+
 def calib_copy():
     """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB) for scaling the HBM
     counters of a profiler run."""
@@ -157,6 +178,17 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4, alone=True):
     t_batch = (time.perf_counter() - t0) / steps
     en = ctx.batch_energy()
     st = ctx.stats()
+    # force error of the batched form: 4 seeded clusters (smallest, largest, two
+    # others), 256 targets each, at their positions after the timed steps
+    xs, _, acc_b, _ = ctx.get_state()
+    xs = xs.cpu().numpy()
+    acc_b = acc_b.cpu().numpy()
+    starts = np.concatenate([[0], np.cumsum([q["n"] for q in cl])[:-1]])
+    pick = sorted({int(np.argmin([q["n"] for q in cl])), int(np.argmax([q["n"] for q in cl]))}
+                  | set(np.random.default_rng(13).choice(k, 2, replace=False).tolist()))
+    accuracy = pooled_accuracy([(xs[starts[c]:starts[c] + cl[c]["n"]], cl[c]["mass"],
+                                 acc_b[starts[c]:starts[c] + cl[c]["n"]], cl[c]["eps"]) for c in pick],
+                                256, 14)
 
     # leaf and group sizes tuned per class (floor(log2 N), theta), then the same
     # clusters reloaded with the tuned sizes and timed again
@@ -182,6 +214,7 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4, alone=True):
         "value": ntot / t_batch, "unit": "particles/s",
         "ms_per_step": 1e3 * t_batch,
         "max_abs_energy_error": float(np.abs(en[:, 6]).max()),
+        "accuracy_vs_direct": accuracy,
         "graph_launches": int(st.graph_launches),
         "tuned_value": ntot / t_tuned,
         "tuned_ms_per_step": 1e3 * t_tuned,
@@ -244,6 +277,13 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
         pools[name] = (torch.from_numpy(p).cuda(), torch.from_numpy(v).cuda())
     rng = np.random.default_rng(seed + 1)
     offsets = [int(rng.integers(0, nmax)) for _ in trace]
+    # requests whose final state is checked against direct summation: the two
+    # largest arrivals of each shape in the first half of the trace are too slow
+    # for the oracle, so take four seeded requests below 2^18 particles
+    small = [i for i, q in enumerate(trace) if q["n"] < (1 << 18)]
+    check = set(np.random.default_rng(seed + 2).choice(small, min(4, len(small)),
+                                                      replace=False).tolist())
+    kept = {}
     srv = bh.Server(budget, max_requests=max_requests)
     cap = srv.stats()["capacity_particles"]
     torch.cuda.synchronize()
@@ -264,6 +304,8 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
             tk = srv.submit(pp[o:o + n], m, pv[o:o + n], q["theta"], q["eps"], q["dt"], q["steps"],
                             arrival=t0 + q["arrival"], out_pos=out_pos, out_acc=out_acc)
             open_t.append(tk)
+            if i in check:
+                kept[i] = (m, out_pos, out_acc)
             i += 1
         st = srv.stats()
         if st["completed"] + st["rejected"] == count:
@@ -283,6 +325,10 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
     work = sum(q["n"] * (1 + q["steps"]) for q in trace)
     dE = [abs(d["energy"][6]) for d in done if d["state"] == 2]
     srv.close()
+    torch.cuda.synchronize()
+    accuracy = pooled_accuracy([(kept[i][1].cpu().numpy(), kept[i][0].cpu().numpy(),
+                                 kept[i][2].cpu().numpy(), trace[i]["eps"]) for i in sorted(kept)],
+                               256, 15)
     return {
         "workload": "%d requests, Poisson arrivals at %g/s; Plummer or Hernquist (even odds), "
                     "N log-uniform in [1024, 2097152], theta 0.5 or 0.75, eps 0.01, 1 force "
@@ -295,7 +341,106 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
         "served_particle_evals_per_s": st["particle_evals"] / (t_end - first_arrival),
         "completed": st["completed"], "rejected": st["rejected"], "iterations": st["iterations"],
         "wall_s": t_end, "max_abs_energy_error": max(dE) if dE else None,
+        "accuracy_vs_direct": dict(accuracy, what="final accelerations of 4 seeded requests "
+                                   "below 2^18 particles at their final positions"),
     }
+
+
+def bench_galaxy(steps, ntarget=1024):
+    """The three-component galaxy of 4,194,304 particles at theta 0.4, eps 0.02:
+    leapfrog steps of dt 1/128 with the walk kernel timed, and the force error of
+    the first evaluation against float64 direct summation on seeded targets."""
+    import numpy as np
+    import torch
+
+    import paper_1106_1900_amd as bh
+    import workloads
+    log("generating the galaxy")
+    pos, vel, mass = workloads.galaxy()
+    n = pos.shape[0]
+    theta, eps, dt = 0.4, 0.02, 1.0 / 128
+    ctx = bh.Context()
+    ctx.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda())
+    ctx.set_velocities(torch.from_numpy(vel).cuda())
+    acc0, _ = ctx.compute_forces(theta, eps)
+    acc0 = acc0.cpu().numpy()
+    ctx.energy()
+    for _ in range(2):
+        ctx.leapfrog_step(dt)
+    torch.cuda.synchronize()
+    s0 = ctx.stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.leapfrog_step(dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s1 = ctx.stats()
+    e1 = ctx.energy()
+    ctx.close()
+    launches = s1.walk_kernel_launches - s0.walk_kernel_launches
+    walk_ms = (s1.walk_kernel_ms_total - s0.walk_kernel_ms_total) / max(launches, 1)
+    pp = (s1.total_npp - s0.total_npp) / max(launches, 1)
+    pc = (s1.total_npc - s0.total_npc) / max(launches, 1)
+    achieved = (FLOPS_PP * pp + FLOPS_PC * pc) / (walk_ms * 1e-3) / 1e12
+    log("direct summation on %d targets" % ntarget)
+    return {
+        "workload": "galaxy N=%d (disk 2^20, bulge 2^19, halo 2.5 2^20), theta %g, eps %g, dt 1/128"
+                    % (n, theta, eps),
+        "value": n * steps / el, "unit": "particles/s", "ms_per_step": 1e3 * el / steps,
+        "walk_ms_per_launch": walk_ms, "interactions_per_launch": {"pp": pp, "pc": pc},
+        "walk_tflops": achieved, "walk_frac_of_157_3": achieved / PEAK_FP32_VECTOR_TFLOPS,
+        "energy_error": float(e1[6]),
+        "accuracy_vs_direct": pooled_accuracy([(pos, mass, acc0, eps)], ntarget, 16),
+    }
+
+
+def bench_sweep():
+    """Accuracy and cost against theta at N = 2^15, 2^17, 2^20 (Plummer, eps 1/64):
+    Δa/a against float64 direct summation on 256 seeded targets, interactions per
+    particle, walk time; and one force evaluation (build + walk) against N."""
+    import numpy as np
+    import torch
+
+    import paper_1106_1900_amd as bh
+    import workloads
+    rows = []
+    for n in (1 << 15, 1 << 17, 1 << 20):
+        pos, _, mass = workloads.plummer(n, 2)
+        dp, dm = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
+        ctx = bh.Context()
+        ctx.build_tree(dp, dm)
+        for theta in (0.2, 0.3, 0.4, 0.5, 0.6, 0.75, 0.8):
+            ctx.compute_forces(theta, 1 / 64, want=False)
+            acc, _ = ctx.compute_forces(theta, 1 / 64)
+            torch.cuda.synchronize()
+            st = ctx.stats()
+            a = pooled_accuracy([(pos, mass, acc.cpu().numpy(), 1 / 64)], 256, 17)
+            rows.append({"n": n, "theta": theta, "median": a["median"], "p99": a["p99"],
+                         "pp_per_particle": st.sum_npp / n, "pc_per_particle": st.sum_npc / n,
+                         "walk_ms": st.ms_walk_kernel})
+            log(rows[-1])
+        ctx.close()
+    scaling = []
+    for e in range(15, 25):
+        n = 1 << e
+        pos, _, mass = workloads.plummer(n, 2)
+        ctx = bh.Context()
+        ctx.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda())
+        ctx.compute_forces(0.75, 1 / 64, want=False)
+        ctx.leapfrog_step(0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.leapfrog_step(0.0)       # rebuild and forces at the same positions
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / 5
+        st = ctx.stats()
+        scaling.append({"n": n, "ms_per_eval": ms, "particles_per_s": n / (ms * 1e-3),
+                        "build_ms": st.ms_keys + st.ms_sort + st.ms_move + st.ms_tree + st.ms_moments,
+                        "walk_ms": st.ms_walk_kernel})
+        log(scaling[-1])
+        ctx.close()
+    return {"accuracy_vs_theta": rows, "scaling_theta_0_75": scaling}
 
 
 def main():
@@ -322,7 +467,7 @@ def main():
                     help="device memory for the server (0: 60%% of the free memory)")
     ap.add_argument("--serve-small-budget-gib", type=float, default=4.0,
                     help="a second, constrained budget for the same trace (0: skip)")
-    ap.add_argument("--only", choices=("batch", "serve"),
+    ap.add_argument("--only", choices=("batch", "serve", "galaxy", "sweep"),
                     help="run only that form and print its JSON (for profiling runs)")
     args = ap.parse_args()
 
@@ -342,6 +487,12 @@ def main():
         calib_copy()
     if args.only == "batch":
         print(json.dumps(bench_batch(args.batch_clusters, args.batch_steps, 2, alone=False)), flush=True)
+        return
+    if args.only == "sweep":
+        print(json.dumps(bench_sweep()), flush=True)
+        return
+    if args.only == "galaxy":
+        print(json.dumps(bench_galaxy(args.steps if args.steps != 100 else 10)), flush=True)
         return
     if args.only == "serve":
         budget = int(args.serve_budget_gib * (1 << 30)) or int(0.6 * torch.cuda.mem_get_info()[0])

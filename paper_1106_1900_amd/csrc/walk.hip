@@ -253,7 +253,7 @@ struct Target {
 
 // sources per loop trip: fewer when the lane carries more particles (registers)
 #ifndef BH_WALK_UNROLL2
-#define BH_WALK_UNROLL2 2
+#define BH_WALK_UNROLL2 1
 #endif
 template <int M>
 constexpr int unroll_for() { return M == 1 ? kUnroll : (M == 2 ? BH_WALK_UNROLL2 : 1); }

@@ -443,6 +443,56 @@ def bench_sweep():
     return {"accuracy_vs_theta": rows, "scaling_theta_0_75": scaling}
 
 
+def bench_active(n=1 << 20, theta=0.75, eps=1.0 / 64, reps=5):
+    """Between rebuilds (block time-steps): refit against rebuild, and the walk of
+    the groups holding active particles against the full walk, Plummer N, the
+    active particles drawn uniformly at random."""
+    import numpy as np
+    import torch
+
+    import paper_1106_1900_amd as bh
+    import workloads
+    pos, vel, mass = workloads.plummer(n, 2)
+    ctx = bh.Context()
+    ctx.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda())
+    ctx.set_velocities(torch.from_numpy(vel).cuda())
+    ctx.compute_forces(theta, eps, want=False)
+    ctx.leapfrog_step(0.0)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    out = {"workload": "plummer N=%d theta=%g eps=%g" % (n, theta, eps)}
+    out["full_step_ms"] = timed(lambda: ctx.leapfrog_step(0.0))
+    out["rebuild_and_forces_ms"] = out["full_step_ms"]
+
+    def refit_forces():
+        ctx.drift(0.0)
+        ctx.refit()
+        ctx.compute_forces(theta, eps, want=False)
+    out["refit_and_forces_ms"] = timed(refit_forces)
+    ctx.drift(0.0)
+    out["refit_ms"] = timed(ctx.refit)
+    rows = []
+    rng = np.random.default_rng(18)
+    for frac in (0.001, 0.01, 0.1, 0.5, 1.0):
+        act = torch.from_numpy((rng.uniform(size=n) < frac).astype(np.uint8)).cuda()
+        ms = timed(lambda: ctx.compute_forces_active(theta, eps, act, want=False))
+        st = ctx.stats()
+        rows.append({"active_fraction": frac, "ms": ms, "walk_kernel_ms": st.ms_walk_kernel})
+        log(rows[-1])
+    out["active_walks"] = rows
+    out["full_forces_ms"] = timed(lambda: ctx.compute_forces(theta, eps, want=False))
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,7 +517,7 @@ def main():
                     help="device memory for the server (0: 60%% of the free memory)")
     ap.add_argument("--serve-small-budget-gib", type=float, default=4.0,
                     help="a second, constrained budget for the same trace (0: skip)")
-    ap.add_argument("--only", choices=("batch", "serve", "galaxy", "sweep"),
+    ap.add_argument("--only", choices=("batch", "serve", "galaxy", "sweep", "active"),
                     help="run only that form and print its JSON (for profiling runs)")
     args = ap.parse_args()
 
@@ -487,6 +537,9 @@ def main():
         calib_copy()
     if args.only == "batch":
         print(json.dumps(bench_batch(args.batch_clusters, args.batch_steps, 2, alone=False)), flush=True)
+        return
+    if args.only == "active":
+        print(json.dumps(bench_active()), flush=True)
         return
     if args.only == "sweep":
         print(json.dumps(bench_sweep()), flush=True)

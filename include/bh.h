@@ -172,6 +172,39 @@ int bh_stats_get(bh_ctx *ctx, bh_stats *out);
 int bh_export_tree(bh_ctx *ctx, const bh_tree_host *out);
 
 /* ---------------------------------------------------------------------------
+ * Between rebuilds (block time-steps, Sect. 5): only some particles need new
+ * forces at a given time, and instead of rebuilding the tree it suffices to
+ * recompute the multipole moments of the existing cells.  With these calls a
+ * caller drives such a scheme: drift all particles, refit, evaluate the forces
+ * of the groups that hold active particles, kick the active particles.  The
+ * tree must be rebuilt (bh_set_state, bh_leapfrog_step) when the walk's cost
+ * grows, since drifted particles leave their geometric cells.
+ */
+
+/* x += v dt (float64) for every particle, without touching the tree.  Force
+ * calls are refused (BH_ESTATE) until bh_refit or a rebuild. */
+int bh_drift(bh_ctx *ctx, double dt);
+
+/* v += a dt (float64, a from the last force evaluation) for the particles
+ * whose active[i] != 0 (device [n] uint8, caller order); NULL: all. */
+int bh_kick(bh_ctx *ctx, double dt, const uint8_t *active);
+
+/* Multipole-only update (Sect. 5): keep the cells, keys, domain and groups of
+ * the last build; recompute every cell's moments and every group's tight box
+ * from the current positions.  Opening radii follow at the next force call. */
+int bh_refit(bh_ctx *ctx);
+
+/* Forces of the groups that hold at least one particle with active[i] != 0
+ * (device [n] uint8, caller order): the walk visits those groups only (Sect.
+ * 2.2, 5); their particles' accelerations and potentials are recomputed, all
+ * others keep the values of the previous evaluation.  acc, pot as in
+ * bh_compute_forces (whole arrays, caller order; either may be NULL).  Needs a
+ * prior full evaluation.  Per-group interaction counts in bh_export_tree are
+ * updated for the visited groups only. */
+int bh_compute_forces_active(bh_ctx *ctx, float theta, float eps, const uint8_t *active,
+                             float *acc, float *pot);
+
+/* ---------------------------------------------------------------------------
  * Batches: K independent particle systems ("clusters") in one context.  Each
  * cluster gets its own domain and tree (the trees of the batch form one forest:
  * cluster k's root is cell k), its own opening angle, softening, leaf and group

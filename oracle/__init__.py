@@ -79,6 +79,7 @@ def lib():
         "orc_walk_counts": (ctypes.c_int, [vp, f, vp, vp]),
         "orc_group_lists": (i64, [vp, f, i64, vp, i64, vp, i64, vp]),
         "orc_forces": (ctypes.c_int, [vp, f, f, vp, i64, vp, vp, vp, vp]),
+        "orc_refit": (ctypes.c_int, [vp, vp]),
         "orc_direct": (None, [vp, vp, i64, f, vp, i64, vp, vp]),
         "orc_kdk_step": (ctypes.c_int, [vp, vp, vp, i64, vp, vp, d, f, f,
                                         ctypes.c_int, ctypes.c_int]),
@@ -164,6 +165,16 @@ class Tree:
         if h is not None and _lib is not None:
             _lib.orc_free(h)
             self._h = None
+
+    def refit(self, pos):
+        """Multipole-only update (Sect. 5): same cells, groups, keys and domain;
+        moments and group boxes recomputed from the new positions (input order)."""
+        p = _f64(pos)
+        if p.shape != (self.n, 3):
+            raise ValueError("pos must be (n, 3)")
+        if lib().orc_refit(self._h, _ptr(p)) != 0:
+            raise ValueError("non-finite coordinate")
+        self.pos = p
 
     def domain(self):
         lo = np.zeros(3)

@@ -210,6 +210,8 @@ static int build_cells(orc_tree *t)
 /* and its parent holds more (or it is the root); a leaf that still holds more */
 /* than ncrit particles is cut into runs of ncrit consecutive particles.       */
 
+static void group_boxes(orc_tree *t);
+
 static int build_groups(orc_tree *t)
 {
     int64_t n = t->n;
@@ -237,7 +239,14 @@ static int build_groups(orc_tree *t)
         t->gcount[g] += 1;
     }
     free(start);
-    for (g = 0; g < ng; ++g) {
+    group_boxes(t);
+    return 0;
+}
+
+/* Tight float64 box of each group's particles: centre, float32 half-size. */
+static void group_boxes(orc_tree *t)
+{
+    for (int64_t g = 0; g < t->ngroups; ++g) {
         double bmin[3], bmax[3];
         for (int k = 0; k < 3; ++k) { bmin[k] = INFINITY; bmax[k] = -INFINITY; }
         for (int64_t i = t->gfirst[g]; i < t->gfirst[g] + t->gcount[g]; ++i)
@@ -251,7 +260,6 @@ static int build_groups(orc_tree *t)
             t->gh[3 * g + k] = (float)(0.5 * (bmax[k] - bmin[k]));
         }
     }
-    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -360,6 +368,24 @@ fail:
     free(q_in);
     orc_free(t);
     return NULL;
+}
+
+/* Sect. 5: between rebuilds it suffices to recompute the multipole moments of
+ * the cells whose particles moved.  The cells, groups, keys and domain of the
+ * build stay; the particles take the new positions (input order) and every
+ * cell's moments and every group's box are recomputed from them. */
+int orc_refit(orc_tree *t, const double *pos)
+{
+    if (!t || !pos) return -1;
+    for (int64_t i = 0; i < 3 * t->n; ++i)
+        if (!isfinite(pos[i])) return -1;
+    for (int64_t i = 0; i < t->n; ++i) {
+        int64_t p = t->perm[i];
+        for (int k = 0; k < 3; ++k) t->x[3 * i + k] = pos[3 * p + k];
+    }
+    build_moments(t);
+    group_boxes(t);
+    return 0;
 }
 
 int64_t orc_n(const orc_tree *t) { return t->n; }

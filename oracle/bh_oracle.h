@@ -59,6 +59,12 @@ typedef struct orc_tree orc_tree;
 orc_tree *orc_build(const double *pos, const double *mass, int64_t n, int nleaf, int ncrit);
 void orc_free(orc_tree *t);
 
+/* Multipole-only update (Sect. 5): keep the tree's cells, groups, keys and
+ * domain; take new positions (input order, [n][3]) and recompute every cell's
+ * moments and every group's box from them.  Returns 0, or -1 for a non-finite
+ * coordinate (the tree is then unchanged) or a null argument. */
+int orc_refit(orc_tree *t, const double *pos);
+
 int64_t orc_n(const orc_tree *t);
 int64_t orc_ncells(const orc_tree *t);
 int64_t orc_ngroups(const orc_tree *t);

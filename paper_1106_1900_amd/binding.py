@@ -107,6 +107,10 @@ def load_library():
         "bh_energy": (i32, [_vp, _vp]),
         "bh_stats_get": (i32, [_vp, ctypes.POINTER(Stats)]),
         "bh_export_tree": (i32, [_vp, ctypes.POINTER(TreeHost)]),
+        "bh_drift": (i32, [_vp, f64]),
+        "bh_kick": (i32, [_vp, f64, _vp]),
+        "bh_refit": (i32, [_vp]),
+        "bh_compute_forces_active": (i32, [_vp, f32, f32, _vp, _vp, _vp]),
         "bh_batch_build": (i32, [_vp, ctypes.POINTER(Cluster), i64, _vp, _vp, _vp]),
         "bh_batch_set_params": (i32, [_vp, ctypes.POINTER(Cluster), i64]),
         "bh_batch_forces": (i32, [_vp, _vp, _vp]),
@@ -192,6 +196,32 @@ class Context:
         self._keep = None
         self.n = n
         self.k = 1
+
+    # --- between rebuilds ---------------------------------------------------
+    def drift(self, dt):
+        self._check(self._L.bh_drift(self._h, float(dt)))
+
+    def kick(self, dt, active=None):
+        import torch
+        self._check(self._L.bh_kick(self._h, float(dt),
+                                    _dev_ptr(active, torch.uint8, (self.n,), "active")))
+
+    def refit(self):
+        self._check(self._L.bh_refit(self._h))
+
+    def compute_forces_active(self, theta, eps, active, acc=None, pot=None, want=True):
+        """Forces of the groups holding active particles (uint8 [n] device mask,
+        caller order); the others keep their last values."""
+        import torch
+        if want and acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float32, device=self._device())
+        if want and pot is None:
+            pot = torch.empty((self.n,), dtype=torch.float32, device=self._device())
+        self._check(self._L.bh_compute_forces_active(
+            self._h, float(theta), float(eps), _dev_ptr(active, torch.uint8, (self.n,), "active"),
+            _dev_ptr(acc, torch.float32, (self.n, 3), "acc"),
+            _dev_ptr(pot, torch.float32, (self.n,), "pot")))
+        return acc, pot
 
     # --- batches ------------------------------------------------------------
     @staticmethod

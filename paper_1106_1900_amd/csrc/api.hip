@@ -573,6 +573,7 @@ int load(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n, const double *
     c->built = false;
     c->have_forces = false;
     c->energy_current = false;
+    c->moved = false;
     TRY_ST(load_table(c, cl, n));
     reset_e0(c);
     TRY_HIP(c, enqueue_load(c, pos, mass, vel));
@@ -583,6 +584,7 @@ int load(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n, const double *
 int run_forces(bh_ctx *c, float *acc, float *pot)
 {
     if (!c->built) return fail(c, BH_ESTATE, "forces need a built tree");
+    if (c->moved) return fail(c, BH_ESTATE, "positions moved: refit or rebuild before forces");
     TRY_HIP(c, enqueue_forces(c, acc, pot));
     c->have_forces = true;
     c->energy_current = false;
@@ -676,6 +678,67 @@ int ctx_log2_floor(int64_t n) { return log2_floor(n); }
 }  // namespace bh
 
 extern "C" {
+
+int bh_drift(bh_ctx *c, double dt)
+{
+    if (!c) return BH_EINVAL;
+    if (!std::isfinite(dt)) return fail(c, BH_EINVAL, "dt must be finite");
+    if (!c->built) return fail(c, BH_ESTATE, "no particles loaded");
+    TRY_HIP(c, launch_drift(c, dt));
+    c->moved = true;
+    c->energy_current = false;
+    return BH_OK;
+}
+
+int bh_kick(bh_ctx *c, double dt, const uint8_t *active)
+{
+    if (!c) return BH_EINVAL;
+    if (!std::isfinite(dt)) return fail(c, BH_EINVAL, "dt must be finite");
+    if (!c->built || !c->have_forces) return fail(c, BH_ESTATE, "kick needs a prior force evaluation");
+    TRY_HIP(c, launch_kick_masked(c, dt, active));
+    c->energy_current = false;
+    return BH_OK;
+}
+
+int bh_refit(bh_ctx *c)
+{
+    if (!c) return BH_EINVAL;
+    if (!c->built) return fail(c, BH_ESTATE, "refit needs a built tree");
+    TRY_HIP(c, rec(c, 3));
+    TRY_HIP(c, launch_group_boxes(c));
+    TRY_HIP(c, rec(c, 4));
+    TRY_HIP(c, launch_moments(c));
+    TRY_HIP(c, rec(c, 5));
+    c->moved = false;
+    return BH_OK;
+}
+
+int bh_compute_forces_active(bh_ctx *c, float theta, float eps, const uint8_t *active, float *acc,
+                             float *pot)
+{
+    if (!c) return BH_EINVAL;
+    if (!active) return fail(c, BH_EINVAL, "null active");
+    if (bad_theta(theta) || bad_eps(eps))
+        return fail(c, BH_EINVAL, "theta must be in (0, 1] and eps >= 0");
+    if (!c->built) return fail(c, BH_ESTATE, "forces need a built tree");
+    if (!c->have_forces)
+        return fail(c, BH_ESTATE, "a full force evaluation must come first (inactive particles keep theirs)");
+    if (c->moved) return fail(c, BH_ESTATE, "positions moved: refit or rebuild before forces");
+    std::vector<bh_cluster> cl = c->host_clusters;
+    for (auto &q : cl) {
+        q.theta = theta;
+        q.eps = eps;
+    }
+    TRY_ST(update_params(c, cl));
+    TRY_HIP(c, rec(c, 6));
+    TRY_HIP(c, launch_rcrit(c));
+    TRY_HIP(c, launch_active_groups(c, active));
+    TRY_HIP(c, launch_walk(c, true, true));
+    TRY_HIP(c, launch_scatter(c, acc, pot));
+    TRY_HIP(c, rec(c, 7));
+    c->energy_current = false;
+    return BH_OK;
+}
 
 int bh_default_params(bh_params *p)
 {
@@ -840,6 +903,7 @@ int bh_leapfrog_step(bh_ctx *c, double dt)
     if (!std::isfinite(dt)) return fail(c, BH_EINVAL, "dt must be finite");
     if (!c->built || !c->have_forces)
         return fail(c, BH_ESTATE, "leapfrog_step needs a prior compute_forces");
+    c->moved = false;       // the step rebuilds the tree
     std::vector<bh_cluster> cl = c->host_clusters;
     for (auto &q : cl) q.dt = dt;
     TRY_ST(update_params(c, cl));
@@ -854,6 +918,7 @@ int bh_batch_run(bh_ctx *c, int32_t nsteps)
     if (nsteps < 0) return fail(c, BH_EINVAL, "nsteps must be >= 0");
     if (!c->built || !c->have_forces)
         return fail(c, BH_ESTATE, "batch_run needs a prior force evaluation");
+    c->moved = false;       // every step rebuilds the trees
     for (int32_t s = 0; s < nsteps; ++s) {
         TRY_ST(step_graph(c));
         c->energy_current = true;
@@ -879,6 +944,7 @@ int bh_set_state(bh_ctx *c, const double *pos, const double *vel)
     reset_e0(c);
     c->have_forces = false;
     c->energy_current = false;
+    c->moved = false;
     TRY_HIP(c, enqueue_rebuild(c));
     return sync_check(c);
 }

@@ -94,7 +94,7 @@ struct DevMisc {
     uint32_t depth;
     uint32_t walk_next;                // group work counter of the walk
     uint32_t levels_done;              // levels scanned in the current build (self-clearing)
-    uint32_t pad1;
+    uint32_t nactive;                  // groups in the active list of a partial walk
     uint32_t walk_overflow;            // set if a per-wave list would overflow
     unsigned long long sum_npp;
     unsigned long long sum_npc;
@@ -125,6 +125,7 @@ struct bh_ctx {
     bool have_e0 = false;
     bool energy_current = false;  // e_out holds the sums of the current state
     bool any_eps0 = false;        // some cluster has zero softening (walk variant)
+    bool moved = false;           // positions drifted since the last build or refit
     int64_t layout = 0;     // changes whenever buffers or the cluster table change
 
     // host copies of counts, refreshed at synchronisation points
@@ -231,7 +232,8 @@ int64_t sort_blk_words(int64_t n);
 int64_t scan_tmp_words(int64_t n);
 
 // walk.hip
-hipError_t launch_walk(bh_ctx *c, bool timed);
+hipError_t launch_walk(bh_ctx *c, bool timed, bool active_only = false);
+hipError_t launch_active_groups(bh_ctx *c, const uint8_t *active);   // list for active_only
 void walk_timer_harvest(bh_ctx *c, bool block);
 hipEvent_t *walk_timer_slot(bh_ctx *c);
 hipError_t launch_scatter(bh_ctx *c, float *acc, float *pot);
@@ -257,6 +259,8 @@ int ctx_log2_floor(int64_t n);
 hipError_t launch_kick_drift(bh_ctx *c);
 hipError_t launch_energy(bh_ctx *c);
 hipError_t launch_kick_energy(bh_ctx *c);          // closing kick fused with the energy sums
+hipError_t launch_drift(bh_ctx *c, double dt);                       // x += v dt, all particles
+hipError_t launch_kick_masked(bh_ctx *c, double dt, const uint8_t *active);  // v += a dt
 hipError_t launch_set_velocities(bh_ctx *c, const double *vel);
 hipError_t launch_get_state(bh_ctx *c, double *pos, double *vel, float *acc, float *pot);
 hipError_t launch_set_positions(bh_ctx *c, const double *pos, const double *vel);

@@ -36,6 +36,36 @@ kick_drift_kernel(int64_t n, const uint32_t *__restrict__ pcl, const DevCluster 
     p4[i] = p;
 }
 
+// x += v dt for every particle (a drift without rebuilding the tree)
+__global__ void __launch_bounds__(kBlock)
+drift_kernel(int64_t n, const double4 *__restrict__ v4, double4 *__restrict__ p4, double dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double4 v = v4[i];
+    double4 p = p4[i];
+    p.x = p.x + v.x * dt;
+    p.y = p.y + v.y * dt;
+    p.z = p.z + v.z * dt;
+    p4[i] = p;
+}
+
+// v += a dt for the particles whose flag (caller order) is set, all if none given
+__global__ void __launch_bounds__(kBlock)
+kick_masked_kernel(int64_t n, const uint32_t *__restrict__ pid, const uint8_t *__restrict__ active,
+                   const float4 *__restrict__ acc4, double4 *__restrict__ v4, double dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (active && !active[pid[i]]) return;
+    const float4 a = acc4[i];
+    double4 v = v4[i];
+    v.x = v.x + (double)a.x * dt;
+    v.y = v.y + (double)a.y * dt;
+    v.z = v.z + (double)a.z * dt;
+    v4[i] = v;
+}
+
 // Per chunk: the closing kick v += a dt/2 of the chunk's cluster, then the T, W,
 // Px, Py, Pz partial sums of the new state (same order as energy_partial_kernel).
 __global__ void __launch_bounds__(kBlock)
@@ -183,6 +213,22 @@ hipError_t launch_kick_drift(bh_ctx *c)
 {
     hipLaunchKernelGGL(kick_drift_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
                        c->pcl, c->clus, c->acc4, c->v4[c->cur], c->p4[c->cur]);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_drift(bh_ctx *c, double dt)
+{
+    hipLaunchKernelGGL(drift_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
+                       c->v4[c->cur], c->p4[c->cur], dt);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_kick_masked(bh_ctx *c, double dt, const uint8_t *active)
+{
+    hipLaunchKernelGGL(kick_masked_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
+                       c->pid[c->cur], active, c->acc4, c->v4[c->cur], dt);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

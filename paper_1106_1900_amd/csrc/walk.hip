@@ -83,6 +83,7 @@ struct WalkArgs {
     uint32_t *g_npc;
     uint32_t *spill;          // kSpillPerWave entries per wavefront of the grid
     DevMisc *misc;            // group and cell counts, work counter, interaction totals
+    const uint32_t *glist;    // groups to walk (misc->nactive of them), or null: all
 };
 
 struct WaveLds {
@@ -383,7 +384,9 @@ __device__ __forceinline__ bool next_group(const WalkArgs &a, uint32_t ngroups, 
     uint32_t v = 0;
     if (lane_id() == 0) v = atomicAdd(&a.misc->walk_next, 1u);
     g = readfirst(v);
-    return g < ngroups;
+    if (g >= ngroups) return false;
+    if (a.glist) g = readfirst(a.glist[g]);
+    return true;
 }
 
 // One group: walk its cluster's tree from the root, evaluate its lists, and
@@ -595,7 +598,7 @@ template <bool kEps0>
 __global__ void __launch_bounds__(kWalkBlock)
 __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs a)
 {
-    const uint32_t ngroups = readfirst(a.misc->ngroups);
+    const uint32_t ngroups = readfirst(a.glist ? a.misc->nactive : a.misc->ngroups);
     const uint32_t ncells = readfirst(a.misc->ncells);
     __shared__ WaveLds s_lds[kWalkWaves];
     const int w = threadIdx.x / kWave;
@@ -730,7 +733,37 @@ int64_t walk_grid_waves(bh_ctx *c)
 
 // The work counter and interaction sums are cleared by launch_rcrit, which
 // always precedes the walk.
-hipError_t launch_walk(bh_ctx *c, bool timed)
+// Flags the groups that hold at least one active particle (flags[g], zero for
+// g >= ngroups up to n so that the flags can be compacted over n entries).
+__global__ void __launch_bounds__(256)
+mark_active_groups_kernel(const DevMisc *__restrict__ m, const uint32_t *__restrict__ g_first,
+                          const uint32_t *__restrict__ g_count, const uint32_t *__restrict__ pid,
+                          const uint8_t *__restrict__ active, int64_t n, uint8_t *__restrict__ flags)
+{
+    const uint32_t ngroups = m->ngroups;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < n;
+         g += (int64_t)gridDim.x * 256) {
+        uint8_t f = 0;
+        if (g < (int64_t)ngroups) {
+            const uint32_t s = g_first[g], e = s + g_count[g];
+            for (uint32_t i = s; i < e && !f; ++i) f = active[pid[i]] != 0;
+        }
+        flags[g] = f;
+    }
+}
+
+hipError_t launch_active_groups(bh_ctx *c, const uint8_t *active)
+{
+    int g = (int)((c->n + 255) / 256);
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(mark_active_groups_kernel, dim3(g), dim3(256), 0, c->stream, c->misc,
+                       c->g_first, c->g_count, c->pid[c->cur], active, c->n, c->gflag);
+    BH_LAUNCH_CHECK();
+    // the active group list goes to the sort's spare value buffer
+    return compact_flags(c, c->gflag, c->n, c->val[1], &c->misc->nactive);
+}
+
+hipError_t launch_walk(bh_ctx *c, bool timed, bool active_only)
 {
     int64_t blocks = walk_grid_waves(c) / kWalkWaves;
     if (blocks * kWalkWaves > c->walk_spill_waves) blocks = c->walk_spill_waves / kWalkWaves;
@@ -748,6 +781,7 @@ hipError_t launch_walk(bh_ctx *c, bool timed)
     a.g_npc = c->g_npc;
     a.spill = c->walk_spill;
     a.misc = c->misc;
+    a.glist = active_only ? c->val[1] : nullptr;
     hipEvent_t *ev = timed ? walk_timer_slot(c) : nullptr;
     if (ev) BH_HIP_TRY(hipEventRecord(ev[0], c->stream));
     if (c->any_eps0)

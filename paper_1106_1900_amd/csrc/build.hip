@@ -33,6 +33,8 @@
 // No kernel here needs a count on the host: cell, group and level counts stay in
 // device memory and the kernels that depend on them loop over fixed grids, so a
 // whole build can be captured in a HIP graph.
+#include <algorithm>
+
 #include "bh_internal.h"
 
 #pragma clang fp contract(off)
@@ -579,7 +581,12 @@ __device__ __forceinline__ void store_walk_multipole(uint32_t c, const double *S
 }
 
 // Moments of cell c: a leaf from its particles, a node from its children (one
-// level deeper, already done), both in array order.
+// level deeper, already done), both in array order.  Each pass over the members
+// loads a run of kRun of them at once (indices past the end repeat the last
+// member and are left out of the sums), so a pass costs one memory latency per
+// run instead of one per member; the sums keep the members' order.
+constexpr int kRun = 8;
+
 template <bool kLeaf>
 __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restrict__ c_first,
                                              const uint32_t *__restrict__ c_count,
@@ -589,51 +596,75 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
                                              double4 *__restrict__ c_com, double *__restrict__ c_S,
                                              float4 *__restrict__ q0, float4 *__restrict__ q1)
 {
+    // members [s, s + n): particles of a leaf (position, mass) or children of a
+    // node (centre of mass, mass; second moments in c_S)
+    const uint32_t s = kLeaf ? c_first[c] : c_child[c];
+    const uint32_t n = kLeaf ? c_count[c] : c_nchild[c];
+    const double4 *__restrict__ src = kLeaf ? p4 : c_com;
     double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     double S[6] = {0, 0, 0, 0, 0, 0};
-    double cx, cy, cz;
-    if (kLeaf) {
-        const uint32_t s = c_first[c], e = s + c_count[c];
-        for (uint32_t j = s; j < e; ++j) M = M + p4[j].w;
-        for (uint32_t j = s; j < e; ++j) {
-            const double4 p = p4[j];
-            sx = sx + p.w * p.x;
-            sy = sy + p.w * p.y;
-            sz = sz + p.w * p.z;
+    for (uint32_t r = 0; r < n; r += kRun) {
+        double4 q[kRun];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) q[k] = src[s + min(r + k, n - 1)];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k)
+            if (r + k < n) M = M + q[k].w;
+    }
+    for (uint32_t r = 0; r < n; r += kRun) {
+        double4 q[kRun];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) q[k] = src[s + min(r + k, n - 1)];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            if (r + k < n) {
+                sx = sx + q[k].w * q[k].x;
+                sy = sy + q[k].w * q[k].y;
+                sz = sz + q[k].w * q[k].z;
+            }
         }
-        cx = sx / M;
-        cy = sy / M;
-        cz = sz / M;
-        for (uint32_t j = s; j < e; ++j) {
-            const double4 p = p4[j];
-            const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
-            S[0] += p.w * dx * dx; S[1] += p.w * dy * dy; S[2] += p.w * dz * dz;
-            S[3] += p.w * dx * dy; S[4] += p.w * dx * dz; S[5] += p.w * dy * dz;
-        }
-    } else {
-        const uint32_t s = c_child[c], e = s + c_nchild[c];
-        for (uint32_t k = s; k < e; ++k) M = M + c_com[k].w;
-        for (uint32_t k = s; k < e; ++k) {
-            const double4 q = c_com[k];
-            sx = sx + q.w * q.x;
-            sy = sy + q.w * q.y;
-            sz = sz + q.w * q.z;
-        }
-        cx = sx / M;
-        cy = sy / M;
-        cz = sz / M;
-        for (uint32_t k = s; k < e; ++k) {
-            const double4 q = c_com[k];
-            const double ex = q.x - cx, ey = q.y - cy, ez = q.z - cz;
-            const double *Sk = c_S + 6 * (int64_t)k;
-            S[0] += Sk[0] + q.w * ex * ex; S[1] += Sk[1] + q.w * ey * ey;
-            S[2] += Sk[2] + q.w * ez * ez; S[3] += Sk[3] + q.w * ex * ey;
-            S[4] += Sk[4] + q.w * ex * ez; S[5] += Sk[5] + q.w * ey * ez;
+    }
+    const double cx = sx / M, cy = sy / M, cz = sz / M;
+    for (uint32_t r = 0; r < n; r += kRun) {
+        double4 q[kRun];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) q[k] = src[s + min(r + k, n - 1)];
+        if (kLeaf) {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                if (r + k < n) {
+                    const double dx = q[k].x - cx, dy = q[k].y - cy, dz = q[k].z - cz;
+                    const double w = q[k].w;
+                    S[0] += w * dx * dx; S[1] += w * dy * dy; S[2] += w * dz * dz;
+                    S[3] += w * dx * dy; S[4] += w * dx * dz; S[5] += w * dy * dz;
+                }
+            }
+        } else {
+            double2 Sk[kRun][3];
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const double2 *p = reinterpret_cast<const double2 *>(c_S + 6 * (int64_t)(s + min(r + k, n - 1)));
+                Sk[k][0] = p[0];
+                Sk[k][1] = p[1];
+                Sk[k][2] = p[2];
+            }
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                if (r + k < n) {
+                    const double ex = q[k].x - cx, ey = q[k].y - cy, ez = q[k].z - cz;
+                    const double w = q[k].w;
+                    S[0] += Sk[k][0].x + w * ex * ex; S[1] += Sk[k][0].y + w * ey * ey;
+                    S[2] += Sk[k][1].x + w * ez * ez; S[3] += Sk[k][1].y + w * ex * ey;
+                    S[4] += Sk[k][2].x + w * ex * ez; S[5] += Sk[k][2].y + w * ey * ez;
+                }
+            }
         }
     }
     c_com[c] = make_double4(cx, cy, cz, M);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) c_S[6 * (int64_t)c + k] = S[k];
+    double2 *out = reinterpret_cast<double2 *>(c_S + 6 * (int64_t)c);
+    out[0] = make_double2(S[0], S[1]);
+    out[1] = make_double2(S[2], S[3]);
+    out[2] = make_double2(S[4], S[5]);
     store_walk_multipole(c, S, q0, q1);
 }
 
@@ -657,9 +688,9 @@ moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restri
 }
 
 // The nodes of levels hi down to lo in one workgroup, a barrier between levels:
-// for runs of levels holding few cells, where a launch per level would cost more
-// than the work.
-constexpr int kLevelsBlock = 1024;
+// for the levels below the tree's expected depth, which normally hold no cells,
+// where a launch per level would cost more than the work.
+constexpr int kLevelsBlock = 256;
 
 __global__ void __launch_bounds__(kLevelsBlock)
 moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
@@ -849,28 +880,28 @@ hipError_t launch_moments(bh_ctx *c)
                        c->c_com, c->c_S, c->c_q0, c->c_q1);
     BH_LAUNCH_CHECK();
     // nodes from their children, deepest level first (level 20 holds only leaves).
-    // The level sizes are known on the device only; the host uses the sizes seen
-    // at its last synchronisation as a hint: a level that held more than
-    // kSmallLevel cells gets a launch of its own, runs of the others share one
-    // workgroup.  Any tree is handled correctly whatever the hint.
-    constexpr uint32_t kSmallLevel = 2048;
-    const uint32_t *hint = c->misc_h->level_count;
-    int lev = kMaxLevel - 1;
-    while (lev >= 0) {
-        if (hint[lev] > kSmallLevel) {
-            hipLaunchKernelGGL(moments_kernel<false>, dim3(g), dim3(kBlock), 0, c->stream, lev,
-                               c->misc, c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild,
-                               c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
-            BH_LAUNCH_CHECK();
-            --lev;
-        } else {
-            const int hi = lev;
-            while (lev >= 0 && hint[lev] <= kSmallLevel) --lev;
-            hipLaunchKernelGGL(moments_levels_kernel, dim3(1), dim3(kLevelsBlock), 0, c->stream, hi,
-                               lev + 1, c->misc, c->c_leaf, c->c_first, c->c_count, c->c_child,
-                               c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
-            BH_LAUNCH_CHECK();
-        }
+    // The level sizes are known on the device only; the host takes those seen at
+    // its last synchronisation as hints: levels more than two below the hinted
+    // depth (normally empty) share one workgroup, every other level gets a launch
+    // of its own with a grid sized for twice its hinted count.  The kernels read
+    // the true counts and loop over them, so any tree is handled whatever the hints.
+    const DevMisc &hint = *c->misc_h;
+    const int deep = hint.depth ? std::min(kMaxLevel - 1, (int)hint.depth + 2) : kMaxLevel - 1;
+    if (deep < kMaxLevel - 1) {
+        hipLaunchKernelGGL(moments_levels_kernel, dim3(1), dim3(kLevelsBlock), 0, c->stream,
+                           kMaxLevel - 1, deep + 1, c->misc, c->c_leaf, c->c_first, c->c_count,
+                           c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0,
+                           c->c_q1);
+        BH_LAUNCH_CHECK();
+    }
+    for (int lev = deep; lev >= 0; --lev) {
+        int gl = g;
+        if (hint.depth && hint.level_count[lev])
+            gl = (int)std::min<int64_t>(g, grid_for(2 * (int64_t)hint.level_count[lev], kBlock));
+        hipLaunchKernelGGL(moments_kernel<false>, dim3(gl), dim3(kBlock), 0, c->stream, lev, c->misc,
+                           c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild,
+                           c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
+        BH_LAUNCH_CHECK();
     }
     return hipSuccess;
 }

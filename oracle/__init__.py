@@ -12,7 +12,9 @@ What each function follows in the paper:
 * ``argsort`` - App. A (stable radix sort = stable ascending order of keys).
 * ``Tree`` - Sect. 2.1 (level-by-level cells, links), Sect. 2.2 (groups),
   Sect. 3.2 (float64 monopole and quadrupole moments).
-* ``Tree.rcrit``/``Tree.mac_accept`` - Sect. 3.3, Eq. (1).
+* ``Tree.rcrit``/``Tree.mac_accept`` - Sect. 3.3, Eq. (1); with ``mac=1`` the
+  minimum-distance test that Sect. 3.3 names as the alternative (Salmon & Warren
+  1994): the group's box must be farther than l/theta from the cell's cube.
 * ``Tree.walk_counts``/``Tree.group_lists``/``Tree.forces`` - Sect. 2.2
   breadth-first group walk with float64 evaluation.
 * ``direct`` - the direct-summation reference of Sect. 4.2.1 (Eq. (2)).
@@ -76,6 +78,9 @@ def lib():
         "orc_get_moments": (None, [vp, vp, vp, vp]),
         "orc_rcrit": (None, [vp, f, vp, vp]),
         "orc_mac_accept": (ctypes.c_int, [vp, i64, i64, f]),
+        "orc_mac_accept_min": (ctypes.c_int, [vp, i64, i64, f]),
+        "orc_set_mac": (None, [vp, ctypes.c_int]),
+        "orc_get_mac": (ctypes.c_int, [vp]),
         "orc_walk_counts": (ctypes.c_int, [vp, f, vp, vp]),
         "orc_group_lists": (i64, [vp, f, i64, vp, i64, vp, i64, vp]),
         "orc_forces": (ctypes.c_int, [vp, f, f, vp, i64, vp, vp, vp, vp]),
@@ -142,7 +147,7 @@ def argsort(key):
 class Tree:
     """The canonical tree of a particle set (Sect. 2.1-2.2, 3.2)."""
 
-    def __init__(self, pos, mass, nleaf=16, ncrit=64):
+    def __init__(self, pos, mass, nleaf=16, ncrit=64, mac=0):
         self.pos = _f64(pos)
         self.mass = _f64(mass)
         n = self.pos.shape[0]
@@ -159,6 +164,8 @@ class Tree:
         self.ncells = int(L.orc_ncells(self._h))
         self.ngroups = int(L.orc_ngroups(self._h))
         self.depth = int(L.orc_depth(self._h))
+        L.orc_set_mac(self._h, int(mac))
+        self.mac = int(L.orc_get_mac(self._h))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -222,7 +229,8 @@ class Tree:
         return r2, centre
 
     def mac_accept(self, g, c, rcrit2_c):
-        return bool(lib().orc_mac_accept(self._h, int(g), int(c), float(rcrit2_c)))
+        f = lib().orc_mac_accept_min if self.mac else lib().orc_mac_accept
+        return bool(f(self._h, int(g), int(c), float(rcrit2_c)))
 
     def walk_counts(self, theta):
         npp = np.zeros(self.ngroups, np.int64)

@@ -39,6 +39,7 @@ struct orc_tree {
     double *gc;         /* [g][3] */
     float *gh;          /* [g][3] */
     int depth;
+    int mac;            /* opening test: 0 Eq. (1), 1 minimum distance */
 };
 
 /* ------------------------------------------------------------------------- */
@@ -442,22 +443,40 @@ void orc_get_moments(const orc_tree *t, double *mass, double *com, double *S)
 /* ------------------------------------------------------------------------- */
 /* Sect. 3.3, Eq. (1): d > l/theta + delta.                                    */
 
+void orc_set_mac(orc_tree *t, int mac) { t->mac = mac ? 1 : 0; }
+
+int orc_get_mac(const orc_tree *t) { return t->mac; }
+
+/* Geometric centre of cell c (from the key prefix of any of its particles) and
+ * its side l. */
+static double cell_geometry(const orc_tree *t, int64_t c, double g[3])
+{
+    int lev = t->level[c];
+    double l = ldexp(t->L, -lev);
+    const uint32_t *q = t->q + 3 * t->first[c];
+    for (int k = 0; k < 3; ++k) {
+        uint32_t p = q[k] >> (ORC_MAX_LEVEL - lev);
+        g[k] = t->lo[k] + ((double)p + 0.5) * l;
+    }
+    return l;
+}
+
 void orc_rcrit(const orc_tree *t, float theta, float *rcrit2, double *centre)
 {
     for (int64_t c = 0; c < t->ncells; ++c) {
-        int lev = t->level[c];
-        double l = ldexp(t->L, -lev);
-        const uint32_t *q = t->q + 3 * t->first[c];
         double g[3];
-        for (int k = 0; k < 3; ++k) {
-            uint32_t p = q[k] >> (ORC_MAX_LEVEL - lev);
-            g[k] = t->lo[k] + ((double)p + 0.5) * l;
+        double l = cell_geometry(t, c, g);
+        double r;
+        if (t->mac) {
+            /* minimum-distance test: the cell's cube must lie beyond l / theta */
+            r = l / (double)theta;
+        } else {
+            double dx = t->com[3 * c] - g[0];
+            double dy = t->com[3 * c + 1] - g[1];
+            double dz = t->com[3 * c + 2] - g[2];
+            double delta = sqrt((dx * dx + dy * dy) + dz * dz);
+            r = l / (double)theta + delta;
         }
-        double dx = t->com[3 * c] - g[0];
-        double dy = t->com[3 * c + 1] - g[1];
-        double dz = t->com[3 * c + 2] - g[2];
-        double delta = sqrt((dx * dx + dy * dy) + dz * dz);
-        double r = l / (double)theta + delta;
         if (rcrit2) rcrit2[c] = (float)(r * r);
         if (centre) { centre[3 * c] = g[0]; centre[3 * c + 1] = g[1]; centre[3 * c + 2] = g[2]; }
     }
@@ -475,6 +494,31 @@ int orc_mac_accept(const orc_tree *t, int64_t g, int64_t c, float rcrit2_c)
     }
     float d2 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
     return d2 > rcrit2_c;
+}
+
+/* Minimum-distance test (Salmon & Warren 1994, named in Sect. 3.3 as the
+ * alternative): d is the smallest distance between the group's box and the
+ * cell's cube (side l about its geometric centre), taken in float32 on offsets
+ * from the group centre with the cube's half side (float)(l / 2); accept when
+ * d^2 > rmin2_c = (float)((l / theta)^2). */
+int orc_mac_accept_min(const orc_tree *t, int64_t g, int64_t c, float rmin2_c)
+{
+    double gcen[3];
+    double l = cell_geometry(t, c, gcen);
+    float h = (float)(0.5 * l);
+    float u[3];
+    for (int k = 0; k < 3; ++k) {
+        float o = (float)(gcen[k] - t->gc[3 * g + k]);
+        float d = (fabsf(o) - t->gh[3 * g + k]) - h;
+        u[k] = d > 0.0f ? d : 0.0f;
+    }
+    float d2 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+    return d2 > rmin2_c;
+}
+
+static int accept(const orc_tree *t, int64_t g, int64_t c, float rc2_c)
+{
+    return t->mac ? orc_mac_accept_min(t, g, c, rc2_c) : orc_mac_accept(t, g, c, rc2_c);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -504,7 +548,7 @@ static int walk_group(const orc_tree *t, const float *rc2, int64_t g, ivec *pc, 
         nxt->n = 0;
         for (int64_t k = 0; k < cur->n; ++k) {
             int64_t c = cur->v[k];
-            if (orc_mac_accept(t, g, c, rc2[c])) {
+            if (accept(t, g, c, rc2[c])) {
                 if (ivec_push(pc, c)) return -2;
             } else if (t->leaf[c]) {
                 if (ivec_push(ppl, c)) return -2;

@@ -87,15 +87,26 @@ void orc_get_groups(const orc_tree *t, int64_t *gfirst, int64_t *gcount,
  * mass S [c][6] = xx, yy, zz, xy, xz, yz. */
 void orc_get_moments(const orc_tree *t, double *mass, double *com, double *S);
 
-/* Opening radius of Eq. (1): r_crit = l / theta + delta, with l = L 2^-level the
- * cell side and delta the distance between the geometric centre and the centre
- * of mass.  Outputs (each optional): rcrit2[c] = (float)(r_crit^2), centre
- * [c][3] = geometric centre. */
+/* Opening test used by the walk functions below: 0 (the default) Eq. (1), 1 the
+ * minimum-distance test named in Sect. 3.3 as the alternative. */
+void orc_set_mac(orc_tree *t, int mac);
+int orc_get_mac(const orc_tree *t);
+
+/* Opening radius of the tree's test.  Eq. (1): r_crit = l / theta + delta, with
+ * l = L 2^-level the cell side and delta the distance between the geometric
+ * centre and the centre of mass; minimum distance: r_crit = l / theta.  Outputs
+ * (each optional): rcrit2[c] = (float)(r_crit^2), centre [c][3] = geometric
+ * centre. */
 void orc_rcrit(const orc_tree *t, float theta, float *rcrit2, double *centre);
 
 /* Opening test of Eq. (1) between group g and cell c, given rcrit2 of the cell.
  * Returns 1 if the cell is accepted (its multipole is used), 0 if it is opened. */
 int orc_mac_accept(const orc_tree *t, int64_t g, int64_t c, float rcrit2_c);
+
+/* Minimum-distance test between group g and cell c: the smallest distance from
+ * the group's box to the cell's cube must exceed l / theta (rmin2_c =
+ * (float)((l / theta)^2)).  Returns 1 if the cell is accepted. */
+int orc_mac_accept_min(const orc_tree *t, int64_t g, int64_t c, float rmin2_c);
 
 /* Interaction counts per group for opening angle theta (Sect. 2.2): npp = number
  * of particles in opened leaves (the group's own included), npc = number of

@@ -493,6 +493,42 @@ def bench_active(n=1 << 20, theta=0.75, eps=1.0 / 64, reps=5):
     return out
 
 
+def bench_mac(n=1 << 20, eps=1.0 / 64, reps=5, ntarget=1024):
+    """The two opening tests of Sect. 3.3 at the same theta on the Plummer sphere:
+    one force evaluation (rebuild and walk at fixed positions), the walk alone,
+    interactions per particle and Δa/a against float64 direct summation on
+    seeded targets."""
+    import torch
+
+    import paper_1106_1900_amd as bh
+    import workloads
+    pos, _, mass = workloads.plummer(n, 2)
+    rows = []
+    for theta in (0.5, 0.75):
+        for mac in (bh.MAC_EQ1, bh.MAC_MIN_DIST):
+            ctx = bh.Context()
+            ctx.set_mac(mac)
+            ctx.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda())
+            acc, _ = ctx.compute_forces(theta, eps)
+            ctx.leapfrog_step(0.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.leapfrog_step(0.0)     # rebuild and forces at the same positions
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            st = ctx.stats()
+            a = accuracy_sample(pos, mass, acc.cpu().numpy(), eps, ntarget)
+            rows.append({"theta": theta, "mac": "eq1" if mac == bh.MAC_EQ1 else "min_dist",
+                         "ms_per_eval": ms, "particles_per_s": n / (ms * 1e-3),
+                         "walk_ms": st.ms_walk_kernel, "pp_per_particle": st.sum_npp / n,
+                         "pc_per_particle": st.sum_npc / n, "median": a["median"], "p99": a["p99"]})
+            log(rows[-1])
+            ctx.close()
+    return {"workload": "plummer N=%d eps=%g, %d direct-sum targets" % (n, eps, ntarget),
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,7 +553,7 @@ def main():
                     help="device memory for the server (0: 60%% of the free memory)")
     ap.add_argument("--serve-small-budget-gib", type=float, default=4.0,
                     help="a second, constrained budget for the same trace (0: skip)")
-    ap.add_argument("--only", choices=("batch", "serve", "galaxy", "sweep", "active"),
+    ap.add_argument("--only", choices=("batch", "serve", "galaxy", "sweep", "active", "mac"),
                     help="run only that form and print its JSON (for profiling runs)")
     args = ap.parse_args()
 
@@ -543,6 +579,9 @@ def main():
         return
     if args.only == "sweep":
         print(json.dumps(bench_sweep()), flush=True)
+        return
+    if args.only == "mac":
+        print(json.dumps(bench_mac()), flush=True)
         return
     if args.only == "galaxy":
         print(json.dumps(bench_galaxy(args.steps if args.steps != 100 else 10)), flush=True)

@@ -133,7 +133,8 @@ int bh_build_tree(bh_ctx *ctx, const double *pos, const double *mass, int64_t n)
 int bh_set_velocities(bh_ctx *ctx, const double *vel);
 
 /* Accelerations and potentials of every particle by the group walk (Sect. 2.2)
- * with the opening test d > l/theta + delta (Eq. (1)) and Plummer softening
+ * with the cluster's opening test (Eq. (1) unless bh_set_mac chose the
+ * minimum-distance test) and Plummer softening
  * eps: phi_i = -sum m_j (r_ij^2 + eps^2)^(-1/2) over particles and the
  * monopole + quadrupole expansion over accepted cells.  The self pair is left
  * out.  theta in (0, 1], eps >= 0.  acc: device [n][3] float32, pot: device [n]
@@ -141,6 +142,21 @@ int bh_set_velocities(bh_ctx *ctx, const double *vel);
  * inside the context).  Needs a prior build.  Interactions are float32 on
  * offsets from each group's box centre; sums are compensated per particle. */
 int bh_compute_forces(bh_ctx *ctx, float theta, float eps, float *acc, float *pot);
+
+/* Opening tests.  BH_MAC_EQ1: Eq. (1) of Sect. 3.3, d > l/theta + delta with d the
+ * distance from the cell's centre of mass to the group's box.  BH_MAC_MIN_DIST:
+ * the minimum-distance test that Sect. 3.3 names as the alternative (Salmon &
+ * Warren 1994): the smallest distance between the group's box and the cell's
+ * cube (side l about its geometric centre) must exceed l/theta; the paper reports
+ * a 10-50% smaller acceleration error for the same theta at a higher cost.  Both
+ * are taken in float32 on offsets from the group's box centre. */
+#define BH_MAC_EQ1      0
+#define BH_MAC_MIN_DIST 1
+
+/* Set the opening test of every loaded cluster and the one bh_build_tree gives
+ * the clusters it loads (the context starts with BH_MAC_EQ1).  Takes effect for
+ * work enqueued afterwards.  BH_EINVAL for any other value. */
+int bh_set_mac(bh_ctx *ctx, int32_t mac);
 
 /* One leapfrog step (Sect. 3.1) as kick-drift-kick: v += a dt/2; x += v dt
  * (float64); rebuild the tree; forces with the last theta and eps; v += a dt/2.
@@ -225,6 +241,8 @@ typedef struct {
                            forces are evaluated) */
     int32_t nleaf;      /* 1..64; 0: the context's nleaf */
     int32_t ncrit;      /* 1..64; 0: the context's ncrit */
+    int32_t mac;        /* opening test: BH_MAC_EQ1 or BH_MAC_MIN_DIST */
+    int32_t pad;        /* zero */
 } bh_cluster;
 
 /* Load k clusters and build their forest.  clusters: host [k].  pos: device
@@ -317,6 +335,7 @@ typedef struct {
     int32_t nsteps;             /* steps after the force evaluation, >= 0 */
     int32_t nleaf;              /* 1..64, or 0: the server's */
     int32_t ncrit;              /* 1..64, or 0: the server's */
+    int32_t mac;                /* opening test: BH_MAC_EQ1 or BH_MAC_MIN_DIST */
     double arrival;             /* arrival time on the server clock (seconds, see
                                    bh_server_now); a negative value: the time of
                                    the submit call */

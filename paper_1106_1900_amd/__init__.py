@@ -8,6 +8,8 @@ import of ``Context`` fails.
 """
 
 from .binding import (  # noqa: F401
+    MAC_EQ1,
+    MAC_MIN_DIST,
     BHError,
     Cluster,
     Context,
@@ -18,4 +20,4 @@ from .binding import (  # noqa: F401
     declared_functions,
 )
 
-__all__ = ["BHError", "Cluster", "Context", "Server", "Stats", "library_path", "load_library", "declared_functions"]
+__all__ = ["MAC_EQ1", "MAC_MIN_DIST", "BHError", "Cluster", "Context", "Server", "Stats", "library_path", "load_library", "declared_functions"]

@@ -15,6 +15,7 @@ _ROOT = os.path.dirname(_HERE)
 HEADER = os.path.join(_ROOT, "include", "bh.h")
 
 BH_OK, BH_EINVAL, BH_ENOMEM, BH_EDEVICE, BH_ESTATE = 0, -1, -2, -3, -4
+MAC_EQ1, MAC_MIN_DIST = 0, 1     # opening tests (BH_MAC_EQ1, BH_MAC_MIN_DIST)
 _NAMES = {BH_EINVAL: "EINVAL", BH_ENOMEM: "ENOMEM", BH_EDEVICE: "EDEVICE", BH_ESTATE: "ESTATE"}
 
 
@@ -33,7 +34,8 @@ class Params(ctypes.Structure):
 class Cluster(ctypes.Structure):
     """One cluster of a batch (bh_cluster)."""
     _fields_ = [("n", ctypes.c_int64), ("theta", ctypes.c_float), ("eps", ctypes.c_float),
-                ("dt", ctypes.c_double), ("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32)]
+                ("dt", ctypes.c_double), ("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
+                ("mac", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -100,6 +102,7 @@ def load_library():
         "bh_destroy": (i32, [_vp]),
         "bh_build_tree": (i32, [_vp, _vp, _vp, i64]),
         "bh_set_velocities": (i32, [_vp, _vp]),
+        "bh_set_mac": (i32, [_vp, i32]),
         "bh_compute_forces": (i32, [_vp, f32, f32, _vp, _vp]),
         "bh_leapfrog_step": (i32, [_vp, f64]),
         "bh_get_state": (i32, [_vp, _vp, _vp, _vp, _vp]),
@@ -227,7 +230,7 @@ class Context:
     @staticmethod
     def _table(clusters):
         """clusters: sequence of dicts with n, theta, eps and optional dt, nleaf,
-        ncrit (0: the context's)."""
+        ncrit (0: the context's), mac (MAC_EQ1 or MAC_MIN_DIST)."""
         arr = (Cluster * len(clusters))()
         for a, q in zip(arr, clusters):
             a.n = int(q["n"])
@@ -236,6 +239,7 @@ class Context:
             a.dt = float(q.get("dt", 0.0))
             a.nleaf = int(q.get("nleaf", 0))
             a.ncrit = int(q.get("ncrit", 0))
+            a.mac = int(q.get("mac", MAC_EQ1))
         return arr
 
     def batch_build(self, clusters, pos, mass, vel=None):
@@ -289,6 +293,10 @@ class Context:
             for k, _ in TuneEntry._fields_:
                 setattr(a, k, t[k])
         self._check(self._L.bh_set_tuning(self._h, arr, len(table)))
+
+    def set_mac(self, mac):
+        """Opening test of every loaded cluster and of later bh_build_tree loads."""
+        self._check(self._L.bh_set_mac(self._h, int(mac)))
 
     def set_velocities(self, vel):
         import torch
@@ -379,8 +387,8 @@ class Request(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("pos", _vp), ("mass", _vp), ("vel", _vp),
                 ("theta", ctypes.c_float), ("eps", ctypes.c_float), ("dt", ctypes.c_double),
                 ("nsteps", ctypes.c_int32), ("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
-                ("arrival", ctypes.c_double), ("out_pos", _vp), ("out_vel", _vp),
-                ("out_acc", _vp), ("out_pot", _vp)]
+                ("mac", ctypes.c_int32), ("arrival", ctypes.c_double), ("out_pos", _vp),
+                ("out_vel", _vp), ("out_acc", _vp), ("out_pot", _vp)]
 
 
 class RequestStatus(ctypes.Structure):
@@ -467,7 +475,7 @@ class Server:
 
     def submit(self, pos, mass, vel=None, theta=0.75, eps=0.01, dt=1.0 / 128, nsteps=10,
                nleaf=0, ncrit=0, arrival=-1.0, out_pos=None, out_vel=None, out_acc=None,
-               out_pot=None):
+               out_pot=None, mac=0):
         """Queue a request; the tensors are kept alive until it is done."""
         import torch
         n = int(pos.shape[0])
@@ -477,7 +485,7 @@ class Server:
         r.mass = _dev_ptr(mass, torch.float64, (n,), "mass")
         r.vel = _dev_ptr(vel, torch.float64, (n, 3), "vel")
         r.theta, r.eps, r.dt, r.nsteps = float(theta), float(eps), float(dt), int(nsteps)
-        r.nleaf, r.ncrit, r.arrival = int(nleaf), int(ncrit), float(arrival)
+        r.nleaf, r.ncrit, r.arrival, r.mac = int(nleaf), int(ncrit), float(arrival), int(mac)
         r.out_pos = _dev_ptr(out_pos, torch.float64, (n, 3), "out_pos")
         r.out_vel = _dev_ptr(out_vel, torch.float64, (n, 3), "out_vel")
         r.out_acc = _dev_ptr(out_acc, torch.float32, (n, 3), "out_acc")

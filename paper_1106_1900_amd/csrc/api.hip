@@ -96,6 +96,7 @@ void free_buffers(bh_ctx *c)
     dfree(c->c_q1);
     dfree(c->c_rcrit2);
     dfree(c->c_rec);
+    dfree(c->c_geo);
     dfree(c->walk_spill);
     dfree(c->g_first);
     dfree(c->g_count);
@@ -180,6 +181,7 @@ hipError_t each_buffer(bh_ctx *c, const Sizes &z, F f)
     B(c->c_q1, z.cells);
     B(c->c_rcrit2, z.cells);
     B(c->c_rec, z.cells);
+    B(c->c_geo, z.cells);
     B(c->walk_spill, walk_spill_words(z.spill_waves));
     B(c->g_first, z.n);
     B(c->g_count, z.n);
@@ -323,6 +325,8 @@ int check_clusters(bh_ctx *c, const bh_cluster *cl, int64_t K, std::vector<bh_cl
         if (bad_theta(q.theta)) return fail(c, BH_EINVAL, "cluster theta must be in (0, 1]");
         if (bad_eps(q.eps)) return fail(c, BH_EINVAL, "cluster eps must be finite and >= 0");
         if (!std::isfinite(q.dt)) return fail(c, BH_EINVAL, "cluster dt must be finite");
+        if (q.mac != BH_MAC_EQ1 && q.mac != BH_MAC_MIN_DIST)
+            return fail(c, BH_EINVAL, "cluster mac must be BH_MAC_EQ1 or BH_MAC_MIN_DIST");
         n += q.n;
         if (n > 0x7fffffffLL) return fail(c, BH_EINVAL, "a batch holds fewer than 2^31 particles");
     }
@@ -343,6 +347,7 @@ void fill_params(DevCluster &d, const bh_cluster &q)
     d.theta = q.theta;
     const float e = q.eps;
     d.eps2 = e * e;
+    d.mac = (uint32_t)q.mac;
 }
 
 // Writes the cluster and chunk tables of the (checked) batch to the staging
@@ -395,7 +400,7 @@ int update_params(bh_ctx *c, const std::vector<bh_cluster> &cl)
     bool changed = false;
     for (int64_t k = 0; k < c->K && !changed; ++k) {
         const bh_cluster &a = c->host_clusters[k], &b = cl[k];
-        changed = a.theta != b.theta || a.eps != b.eps || a.dt != b.dt;
+        changed = a.theta != b.theta || a.eps != b.eps || a.dt != b.dt || a.mac != b.mac;
     }
     if (!changed) return BH_OK;
     TRY_ST(staging_ready(c));
@@ -827,8 +832,9 @@ int bh_build_tree(bh_ctx *c, const double *pos, const double *mass, int64_t n)
     if (!c) return BH_EINVAL;
     if (!pos || !mass) return fail(c, BH_EINVAL, "null pos or mass");
     if (n < 1 || n > 0x7fffffffLL) return fail(c, BH_EINVAL, "n must be in [1, 2^31)");
-    bh_cluster one;
+    bh_cluster one{};
     one.n = n;
+    one.mac = c->mac;
     // theta, eps and dt are set by the force and step calls
     one.theta = c->K == 1 && !c->host_clusters.empty() ? c->host_clusters[0].theta : 0.75f;
     one.eps = c->K == 1 && !c->host_clusters.empty() ? c->host_clusters[0].eps : 0.0f;
@@ -862,6 +868,18 @@ int bh_batch_set_params(bh_ctx *c, const bh_cluster *clusters, int64_t k)
         if (a.n != b.n || a.nleaf != b.nleaf || a.ncrit != b.ncrit)
             return fail(c, BH_EINVAL, "n, nleaf and ncrit must match the loaded batch");
     }
+    return update_params(c, cl);
+}
+
+int bh_set_mac(bh_ctx *c, int32_t mac)
+{
+    if (!c) return BH_EINVAL;
+    if (mac != BH_MAC_EQ1 && mac != BH_MAC_MIN_DIST)
+        return fail(c, BH_EINVAL, "mac must be BH_MAC_EQ1 or BH_MAC_MIN_DIST");
+    c->mac = mac;
+    if (!c->built) return BH_OK;
+    std::vector<bh_cluster> cl = c->host_clusters;
+    for (auto &q : cl) q.mac = mac;
     return update_params(c, cl);
 }
 

@@ -38,7 +38,8 @@ constexpr int kStackCap = 1408;        // >= 21 levels x 64 ranges (see walk.hip
 struct alignas(64) WalkCell {
     double cx, cy, cz;   // centre of mass (float64)
     float mass;          // cell mass (float32)
-    float rcrit2;        // squared opening radius of Eq. (1) (float32)
+    float rcrit2;        // squared opening radius (float32): (l/theta + delta)^2 for
+                         // Eq. (1), (l/theta)^2 for the minimum-distance test
     uint32_t link;       // first child (node) or first particle (leaf)
     uint32_t info;       // number of children (node) or count | 0x80000000 (leaf)
     float s3[6];         // 3 S: xx, yy, zz, xy, xz, yz (second moment about the centre of mass)
@@ -58,7 +59,8 @@ struct DevCluster {
     uint32_t ncrit;      // most particles in a group
     uint32_t chunk0;     // first chunk of the cluster in the chunk table
     uint32_t nchunk;     // chunks of the cluster
-    uint32_t pad[2];
+    uint32_t mac;        // opening test: 0 Eq. (1), 1 minimum distance
+    uint32_t pad;
 };
 static_assert(sizeof(DevCluster) == 48, "cluster record layout");
 
@@ -125,6 +127,7 @@ struct bh_ctx {
     bool have_e0 = false;
     bool energy_current = false;  // e_out holds the sums of the current state
     bool any_eps0 = false;        // some cluster has zero softening (walk variant)
+    int32_t mac = 0;              // opening test bh_build_tree gives its cluster
     bool moved = false;           // positions drifted since the last build or refit
     int64_t layout = 0;     // changes whenever buffers or the cluster table change
 
@@ -171,6 +174,7 @@ struct bh_ctx {
     float4 *c_q0 = nullptr, *c_q1 = nullptr; // float32 walk multipoles
     float *c_rcrit2 = nullptr;
     bh::WalkCell *c_rec = nullptr;           // per-cell walk record (walk.hip)
+    double4 *c_geo = nullptr;                // geometric centre, half side (minimum-distance test)
     uint32_t *walk_spill = nullptr;          // per-wave overflow of the walk stack
     int64_t walk_spill_waves = 0;
 

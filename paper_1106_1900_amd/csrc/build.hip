@@ -714,8 +714,9 @@ moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
 
 // Eq. (1): r_crit = l/theta + delta with l = L 2^-level and delta the distance of
 // the centre of mass from the cell's geometric centre; stored as float32 r_crit^2,
-// together with the rest of the cell's walk record.  theta and the domain are
-// those of the cell's cluster.
+// together with the rest of the cell's walk record.  theta, the opening test and
+// the domain are those of the cell's cluster; for the minimum-distance test
+// r_crit = l/theta and the cube (centre, half side) goes to geo.
 __global__ void __launch_bounds__(kBlock)
 rcrit_kernel(DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
              const DevDomain *__restrict__ dom, const uint32_t *__restrict__ pcl, const uint8_t *__restrict__ c_level,
@@ -723,7 +724,8 @@ rcrit_kernel(DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
              const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
              const uint8_t *__restrict__ c_leaf, const uint64_t *__restrict__ skey,
              const double4 *__restrict__ c_com, const float4 *__restrict__ q0,
-             const float4 *__restrict__ q1, float *__restrict__ rcrit2, WalkCell *__restrict__ rec)
+             const float4 *__restrict__ q1, float *__restrict__ rcrit2, WalkCell *__restrict__ rec,
+             double4 *__restrict__ geo)
 {
     // the walk that follows takes its groups from a counter cleared here
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -744,9 +746,17 @@ rcrit_kernel(DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
         const double gy = cl.lo[1] + ((double)compact3(pre >> 1) + 0.5) * l;
         const double gz = cl.lo[2] + ((double)compact3(pre >> 2) + 0.5) * l;
         const double4 cm = c_com[c];
-        const double dx = cm.x - gx, dy = cm.y - gy, dz = cm.z - gz;
-        const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
-        const double r = l / (double)theta + delta;
+        double r;
+        if (clus[k].mac) {
+            // minimum-distance test: the cube (geometric centre, half side) must lie
+            // beyond l / theta of the group's box
+            r = l / (double)theta;
+            geo[c] = make_double4(gx, gy, gz, 0.5 * l);
+        } else {
+            const double dx = cm.x - gx, dy = cm.y - gy, dz = cm.z - gz;
+            const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
+            r = l / (double)theta + delta;
+        }
         const float r2 = (float)(r * r);
         rcrit2[c] = r2;
         const bool leaf = c_leaf[c] != 0;
@@ -912,7 +922,7 @@ hipError_t launch_rcrit(bh_ctx *c)
     if (g > kFixedGrid) g = kFixedGrid;
     hipLaunchKernelGGL(rcrit_kernel, dim3(g), dim3(kBlock), 0, c->stream, c->misc, c->clus, c->dom,
                        c->pcl, c->c_level, c->c_first, c->c_count, c->c_child, c->c_nchild, c->c_leaf,
-                       c->key[0], c->c_com, c->c_q0, c->c_q1, c->c_rcrit2, c->c_rec);
+                       c->key[0], c->c_com, c->c_q0, c->c_q1, c->c_rcrit2, c->c_rec, c->c_geo);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -209,8 +209,9 @@ int ctx_err(bh_server *s, int code)
 
 bh_cluster cluster_of(const Req &q)
 {
-    bh_cluster c;
+    bh_cluster c{};
     c.n = q.r.n;
+    c.mac = q.r.mac;
     c.theta = q.r.theta;
     c.eps = q.r.eps;
     // the first unit of a request is its force evaluation: a step with dt = 0
@@ -382,8 +383,9 @@ int bh_server_submit(bh_server *s, const bh_request *r, int64_t *ticket)
     if (!r || !ticket) return sfail(s, BH_EINVAL, "null request or ticket");
     if (!r->pos || !r->mass) return sfail(s, BH_EINVAL, "null pos or mass");
     if (r->nsteps < 0) return sfail(s, BH_EINVAL, "nsteps must be >= 0");
-    bh_cluster c;
+    bh_cluster c{};
     c.n = r->n;
+    c.mac = r->mac;
     c.theta = r->theta;
     c.eps = r->eps;
     c.dt = r->dt;

@@ -2,7 +2,9 @@
 //
 // One wavefront (64 lanes) takes one group of at most 64 particles.  It walks
 // the tree from the root: up to 64 cells are tested at a time, one per lane,
-// with the opening test of Eq. (1).  An accepted cell goes to the cell list, an
+// with the cluster's opening test (Eq. (1), or the minimum distance between the
+// group's box and the cell's cube, the alternative of Sect. 3.3; both in float32
+// on offsets from the group centre).  An accepted cell goes to the cell list, an
 // opened leaf to the particle list, an opened node pushes its contiguous
 // children.  As soon as a list holds 64 entries it is evaluated: the 64 sources
 // are staged in LDS as float32 offsets from the group's box centre and every
@@ -78,6 +80,7 @@ struct WalkArgs {
     const float4 *g_half;
     const double4 *p4;        // sources and targets: x, y, z, mass (sorted order)
     const WalkCell *rec;      // per-cell walk records
+    const double4 *geo;       // per-cell geometric centre, half side (minimum-distance test)
     float4 *acc4;             // out: ax, ay, az, pot (sorted order)
     uint32_t *g_npp;
     uint32_t *g_npc;
@@ -395,8 +398,8 @@ template <bool kEps0, int M>
 __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellStack &stack,
                                            LeafList &leaves, uint32_t ncells, uint32_t gs, int gn,
                                            const double4 gc, const float4 gh, uint32_t cid,
-                                           float eps2, uint32_t &npp_out, uint32_t &npc_out,
-                                           bool &overflow_out)
+                                           float eps2, bool mindist, uint32_t &npp_out,
+                                           uint32_t &npc_out, bool &overflow_out)
 {
     const int lane = lane_id();
     const int P = (gn + M - 1) / M;
@@ -450,9 +453,20 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
             ox = (float)(w.cx - gc.x);
             oy = (float)(w.cy - gc.y);
             oz = (float)(w.cz - gc.z);
-            const float dx = fabsf(ox) - gh.x;
-            const float dy = fabsf(oy) - gh.y;
-            const float dz = fabsf(oz) - gh.z;
+            float dx, dy, dz;
+            if (mindist) {
+                // distance from the group's box to the cell's cube
+                const double4 q = a.geo[cell];
+                const float h = (float)q.w;
+                dx = (fabsf((float)(q.x - gc.x)) - gh.x) - h;
+                dy = (fabsf((float)(q.y - gc.y)) - gh.y) - h;
+                dz = (fabsf((float)(q.z - gc.z)) - gh.z) - h;
+            } else {
+                // distance from the group's box to the cell's centre of mass
+                dx = fabsf(ox) - gh.x;
+                dy = fabsf(oy) - gh.y;
+                dz = fabsf(oz) - gh.z;
+            }
             const float ux = dx > 0.0f ? dx : 0.0f;
             const float uy = dy > 0.0f ? dy : 0.0f;
             const float uz = dz > 0.0f ? dz : 0.0f;
@@ -623,21 +637,23 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
         // the group's cluster: its root is the cluster's level-0 cell
         const uint32_t cid = readfirst((uint32_t)gc.w);
         const float eps2 = a.clus[cid].eps2;
+        const bool mindist = uniform((int)a.clus[cid].mac) != 0;
         uint32_t npp = 0, npc = 0;
         bool overflow = false;
         switch (uniform(lanes_mode(gn))) {
         case 1:
-            walk_group<kEps0, 1>(a, L, stack, leaves, ncells, gs, gn, gc, gh, cid, eps2, npp, npc,
-                                 overflow);
+            walk_group<kEps0, 1>(a, L, stack, leaves, ncells, gs, gn, gc, gh, cid, eps2, mindist,
+                                 npp, npc, overflow);
             break;
         case 2:
-            walk_group<kEps0, 2>(a, L, stack, leaves, ncells, gs, gn, gc, gh, cid, eps2, npp, npc,
-                                 overflow);
+            walk_group<kEps0, 2>(a, L, stack, leaves, ncells, gs, gn, gc, gh, cid, eps2, mindist,
+                                 npp, npc, overflow);
             break;
         default:
             if (kMaxPerLane >= 3)
                 walk_group<kEps0, (kMaxPerLane >= 3 ? 3 : 1)>(a, L, stack, leaves, ncells, gs, gn,
-                                                              gc, gh, cid, eps2, npp, npc, overflow);
+                                                              gc, gh, cid, eps2, mindist, npp,
+                                                              npc, overflow);
             break;
         }
         if (lane == 0) {
@@ -776,6 +792,7 @@ hipError_t launch_walk(bh_ctx *c, bool timed, bool active_only)
     a.g_half = c->g_half;
     a.p4 = c->p4[c->cur];
     a.rec = c->c_rec;
+    a.geo = c->c_geo;
     a.acc4 = c->acc4;
     a.g_npp = c->g_npp;
     a.g_npc = c->g_npc;

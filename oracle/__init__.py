@@ -19,6 +19,9 @@ What each function follows in the paper:
   breadth-first group walk with float64 evaluation.
 * ``direct`` - the direct-summation reference of Sect. 4.2.1 (Eq. (2)).
 * ``kdk_step`` - Sect. 3.1 leapfrog; ``energy`` - Eq. (3) ingredients.
+* ``block_bins``/``Block`` - block time-steps motivated in Sect. 5 (forces only
+  for the particles due, multipole-only refits in between, a rebuild once the
+  walk has grown); the criterion and schedule are readings (bh_oracle.c).
 """
 
 import ctypes
@@ -89,6 +92,12 @@ def lib():
         "orc_kdk_step": (ctypes.c_int, [vp, vp, vp, i64, vp, vp, d, f, f,
                                         ctypes.c_int, ctypes.c_int]),
         "orc_energy": (None, [vp, vp, vp, i64, vp]),
+        "orc_block_bins": (None, [vp, i64, d, ctypes.c_int, d, d, vp]),
+        "orc_block_new": (vp, [vp, vp, vp, i64, vp, vp, f, f, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_int]),
+        "orc_block_free": (None, [vp]),
+        "orc_block_base": (d, [vp]),
+        "orc_block_step": (ctypes.c_int, [vp, vp, ctypes.c_int, d, d, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -302,3 +311,55 @@ def energy(vel, mass, pot):
     out = np.zeros(6)
     lib().orc_energy(_ptr(vel), _ptr(mass), _ptr(pot), mass.shape[0], _ptr(out))
     return out
+
+
+def block_bins(acc, dt_max, max_level, eta, length):
+    """Power-of-two time-step bins from float32 accelerations [n, 3]."""
+    a = np.ascontiguousarray(acc, dtype=np.float32)
+    n = a.shape[0]
+    bins = np.zeros(n, np.uint8)
+    lib().orc_block_bins(_ptr(a), n, float(dt_max), int(max_level), float(eta), float(length),
+                         _ptr(bins))
+    return bins
+
+
+class Block:
+    """A system advanced by block time-steps (float64, caller order).  pos, vel,
+    acc, pot are numpy arrays updated in place."""
+
+    def __init__(self, pos, vel, mass, theta, eps, nleaf=16, ncrit=64, mac=0):
+        self.pos = _f64(pos).copy()
+        self.vel = _f64(vel).copy()
+        self.mass = _f64(mass).copy()
+        n = self.pos.shape[0]
+        self.n = n
+        self.acc = np.zeros((n, 3))
+        self.pot = np.zeros(n)
+        h = lib().orc_block_new(_ptr(self.pos), _ptr(self.vel), _ptr(self.mass), n,
+                                _ptr(self.acc), _ptr(self.pot), float(theta), float(eps),
+                                int(nleaf), int(ncrit), int(mac))
+        if not h:
+            raise ValueError("oracle block system failed")
+        self._h = ctypes.c_void_p(h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_block_free(h)
+
+    @property
+    def base(self):
+        return float(lib().orc_block_base(self._h))
+
+    def step(self, bins, max_level, dt_max, growth):
+        """One block step; returns (rebuilt, interactions per particle of the last
+        walk, completed steps per particle)."""
+        b = np.ascontiguousarray(bins, dtype=np.uint8)
+        rebuilt = ctypes.c_int()
+        inter = ctypes.c_double()
+        kicks = np.zeros(self.n, np.int64)
+        st = lib().orc_block_step(self._h, _ptr(b), int(max_level), float(dt_max), float(growth),
+                                  ctypes.byref(rebuilt), ctypes.byref(inter), _ptr(kicks))
+        if st:
+            raise ValueError("oracle block step failed (%d)" % st)
+        return bool(rebuilt.value), float(inter.value), kicks

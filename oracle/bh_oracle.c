@@ -737,6 +737,172 @@ int orc_kdk_step(double *pos, double *vel, const double *mass, int64_t n,
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Block time-steps (Sect. 5: only the particles due for an update get forces,  */
+/* the moments of the existing cells are recomputed in between, and the tree is */
+/* rebuilt once the walk has become considerably more expensive).  The paper   */
+/* gives neither the time-step criterion nor the schedule; the readings here:   */
+/*  - step of particle i: dt_i = sqrt(2 eta l / |a_i|), l a length (the        */
+/*    softening), rounded down to a power-of-two fraction dt_max 2^-b of the    */
+/*    block step, b in [0, B];                                                  */
+/*  - kick-drift-kick per bin: every particle drifts every substep of           */
+/*    dt_max 2^-B; a particle of bin b is kicked (half, then half again) at     */
+/*    the end of each of its 2^b steps, with forces recomputed for the groups   */
+/*    that hold it on the tree refitted to the current positions;               */
+/*  - at the end of the block step (all particles due) the refitted tree's     */
+/*    walk is compared with the walk right after the last rebuild: more than    */
+/*    (1 + growth) times as many interactions per particle -> rebuild.          */
+
+void orc_block_bins(const float *acc, int64_t n, double dt_max, int max_level, double eta,
+                    double length, uint8_t *bins)
+{
+    /* dt_max 2^-b <= sqrt(2 eta l / |a|)  <=>  (dt_max 2^-b)^4 |a|^2 <= (2 eta l)^2 */
+    double k = 2.0 * eta * length;
+    k = k * k;
+    for (int64_t i = 0; i < n; ++i) {
+        double ax = (double)acc[3 * i], ay = (double)acc[3 * i + 1], az = (double)acc[3 * i + 2];
+        double a2 = (ax * ax + ay * ay) + az * az;
+        int b = 0;
+        for (; b < max_level; ++b) {
+            double d = ldexp(dt_max, -b);
+            double d2 = d * d;
+            if ((d2 * d2) * a2 <= k) break;
+        }
+        bins[i] = (uint8_t)b;
+    }
+}
+
+struct orc_block {
+    orc_tree *t;
+    double *pos, *vel, *acc, *pot;   /* caller's arrays, caller order */
+    const double *mass;
+    int64_t n;
+    float theta, eps;
+    int nleaf, ncrit, mac;
+    double base;                     /* interactions per particle after the last rebuild */
+};
+
+/* interactions per particle of the tree's walk (npp + npc summed over group members) */
+static int walk_per_particle(const orc_tree *t, float theta, double *out)
+{
+    int64_t *npp = (int64_t *)malloc(sizeof(int64_t) * (size_t)t->ngroups);
+    int64_t *npc = (int64_t *)malloc(sizeof(int64_t) * (size_t)t->ngroups);
+    if (!npp || !npc) { free(npp); free(npc); return -2; }
+    int st = orc_walk_counts(t, theta, npp, npc);
+    int64_t s = 0;
+    for (int64_t g = 0; g < t->ngroups && !st; ++g) s += t->gcount[g] * (npp[g] + npc[g]);
+    free(npp); free(npc);
+    *out = (double)s / (double)t->n;
+    return st;
+}
+
+static int block_rebuild(orc_block *b)
+{
+    orc_free(b->t);
+    b->t = orc_build(b->pos, b->mass, b->n, b->nleaf, b->ncrit);
+    if (!b->t) return -2;
+    orc_set_mac(b->t, b->mac);
+    return walk_per_particle(b->t, b->theta, &b->base);
+}
+
+orc_block *orc_block_new(double *pos, double *vel, const double *mass, int64_t n, double *acc,
+                         double *pot, float theta, float eps, int nleaf, int ncrit, int mac)
+{
+    orc_block *b = (orc_block *)calloc(1, sizeof(orc_block));
+    if (!b) return NULL;
+    b->pos = pos; b->vel = vel; b->mass = mass; b->acc = acc; b->pot = pot; b->n = n;
+    b->theta = theta; b->eps = eps; b->nleaf = nleaf; b->ncrit = ncrit; b->mac = mac;
+    if (block_rebuild(b) || orc_forces(b->t, theta, eps, NULL, 0, acc, pot, NULL, NULL)) {
+        orc_block_free(b);
+        return NULL;
+    }
+    return b;
+}
+
+void orc_block_free(orc_block *b)
+{
+    if (!b) return;
+    orc_free(b->t);
+    free(b);
+}
+
+double orc_block_base(const orc_block *b) { return b->base; }
+
+int orc_block_step(orc_block *b, const uint8_t *bins, int max_level, double dt_max,
+                   double growth, int *rebuilt, double *sync_inter, int64_t *kicks)
+{
+    const int64_t n = b->n;
+    const int64_t S = (int64_t)1 << max_level;
+    const double dtm = ldexp(dt_max, -max_level);
+    if (max_level < 0 || max_level > 30) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (bins[i] > max_level) return -1;
+    if (kicks) memset(kicks, 0, sizeof(int64_t) * (size_t)n);
+    /* opening half kick of every particle's first step */
+    for (int64_t i = 0; i < n; ++i) {
+        double h = 0.5 * ldexp(dt_max, -bins[i]);
+        for (int k = 0; k < 3; ++k) b->vel[3 * i + k] = b->vel[3 * i + k] + b->acc[3 * i + k] * h;
+    }
+    int64_t *gl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(b->t->ngroups + 1));
+    uint8_t *due = (uint8_t *)malloc((size_t)n);
+    if (!gl || !due) { free(gl); free(due); return -2; }
+    int st = 0;
+    *rebuilt = 0;
+    for (int64_t s = 1; s <= S && !st; ++s) {
+        for (int64_t i = 0; i < 3 * n; ++i) b->pos[i] = b->pos[i] + b->vel[i] * dtm;
+        if (s < S) {
+            /* the particles whose step ends now; forces for the groups holding them */
+            for (int64_t i = 0; i < n; ++i) due[i] = (s % ((int64_t)1 << (max_level - bins[i]))) == 0;
+            st = orc_refit(b->t, b->pos);
+            if (st) break;
+            int64_t ng = 0;
+            for (int64_t g = 0; g < b->t->ngroups; ++g) {
+                int any = 0;
+                for (int64_t j = b->t->gfirst[g]; j < b->t->gfirst[g] + b->t->gcount[g]; ++j)
+                    any |= due[b->t->perm[j]];
+                if (any) gl[ng++] = g;
+            }
+            if (ng > 0) st = orc_forces(b->t, b->theta, b->eps, gl, ng, b->acc, b->pot, NULL, NULL);
+            if (st) break;
+            /* closing half kick of the step that ends, opening half kick of the next */
+            for (int64_t i = 0; i < n; ++i) {
+                if (!due[i]) continue;
+                double h = 0.5 * ldexp(dt_max, -bins[i]);
+                for (int k = 0; k < 3; ++k) b->vel[3 * i + k] = b->vel[3 * i + k] + b->acc[3 * i + k] * h;
+                for (int k = 0; k < 3; ++k) b->vel[3 * i + k] = b->vel[3 * i + k] + b->acc[3 * i + k] * h;
+                if (kicks) kicks[i] += 1;
+            }
+        } else {
+            /* every particle is due: rebuild if the refitted tree's walk has grown */
+            int rb = 1;
+            double inter = 0.0;
+            if (growth > 0.0) {
+                st = orc_refit(b->t, b->pos);
+                if (!st) st = walk_per_particle(b->t, b->theta, &inter);
+                if (st) break;
+                rb = inter > (1.0 + growth) * b->base;
+            }
+            if (rb) {
+                st = block_rebuild(b);
+                if (st) break;
+                inter = b->base;
+            }
+            *rebuilt = rb;
+            if (sync_inter) *sync_inter = inter;
+            st = orc_forces(b->t, b->theta, b->eps, NULL, 0, b->acc, b->pot, NULL, NULL);
+            if (st) break;
+            for (int64_t i = 0; i < n; ++i) {
+                double h = 0.5 * ldexp(dt_max, -bins[i]);
+                for (int k = 0; k < 3; ++k) b->vel[3 * i + k] = b->vel[3 * i + k] + b->acc[3 * i + k] * h;
+                if (kicks) kicks[i] += 1;
+            }
+        }
+    }
+    free(gl);
+    free(due);
+    return st;
+}
+
 void orc_energy(const double *vel, const double *mass, const double *pot, int64_t n,
                 double out[6])
 {

@@ -143,6 +143,28 @@ int orc_kdk_step(double *pos, double *vel, const double *mass, int64_t n,
                  double *acc, double *pot, double dt, float theta, float eps,
                  int nleaf, int ncrit);
 
+/* Block time-steps.  Bin of each particle from its float32 acceleration
+ * acc [n][3]: the smallest b in [0, max_level] with dt_max 2^-b <= sqrt(2 eta
+ * length / |a|), decided as (dt_max 2^-b)^4 |a|^2 <= (2 eta length)^2 in
+ * float64 (max_level if none). */
+void orc_block_bins(const float *acc, int64_t n, double dt_max, int max_level, double eta,
+                    double length, uint8_t *bins);
+
+/* A system advanced by block steps: the arrays are the caller's (caller order)
+ * and are updated in place; creation builds the tree and fills acc, pot. */
+typedef struct orc_block orc_block;
+orc_block *orc_block_new(double *pos, double *vel, const double *mass, int64_t n, double *acc,
+                         double *pot, float theta, float eps, int nleaf, int ncrit, int mac);
+void orc_block_free(orc_block *b);
+/* interactions per particle of the walk right after the last rebuild */
+double orc_block_base(const orc_block *b);
+/* One block step of dt_max with the given bins (caller order): 2^max_level
+ * substeps; see bh_oracle.c for the schedule.  *rebuilt: the tree was rebuilt at
+ * the end; *sync_inter: interactions per particle of the walk that gave the
+ * final forces; kicks (optional, [n]): steps completed per particle. */
+int orc_block_step(orc_block *b, const uint8_t *bins, int max_level, double dt_max,
+                   double growth, int *rebuilt, double *sync_inter, int64_t *kicks);
+
 /* out = {T, W, E, Px, Py, Pz}: kinetic energy, potential energy (half the
  * mass-weighted sum of phi), their sum, and the linear momentum. */
 void orc_energy(const double *vel, const double *mass, const double *pot, int64_t n,

@@ -1,0 +1,140 @@
+"""Pins of the oracle's block time-steps (Sect. 5: forces only for the particles
+due, multipole-only refits in between, a rebuild once the walk has grown).  The
+paper gives neither the time-step criterion nor the schedule; the pins check the
+readings taken (bh_oracle.c) against closed forms, against the oracle's own
+shared-step leapfrog, and against the integrator's order."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+
+def test_bins_against_the_closed_form():
+    rng = np.random.default_rng(3)
+    n = 20000
+    acc = (rng.standard_normal((n, 3)) * np.exp(rng.uniform(-6, 6, (n, 1)))).astype(np.float32)
+    acc[:5] = 0.0
+    dt_max, B, eta, length = 1 / 16, 6, 0.025, 0.01
+    bins = oracle.block_bins(acc, dt_max, B, eta, length)
+    a = np.linalg.norm(acc.astype(np.float64), axis=1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        x = np.log2(dt_max / np.sqrt(2 * eta * length / a))   # bins needed: ceil(x)
+        want = np.clip(np.ceil(x), 0, B).astype(int)
+        clear = (a == 0) | (np.abs(x - np.round(x)) > 1e-9)
+    want[a == 0] = 0
+    assert clear.sum() > n - 10
+    assert np.array_equal(bins[clear], want[clear])
+    assert np.all(bins[:5] == 0)
+    # the bin never decreases as |a| grows
+    order = np.argsort(a, kind="stable")
+    assert np.all(np.diff(bins[order].astype(int)) >= 0)
+    assert set(np.unique(bins)) == set(range(B + 1))
+
+
+def test_one_level_always_rebuilding_is_the_leapfrog():
+    pos, vel, m = workloads.plummer(2000, 41)
+    b = oracle.Block(pos, vel, m, 0.6, 0.01)
+    p, v = pos.copy(), vel.copy()
+    t = oracle.Tree(p, m)
+    acc, pot, _, _ = t.forces(0.6, 0.01)
+    for _ in range(3):
+        rebuilt, _, kicks = b.step(np.zeros(2000, np.uint8), 0, 1 / 64, 0.0)
+        oracle.kdk_step(p, v, m, acc, pot, 1 / 64, 0.6, 0.01)
+        assert rebuilt and np.all(kicks == 1)
+        assert np.array_equal(b.pos, p) and np.array_equal(b.vel, v)
+        assert np.array_equal(b.acc, acc) and np.array_equal(b.pot, pot)
+
+
+def test_coarsest_bin_only_drifts_between_its_kicks():
+    # every particle in bin 0 of a 3-level block: no kick before the end, so the
+    # step is the leapfrog step with its drift cut into 8 pieces
+    pos, vel, m = workloads.plummer(1500, 42)
+    b = oracle.Block(pos, vel, m, 0.6, 0.01)
+    p, v = pos.copy(), vel.copy()
+    t = oracle.Tree(p, m)
+    acc, pot, _, _ = t.forces(0.6, 0.01)
+    _, _, kicks = b.step(np.zeros(1500, np.uint8), 3, 1 / 32, 0.0)
+    oracle.kdk_step(p, v, m, acc, pot, 1 / 32, 0.6, 0.01)
+    assert np.all(kicks == 1)
+    assert np.allclose(b.pos, p, rtol=0, atol=1e-14)
+    assert np.allclose(b.vel, v, rtol=0, atol=1e-12)
+
+
+def test_each_particle_completes_two_to_the_bin_steps():
+    pos, vel, m = workloads.clustered(2500, 43)
+    rng = np.random.default_rng(44)
+    bins = rng.integers(0, 5, 2500).astype(np.uint8)
+    b = oracle.Block(pos, vel, m, 0.7, 0.01)
+    _, _, kicks = b.step(bins, 4, 1 / 64, 0.0)
+    assert np.array_equal(kicks, 1 << bins.astype(np.int64))
+
+
+def test_finest_bin_equals_shared_steps_of_the_finest_size():
+    # theta -> 0 makes the forces the direct sum whatever the tree (refit or
+    # rebuild), so all particles in bin B must follow 2^B leapfrog steps of dt/2^B
+    pos, vel, m = workloads.plummer(300, 45)
+    b = oracle.Block(pos, vel, m, 1e-6, 0.01)
+    p, v = pos.copy(), vel.copy()
+    acc, pot = oracle.direct(p, m, 0.01)
+    b.step(np.full(300, 2, np.uint8), 2, 1 / 16, 0.0)
+    for _ in range(4):
+        oracle.kdk_step(p, v, m, acc, pot, 1 / 64, 1e-6, 0.01)
+    assert np.allclose(b.pos, p, rtol=0, atol=1e-13)
+    assert np.allclose(b.vel, v, rtol=0, atol=1e-12)
+
+
+def _orbit_error(bins, nper, e=0.5, m1=1.0, m2=0.3):
+    M = m1 + m2
+    rp = 1.0 - e
+    vp = np.sqrt(M * (1 + e) / rp)
+    pos = np.array([[-m2 / M * rp, 0, 0], [m1 / M * rp, 0, 0]])
+    vel = np.array([[0, -m2 / M * vp, 0], [0, m1 / M * vp, 0]])
+    mass = np.array([m1, m2])
+    b = oracle.Block(pos, vel, mass, 1.0, 0.0, 1, 1)
+
+    def energy():
+        T = 0.5 * (mass * (b.vel ** 2).sum(axis=1)).sum()
+        return T - m1 * m2 / np.linalg.norm(b.pos[0] - b.pos[1])
+    e0 = energy()
+    period = 2 * np.pi / np.sqrt(M)
+    worst = 0.0
+    for _ in range(nper):
+        b.step(np.array(bins, np.uint8), 2, period / nper, 0.0)
+        worst = max(worst, abs((energy() - e0) / e0))
+    return worst
+
+
+@pytest.mark.parametrize("bins", [(0, 2), (1, 2), (2, 0)])
+def test_second_order_with_mixed_bins(bins):
+    # an eccentric Kepler orbit over one period: halving the block step divides
+    # the largest energy error by 4
+    errs = [_orbit_error(bins, n) for n in (64, 128, 256)]
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 < a / b < 4.4, errs
+
+
+def test_rebuild_rule_and_the_walk_it_measures():
+    pos, vel, m = workloads.plummer(3000, 46)
+    b = oracle.Block(pos, vel, m, 0.6, 0.01)
+    base0 = b.base
+    t0 = oracle.Tree(pos, m)
+    npp, npc = t0.walk_counts(0.6)
+    assert base0 == (t0.groups()["count"] * (npp + npc)).sum() / 3000
+    bins = oracle.block_bins(b.acc.astype(np.float32), 1 / 8, 3, 0.025, 0.01)
+    # a growth limit that cannot be reached: the walk of the refitted tree
+    rebuilt, inter, _ = b.step(bins, 3, 1 / 8, 1e9)
+    assert not rebuilt and b.base == base0
+    t0.refit(b.pos)
+    npp, npc = t0.walk_counts(0.6)
+    assert inter == (t0.groups()["count"] * (npp + npc)).sum() / 3000
+    assert inter > base0        # the refitted cells have grown
+    # a limit below the growth: rebuilt, and the new base is the new tree's walk
+    rebuilt, inter2, _ = b.step(bins, 3, 1 / 8, 1e-9)
+    assert rebuilt
+    t1 = oracle.Tree(b.pos, m)
+    npp, npc = t1.walk_counts(0.6)
+    assert b.base == inter2 == (t1.groups()["count"] * (npp + npc)).sum() / 3000
+    acc, pot, _, _ = t1.forces(0.6, 0.01)
+    assert np.array_equal(b.acc, acc) and np.array_equal(b.pot, pot)

@@ -529,6 +529,74 @@ def bench_mac(n=1 << 20, eps=1.0 / 64, reps=5, ntarget=1024):
             "rows": rows}
 
 
+def bench_block(n=1 << 20, theta=0.75, eps=1.0 / 64, dt_max=1.0 / 16, levels=5, eta=0.01,
+                growth=0.1, blocks=6, workload="plummer"):
+    """Block time-steps against shared steps on the Plummer sphere: the same
+    span of time advanced by block steps of dt_max with up to 2^levels substeps,
+    and by leapfrog steps of the finest occupied bin's size (the step a shared
+    scheme needs for its most demanding particle); time, rebuilds, force
+    evaluations and energy error of each."""
+    import numpy as np
+    import torch
+
+    import paper_1106_1900_amd as bh
+    import workloads
+    if workload == "galaxy":
+        pos, vel, mass = workloads.galaxy(seed=3)
+        n = pos.shape[0]
+    else:
+        pos, vel, mass = workloads.plummer(n, 2)
+
+    def fresh():
+        ctx = bh.Context()
+        ctx.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda())
+        ctx.set_velocities(torch.from_numpy(vel).cuda())
+        ctx.compute_forces(theta, eps, want=False)
+        return ctx
+
+    ctx = fresh()
+    e0 = ctx.energy()[2]
+    _, count = ctx.block_bins(dt_max, eta, eps, levels)
+    rows = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(blocks):
+        t1 = time.perf_counter()
+        st = ctx.block_step(dt_max, eta, eps, levels, growth)
+        st["ms"] = 1e3 * (time.perf_counter() - t1)
+        rows.append(st)
+        log({k: st[k] for k in ("ms", "rebuilt", "updates", "walked_groups", "sync_interactions",
+                                "base_interactions")})
+    torch.cuda.synchronize()
+    block_ms = 1e3 * (time.perf_counter() - t0)
+    e_block = ctx.energy()[2]
+    ctx.close()
+
+    finest = max(b for b in range(levels + 1) if count[b] > 0)
+    ctx = fresh()
+    steps = blocks << finest
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.leapfrog_step(dt_max / (1 << finest))
+    torch.cuda.synchronize()
+    shared_ms = 1e3 * (time.perf_counter() - t0)
+    e_shared = ctx.energy()[2]
+    ctx.close()
+    return {"workload": "%s N=%d theta=%g eps=%g, %d block steps of dt_max=%g with %d levels "
+                        "(eta=%g, length=eps, growth=%g) vs %d leapfrog steps of %g"
+                        % (workload, n, theta, eps, blocks, dt_max, levels, eta, growth, steps,
+                           dt_max / (1 << finest)),
+            "bins_at_start": count[:levels + 1],
+            "block": {"ms_total": block_ms, "ms_per_block_step": block_ms / blocks,
+                      "rebuilds": int(sum(r["rebuilt"] for r in rows)),
+                      "particle_updates": int(sum(r["updates"] for r in rows)),
+                      "energy_error": (e_block - e0) / e0, "steps": rows},
+            "shared": {"ms_total": shared_ms, "ms_per_step": shared_ms / steps,
+                       "particle_updates": int(steps * n), "energy_error": (e_shared - e0) / e0},
+            "speedup": shared_ms / block_ms}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -553,7 +621,7 @@ def main():
                     help="device memory for the server (0: 60%% of the free memory)")
     ap.add_argument("--serve-small-budget-gib", type=float, default=4.0,
                     help="a second, constrained budget for the same trace (0: skip)")
-    ap.add_argument("--only", choices=("batch", "serve", "galaxy", "sweep", "active", "mac"),
+    ap.add_argument("--only", choices=("batch", "serve", "galaxy", "sweep", "active", "mac", "block"),
                     help="run only that form and print its JSON (for profiling runs)")
     args = ap.parse_args()
 
@@ -582,6 +650,12 @@ def main():
         return
     if args.only == "mac":
         print(json.dumps(bench_mac()), flush=True)
+        return
+    if args.only == "block":
+        print(json.dumps(bench_block()), flush=True)
+        for growth in (0.1, 0.0):
+            print(json.dumps(bench_block(theta=0.4, eps=0.02, dt_max=1.0 / 16, levels=6, eta=0.01,
+                                         growth=growth, blocks=3, workload="galaxy")), flush=True)
         return
     if args.only == "galaxy":
         print(json.dumps(bench_galaxy(args.steps if args.steps != 100 else 10)), flush=True)

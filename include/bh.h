@@ -221,6 +221,51 @@ int bh_compute_forces_active(bh_ctx *ctx, float theta, float eps, const uint8_t 
                              float *acc, float *pot);
 
 /* ---------------------------------------------------------------------------
+ * Block time-steps (Sect. 5): particles advance with power-of-two fractions of a
+ * block step; between synchronisation points only the groups holding particles
+ * due for an update are walked, on the tree whose moments are refitted to the
+ * current positions, and the tree is rebuilt when its walk has grown too
+ * expensive.  The paper gives neither the criterion nor the schedule; the
+ * readings (criterion dt_i = sqrt(2 eta length / |a_i|), bins held for a block
+ * step, kick-drift-kick per bin) are described in block.hip.  Work runs on the
+ * context stream with each cluster's theta and eps (from the last force call);
+ * the block parameters apply to every cluster.
+ */
+typedef struct {
+    double dt_max;      /* block step: bin b steps with dt_max 2^-b (> 0) */
+    double eta;         /* accuracy parameter of the criterion (> 0) */
+    double length;      /* length of the criterion, e.g. the softening (> 0) */
+    int32_t max_level;  /* B: bins 0..B, 2^B substeps per block step (0..15) */
+    float growth;       /* rebuild at the end of a block step when the refitted tree's
+                           walk has more than (1 + growth) times the interactions per
+                           particle of the walk right after the last rebuild; <= 0:
+                           rebuild every block step (with B = 0: the leapfrog step) */
+} bh_block_params;
+
+typedef struct {
+    int64_t substeps;           /* 2^B */
+    int64_t rebuilt;            /* 1 if the tree was rebuilt at the end of the step */
+    int64_t updates;            /* particle steps completed: sum over particles of 2^bin */
+    int64_t walked_groups;      /* groups walked over the step (partial and full walks) */
+    double sync_interactions;   /* interactions per particle of the walk that gave the
+                                   final forces */
+    double base_interactions;   /* the same for the walk right after the last rebuild */
+    int64_t bin_count[16];      /* particles per bin during the step */
+} bh_block_stats;
+
+/* Bins of the particles from their current accelerations, as the next block
+ * step would assign them.  bins: device [n] uint8, caller order (may be NULL);
+ * count: host [16] particles per bin (may be NULL).  Synchronous. */
+int bh_block_bins(bh_ctx *ctx, const bh_block_params *p, uint8_t *bins, int64_t *count);
+
+/* One block step of dt_max: bins from the current accelerations, 2^B substeps,
+ * rebuild test at the end.  Needs current forces of every particle (a force
+ * call, leapfrog step or earlier block step, and no drift since).  out: host,
+ * may be NULL.  Synchronous (once at the end; once more at the end when
+ * growth > 0, for the rebuild test). */
+int bh_block_step(bh_ctx *ctx, const bh_block_params *p, bh_block_stats *out);
+
+/* ---------------------------------------------------------------------------
  * Batches: K independent particle systems ("clusters") in one context.  Each
  * cluster gets its own domain and tree (the trees of the batch form one forest:
  * cluster k's root is cell k), its own opening angle, softening, leaf and group

@@ -33,6 +33,8 @@ struct orc_tree {
     uint8_t *leaf;
     int32_t *nchild;
     double *M, *com, *S; /* [c], [c][3], [c][6] */
+    double *side;        /* [c] side l of the opening test: L 2^-level after a build,
+                            grown to the extent of the cell's particles by a refit */
     /* groups */
     int64_t ngroups;
     int64_t *gfirst, *gcount;
@@ -323,7 +325,7 @@ void orc_free(orc_tree *t)
     free(t->perm); free(t->key); free(t->q); free(t->x); free(t->m);
     free(t->level); free(t->prefix); free(t->first); free(t->count);
     free(t->parent); free(t->child); free(t->leaf); free(t->nchild);
-    free(t->M); free(t->com); free(t->S);
+    free(t->M); free(t->com); free(t->S); free(t->side);
     free(t->gfirst); free(t->gcount); free(t->gc); free(t->gh);
     free(t);
 }
@@ -360,7 +362,9 @@ orc_tree *orc_build(const double *pos, const double *mass, int64_t n, int nleaf,
     t->M = (double *)malloc(sizeof(double) * (size_t)t->ncells);
     t->com = (double *)malloc(sizeof(double) * 3 * (size_t)t->ncells);
     t->S = (double *)malloc(sizeof(double) * 6 * (size_t)t->ncells);
-    if (!t->M || !t->com || !t->S) goto fail;
+    t->side = (double *)malloc(sizeof(double) * (size_t)t->ncells);
+    if (!t->M || !t->com || !t->S || !t->side) goto fail;
+    for (int64_t c = 0; c < t->ncells; ++c) t->side[c] = ldexp(t->L, -t->level[c]);
     build_moments(t);
     if (build_groups(t)) goto fail;
     return t;
@@ -374,7 +378,10 @@ fail:
 /* Sect. 5: between rebuilds it suffices to recompute the multipole moments of
  * the cells whose particles moved.  The cells, groups, keys and domain of the
  * build stay; the particles take the new positions (input order) and every
- * cell's moments and every group's box are recomputed from them. */
+ * cell's moments and every group's box are recomputed from them.  The paper
+ * names the growth of the cell size l as what makes the walk of a refitted
+ * tree slower: a cell's side becomes the larger of its build side L 2^-level
+ * and the largest side of its particles' tight box. */
 int orc_refit(orc_tree *t, const double *pos)
 {
     if (!t || !pos) return -1;
@@ -386,6 +393,20 @@ int orc_refit(orc_tree *t, const double *pos)
     }
     build_moments(t);
     group_boxes(t);
+    for (int64_t c = 0; c < t->ncells; ++c) {
+        double ext = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double lo = INFINITY, hi = -INFINITY;
+            for (int64_t j = t->first[c]; j < t->first[c] + t->count[c]; ++j) {
+                double x = t->x[3 * j + k];
+                lo = x < lo ? x : lo;
+                hi = x > hi ? x : hi;
+            }
+            ext = hi - lo > ext ? hi - lo : ext;
+        }
+        double l = ldexp(t->L, -t->level[c]);
+        t->side[c] = ext > l ? ext : l;
+    }
     return 0;
 }
 
@@ -465,7 +486,8 @@ void orc_rcrit(const orc_tree *t, float theta, float *rcrit2, double *centre)
 {
     for (int64_t c = 0; c < t->ncells; ++c) {
         double g[3];
-        double l = cell_geometry(t, c, g);
+        (void)cell_geometry(t, c, g);
+        double l = t->side[c];
         double r;
         if (t->mac) {
             /* minimum-distance test: the cell's cube must lie beyond l / theta */
@@ -504,8 +526,8 @@ int orc_mac_accept(const orc_tree *t, int64_t g, int64_t c, float rcrit2_c)
 int orc_mac_accept_min(const orc_tree *t, int64_t g, int64_t c, float rmin2_c)
 {
     double gcen[3];
-    double l = cell_geometry(t, c, gcen);
-    float h = (float)(0.5 * l);
+    (void)cell_geometry(t, c, gcen);
+    float h = (float)(0.5 * t->side[c]);
     float u[3];
     for (int k = 0; k < 3; ++k) {
         float o = (float)(gcen[k] - t->gc[3 * g + k]);

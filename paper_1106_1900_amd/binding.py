@@ -38,6 +38,24 @@ class Cluster(ctypes.Structure):
                 ("mac", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
+class BlockParams(ctypes.Structure):
+    """bh_block_params: block time-steps."""
+    _fields_ = [("dt_max", ctypes.c_double), ("eta", ctypes.c_double), ("length", ctypes.c_double),
+                ("max_level", ctypes.c_int32), ("growth", ctypes.c_float)]
+
+
+class BlockStats(ctypes.Structure):
+    _fields_ = [("substeps", ctypes.c_int64), ("rebuilt", ctypes.c_int64),
+                ("updates", ctypes.c_int64), ("walked_groups", ctypes.c_int64),
+                ("sync_interactions", ctypes.c_double), ("base_interactions", ctypes.c_double),
+                ("bin_count", ctypes.c_int64 * 16)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "bin_count"}
+        d["bin_count"] = list(self.bin_count)
+        return d
+
+
 class TuneEntry(ctypes.Structure):
     _fields_ = [("log2n", ctypes.c_int32), ("theta", ctypes.c_float), ("nleaf", ctypes.c_int32),
                 ("ncrit", ctypes.c_int32), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
@@ -114,6 +132,8 @@ def load_library():
         "bh_kick": (i32, [_vp, f64, _vp]),
         "bh_refit": (i32, [_vp]),
         "bh_compute_forces_active": (i32, [_vp, f32, f32, _vp, _vp, _vp]),
+        "bh_block_bins": (i32, [_vp, ctypes.POINTER(BlockParams), _vp, _vp]),
+        "bh_block_step": (i32, [_vp, ctypes.POINTER(BlockParams), ctypes.POINTER(BlockStats)]),
         "bh_batch_build": (i32, [_vp, ctypes.POINTER(Cluster), i64, _vp, _vp, _vp]),
         "bh_batch_set_params": (i32, [_vp, ctypes.POINTER(Cluster), i64]),
         "bh_batch_forces": (i32, [_vp, _vp, _vp]),
@@ -225,6 +245,28 @@ class Context:
             _dev_ptr(acc, torch.float32, (self.n, 3), "acc"),
             _dev_ptr(pot, torch.float32, (self.n,), "pot")))
         return acc, pot
+
+    # --- block time-steps ---------------------------------------------------
+    @staticmethod
+    def _block_params(dt_max, eta, length, max_level, growth):
+        return BlockParams(float(dt_max), float(eta), float(length), int(max_level), float(growth))
+
+    def block_bins(self, dt_max, eta, length, max_level, growth=0.0):
+        """Bins (uint8 [n] device tensor, caller order) the next block step would
+        use, and the particles per bin."""
+        import torch
+        bins = torch.empty((self.n,), dtype=torch.uint8, device=self._device())
+        count = (ctypes.c_int64 * 16)()
+        p = self._block_params(dt_max, eta, length, max_level, growth)
+        self._check(self._L.bh_block_bins(self._h, ctypes.byref(p), _vp(bins.data_ptr()), count))
+        return bins, list(count)
+
+    def block_step(self, dt_max, eta, length, max_level, growth):
+        """One block step; returns its statistics (bh_block_stats as a dict)."""
+        p = self._block_params(dt_max, eta, length, max_level, growth)
+        st = BlockStats()
+        self._check(self._L.bh_block_step(self._h, ctypes.byref(p), ctypes.byref(st)))
+        return st.as_dict()
 
     # --- batches ------------------------------------------------------------
     @staticmethod

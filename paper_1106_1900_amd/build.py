@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbh.so")
-SOURCES = ["sort.hip", "build.hip", "walk.hip", "integrate.hip", "api.hip", "serve.hip", "tune.hip"]
+SOURCES = ["sort.hip", "build.hip", "walk.hip", "integrate.hip", "api.hip", "serve.hip", "tune.hip",
+           "block.hip"]
 ARCH = "gfx950"
 
 HIPFLAGS = [

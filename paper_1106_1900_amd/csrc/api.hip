@@ -97,6 +97,9 @@ void free_buffers(bh_ctx *c)
     dfree(c->c_rcrit2);
     dfree(c->c_rec);
     dfree(c->c_geo);
+    dfree(c->c_box);
+    dfree(c->bins);
+    dfree(c->due);
     dfree(c->walk_spill);
     dfree(c->g_first);
     dfree(c->g_count);
@@ -182,6 +185,9 @@ hipError_t each_buffer(bh_ctx *c, const Sizes &z, F f)
     B(c->c_rcrit2, z.cells);
     B(c->c_rec, z.cells);
     B(c->c_geo, z.cells);
+    B(c->c_box, 6 * z.cells);
+    B(c->bins, z.n);
+    B(c->due, z.n);
     B(c->walk_spill, walk_spill_words(z.spill_waves));
     B(c->g_first, z.n);
     B(c->g_count, z.n);
@@ -439,6 +445,7 @@ hipError_t enqueue_finish_build(bh_ctx *c)
 hipError_t enqueue_load(bh_ctx *c, const double *pos, const double *mass, const double *vel)
 {
     c->cur = 0;
+    c->refitted = false;
     BH_HIP_TRY(launch_cluster_ids(c));
     BH_HIP_TRY(rec(c, 0));
     BH_HIP_TRY(launch_domain(c, pos));
@@ -453,6 +460,7 @@ hipError_t enqueue_load(bh_ctx *c, const double *pos, const double *mass, const 
 // Rebuild from the particles held in the context (after a drift or set_state).
 hipError_t enqueue_rebuild(bh_ctx *c)
 {
+    c->refitted = false;
     BH_HIP_TRY(rec(c, 0));
     BH_HIP_TRY(launch_domain(c, nullptr));
     BH_HIP_TRY(launch_keys(c, nullptr));
@@ -468,6 +476,7 @@ hipError_t enqueue_forces(bh_ctx *c, float *acc, float *pot)
     BH_HIP_TRY(rec(c, 6));
     BH_HIP_TRY(launch_rcrit(c));
     BH_HIP_TRY(launch_walk(c, !c->capturing));
+    if (!c->refitted) BH_HIP_TRY(launch_walk_base(c));
     BH_HIP_TRY(launch_scatter(c, acc, pot));
     BH_HIP_TRY(rec(c, 7));
     return hipSuccess;
@@ -680,6 +689,17 @@ int ctx_sync_check(bh_ctx *c) { return sync_check(c); }
 
 int ctx_log2_floor(int64_t n) { return log2_floor(n); }
 
+hipError_t ctx_enqueue_rebuild(bh_ctx *c) { return enqueue_rebuild(c); }
+
+hipError_t ctx_enqueue_refit(bh_ctx *c)
+{
+    c->refitted = true;
+    BH_HIP_TRY(launch_group_boxes(c));
+    return launch_moments(c, true);
+}
+
+hipError_t ctx_enqueue_forces(bh_ctx *c) { return enqueue_forces(c, nullptr, nullptr); }
+
 }  // namespace bh
 
 extern "C" {
@@ -712,9 +732,10 @@ int bh_refit(bh_ctx *c)
     TRY_HIP(c, rec(c, 3));
     TRY_HIP(c, launch_group_boxes(c));
     TRY_HIP(c, rec(c, 4));
-    TRY_HIP(c, launch_moments(c));
+    TRY_HIP(c, launch_moments(c, true));
     TRY_HIP(c, rec(c, 5));
     c->moved = false;
+    c->refitted = true;
     return BH_OK;
 }
 

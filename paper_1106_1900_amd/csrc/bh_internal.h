@@ -81,6 +81,7 @@ struct Chunk {
     uint32_t pad;
 };
 constexpr int kChunk = 4096;           // particles per chunk
+constexpr int kMaxBins = 16;           // time-step bins of the block scheme (levels 0..15)
 
 // Small device-side scalars shared by the build and walk kernels.
 struct DevMisc {
@@ -102,6 +103,13 @@ struct DevMisc {
     unsigned long long sum_npc;
     unsigned long long tot_npp;        // never reset: totals over all walks
     unsigned long long tot_npc;
+    // block time-steps: interactions per particle of the full walk right after
+    // the last rebuild (valid if base_valid), particles per time-step bin
+    double base_inter;
+    uint32_t base_valid;
+    uint32_t pad1;
+    uint32_t bin_count[kMaxBins];
+    unsigned long long walked_groups;  // groups walked by the partial walks of a block step
 };
 
 }  // namespace bh
@@ -129,6 +137,7 @@ struct bh_ctx {
     bool any_eps0 = false;        // some cluster has zero softening (walk variant)
     int32_t mac = 0;              // opening test bh_build_tree gives its cluster
     bool moved = false;           // positions drifted since the last build or refit
+    bool refitted = false;        // the cells' moments were refitted since the last build
     int64_t layout = 0;     // changes whenever buffers or the cluster table change
 
     // host copies of counts, refreshed at synchronisation points
@@ -175,6 +184,9 @@ struct bh_ctx {
     float *c_rcrit2 = nullptr;
     bh::WalkCell *c_rec = nullptr;           // per-cell walk record (walk.hip)
     double4 *c_geo = nullptr;                // geometric centre, half side (minimum-distance test)
+    double *c_box = nullptr;                 // [c][6] tight box of a refitted cell: lo x, y, z, hi x, y, z
+    uint8_t *bins = nullptr;                 // block time-step bin per particle (caller order)
+    uint8_t *due = nullptr;                  // particles due for forces at a substep (caller order)
     uint32_t *walk_spill = nullptr;          // per-wave overflow of the walk stack
     int64_t walk_spill_waves = 0;
 
@@ -223,7 +235,7 @@ hipError_t launch_reorder(bh_ctx *c, const uint32_t *perm);
 hipError_t launch_tree(bh_ctx *c);
 hipError_t launch_groups(bh_ctx *c);
 hipError_t launch_group_boxes(bh_ctx *c);
-hipError_t launch_moments(bh_ctx *c);
+hipError_t launch_moments(bh_ctx *c, bool boxes = false);   // boxes: also tight cell boxes (refit)
 hipError_t launch_rcrit(bh_ctx *c);                 // per-cluster theta; also fills c_rec
 hipError_t launch_cluster_ids(bh_ctx *c);           // pcl from the chunk table
 
@@ -258,6 +270,12 @@ int ctx_update_params(bh_ctx *c, const std::vector<bh_cluster> &cl);
 int ctx_step(bh_ctx *c, bool graph);
 int ctx_sync_check(bh_ctx *c);
 int ctx_log2_floor(int64_t n);
+hipError_t ctx_enqueue_rebuild(bh_ctx *c);   // keys .. moments from the held particles
+hipError_t ctx_enqueue_refit(bh_ctx *c);     // group boxes and moments of the existing cells
+hipError_t ctx_enqueue_forces(bh_ctx *c);    // opening radii and the full walk
+
+// block.hip
+hipError_t launch_walk_base(bh_ctx *c);      // records the walk after a rebuild
 
 // integrate.hip (per-cluster dt from the cluster table)
 hipError_t launch_kick_drift(bh_ctx *c);

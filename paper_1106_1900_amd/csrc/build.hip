@@ -587,14 +587,15 @@ __device__ __forceinline__ void store_walk_multipole(uint32_t c, const double *S
 // run instead of one per member; the sums keep the members' order.
 constexpr int kRun = 8;
 
-template <bool kLeaf>
+template <bool kLeaf, bool kBox>
 __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restrict__ c_first,
                                              const uint32_t *__restrict__ c_count,
                                              const uint32_t *__restrict__ c_child,
                                              const uint32_t *__restrict__ c_nchild,
                                              const double4 *__restrict__ p4,
                                              double4 *__restrict__ c_com, double *__restrict__ c_S,
-                                             float4 *__restrict__ q0, float4 *__restrict__ q1)
+                                             float4 *__restrict__ q0, float4 *__restrict__ q1,
+                                             double2 *__restrict__ box)
 {
     // members [s, s + n): particles of a leaf (position, mass) or children of a
     // node (centre of mass, mass; second moments in c_S)
@@ -603,6 +604,10 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
     const double4 *__restrict__ src = kLeaf ? p4 : c_com;
     double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     double S[6] = {0, 0, 0, 0, 0, 0};
+    // kBox: the tight box of the cell's particles (min and max are exact, so the
+    // order of the members does not matter): a leaf's from its particles, a
+    // node's as the union of its children's
+    double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t r = 0; r < n; r += kRun) {
         double4 q[kRun];
 #pragma unroll
@@ -610,6 +615,24 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
 #pragma unroll
         for (int k = 0; k < kRun; ++k)
             if (r + k < n) M = M + q[k].w;
+        if (kBox && kLeaf) {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                blo[0] = fmin(blo[0], q[k].x); bhi[0] = fmax(bhi[0], q[k].x);
+                blo[1] = fmin(blo[1], q[k].y); bhi[1] = fmax(bhi[1], q[k].y);
+                blo[2] = fmin(blo[2], q[k].z); bhi[2] = fmax(bhi[2], q[k].z);
+            }
+        }
+        if (kBox && !kLeaf) {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                const double2 *b = box + 3 * (int64_t)(s + min(r + k, n - 1));
+                const double2 b0 = b[0], b1 = b[1], b2 = b[2];   // lo x, y; lo z, hi x; hi y, z
+                blo[0] = fmin(blo[0], b0.x); blo[1] = fmin(blo[1], b0.y);
+                blo[2] = fmin(blo[2], b1.x); bhi[0] = fmax(bhi[0], b1.y);
+                bhi[1] = fmax(bhi[1], b2.x); bhi[2] = fmax(bhi[2], b2.y);
+            }
+        }
     }
     for (uint32_t r = 0; r < n; r += kRun) {
         double4 q[kRun];
@@ -661,6 +684,12 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
         }
     }
     c_com[c] = make_double4(cx, cy, cz, M);
+    if (kBox) {
+        double2 *b = box + 3 * (int64_t)c;
+        b[0] = make_double2(blo[0], blo[1]);
+        b[1] = make_double2(blo[2], bhi[0]);
+        b[2] = make_double2(bhi[1], bhi[2]);
+    }
     double2 *out = reinterpret_cast<double2 *>(c_S + 6 * (int64_t)c);
     out[0] = make_double2(S[0], S[1]);
     out[1] = make_double2(S[2], S[3]);
@@ -669,13 +698,15 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
 }
 
 // kLeaves: every leaf of the tree (any level); otherwise the nodes of one level.
-template <bool kLeaves>
+// kBox: also the cells' tight boxes (refits).
+template <bool kLeaves, bool kBox>
 __global__ void __launch_bounds__(kBlock)
 moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restrict__ c_leaf,
                const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
                const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
                const double4 *__restrict__ p4, double4 *__restrict__ c_com,
-               double *__restrict__ c_S, float4 *__restrict__ q0, float4 *__restrict__ q1)
+               double *__restrict__ c_S, float4 *__restrict__ q0, float4 *__restrict__ q1,
+               double2 *__restrict__ box)
 {
     const uint32_t begin = kLeaves ? 0u : m->level_offset[level];
     const uint32_t count = kLeaves ? m->ncells : m->level_count[level];
@@ -683,7 +714,8 @@ moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restri
         const uint32_t c = begin + t;
         const bool leaf = c_leaf[c] != 0;
         if (leaf != kLeaves) continue;
-        cell_moments<kLeaves>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S, q0, q1);
+        cell_moments<kLeaves, kBox>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S, q0,
+                                    q1, box);
     }
 }
 
@@ -692,13 +724,14 @@ moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restri
 // where a launch per level would cost more than the work.
 constexpr int kLevelsBlock = 256;
 
+template <bool kBox>
 __global__ void __launch_bounds__(kLevelsBlock)
 moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
                       const uint8_t *__restrict__ c_leaf, const uint32_t *__restrict__ c_first,
                       const uint32_t *__restrict__ c_count, const uint32_t *__restrict__ c_child,
                       const uint32_t *__restrict__ c_nchild, const double4 *__restrict__ p4,
                       double4 *__restrict__ c_com, double *__restrict__ c_S,
-                      float4 *__restrict__ q0, float4 *__restrict__ q1)
+                      float4 *__restrict__ q0, float4 *__restrict__ q1, double2 *__restrict__ box)
 {
     for (int level = hi; level >= lo; --level) {
         const uint32_t begin = m->level_offset[level];
@@ -706,7 +739,8 @@ moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
         for (uint32_t t = threadIdx.x; t < count; t += kLevelsBlock) {
             const uint32_t c = begin + t;
             if (c_leaf[c] == 0)
-                cell_moments<false>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S, q0, q1);
+                cell_moments<false, kBox>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S,
+                                          q0, q1, box);
         }
         __syncthreads();
     }
@@ -725,7 +759,7 @@ rcrit_kernel(DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
              const uint8_t *__restrict__ c_leaf, const uint64_t *__restrict__ skey,
              const double4 *__restrict__ c_com, const float4 *__restrict__ q0,
              const float4 *__restrict__ q1, float *__restrict__ rcrit2, WalkCell *__restrict__ rec,
-             double4 *__restrict__ geo)
+             double4 *__restrict__ geo, const double2 *__restrict__ box)
 {
     // the walk that follows takes its groups from a counter cleared here
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -746,16 +780,28 @@ rcrit_kernel(DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
         const double gy = cl.lo[1] + ((double)compact3(pre >> 1) + 0.5) * l;
         const double gz = cl.lo[2] + ((double)compact3(pre >> 2) + 0.5) * l;
         const double4 cm = c_com[c];
+        // after a refit the side is the larger of l and the extent of the cell's
+        // particles (box: lo x, y, z, hi x, y, z)
+        double side = l;
+        if (box) {
+            const double2 b0 = box[3 * (int64_t)c], b1 = box[3 * (int64_t)c + 1],
+                          b2 = box[3 * (int64_t)c + 2];
+            double ext = 0.0;
+            const double e[3] = {b1.y - b0.x, b2.x - b0.y, b2.y - b1.x};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ext = e[a] > ext ? e[a] : ext;
+            side = ext > l ? ext : l;
+        }
         double r;
         if (clus[k].mac) {
             // minimum-distance test: the cube (geometric centre, half side) must lie
-            // beyond l / theta of the group's box
-            r = l / (double)theta;
-            geo[c] = make_double4(gx, gy, gz, 0.5 * l);
+            // beyond side / theta of the group's box
+            r = side / (double)theta;
+            geo[c] = make_double4(gx, gy, gz, 0.5 * side);
         } else {
             const double dx = cm.x - gx, dy = cm.y - gy, dz = cm.z - gz;
             const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
-            r = l / (double)theta + delta;
+            r = side / (double)theta + delta;
         }
         const float r2 = (float)(r * r);
         rcrit2[c] = r2;
@@ -880,14 +926,15 @@ hipError_t launch_group_boxes(bh_ctx *c)
     return hipSuccess;
 }
 
-hipError_t launch_moments(bh_ctx *c)
+template <bool kBox>
+hipError_t moments_launches(bh_ctx *c, double2 *box)
 {
     int g = grid_for(c->cap_c, kBlock);
     if (g > kFixedGrid) g = kFixedGrid;
     // every leaf, whatever its level, from its particles
-    hipLaunchKernelGGL(moments_kernel<true>, dim3(g), dim3(kBlock), 0, c->stream, 0, c->misc,
+    hipLaunchKernelGGL((moments_kernel<true, kBox>), dim3(g), dim3(kBlock), 0, c->stream, 0, c->misc,
                        c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild, c->p4[c->cur],
-                       c->c_com, c->c_S, c->c_q0, c->c_q1);
+                       c->c_com, c->c_S, c->c_q0, c->c_q1, box);
     BH_LAUNCH_CHECK();
     // nodes from their children, deepest level first (level 20 holds only leaves).
     // The level sizes are known on the device only; the host takes those seen at
@@ -898,22 +945,28 @@ hipError_t launch_moments(bh_ctx *c)
     const DevMisc &hint = *c->misc_h;
     const int deep = hint.depth ? std::min(kMaxLevel - 1, (int)hint.depth + 2) : kMaxLevel - 1;
     if (deep < kMaxLevel - 1) {
-        hipLaunchKernelGGL(moments_levels_kernel, dim3(1), dim3(kLevelsBlock), 0, c->stream,
+        hipLaunchKernelGGL((moments_levels_kernel<kBox>), dim3(1), dim3(kLevelsBlock), 0, c->stream,
                            kMaxLevel - 1, deep + 1, c->misc, c->c_leaf, c->c_first, c->c_count,
                            c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0,
-                           c->c_q1);
+                           c->c_q1, box);
         BH_LAUNCH_CHECK();
     }
     for (int lev = deep; lev >= 0; --lev) {
         int gl = g;
         if (hint.depth && hint.level_count[lev])
             gl = (int)std::min<int64_t>(g, grid_for(2 * (int64_t)hint.level_count[lev], kBlock));
-        hipLaunchKernelGGL(moments_kernel<false>, dim3(gl), dim3(kBlock), 0, c->stream, lev, c->misc,
-                           c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild,
-                           c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1);
+        hipLaunchKernelGGL((moments_kernel<false, kBox>), dim3(gl), dim3(kBlock), 0, c->stream, lev,
+                           c->misc, c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild,
+                           c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1, box);
         BH_LAUNCH_CHECK();
     }
     return hipSuccess;
+}
+
+hipError_t launch_moments(bh_ctx *c, bool boxes)
+{
+    if (boxes) return moments_launches<true>(c, reinterpret_cast<double2 *>(c->c_box));
+    return moments_launches<false>(c, nullptr);
 }
 
 hipError_t launch_rcrit(bh_ctx *c)
@@ -922,7 +975,8 @@ hipError_t launch_rcrit(bh_ctx *c)
     if (g > kFixedGrid) g = kFixedGrid;
     hipLaunchKernelGGL(rcrit_kernel, dim3(g), dim3(kBlock), 0, c->stream, c->misc, c->clus, c->dom,
                        c->pcl, c->c_level, c->c_first, c->c_count, c->c_child, c->c_nchild, c->c_leaf,
-                       c->key[0], c->c_com, c->c_q0, c->c_q1, c->c_rcrit2, c->c_rec, c->c_geo);
+                       c->key[0], c->c_com, c->c_q0, c->c_q1, c->c_rcrit2, c->c_rec, c->c_geo,
+                       c->refitted ? reinterpret_cast<const double2 *>(c->c_box) : nullptr);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

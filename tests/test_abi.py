@@ -38,7 +38,8 @@ def test_library_exports_every_declared_symbol():
 STRUCTS = [("bh_params", "Params"), ("bh_stats", "Stats"), ("bh_tree_host", "TreeHost"),
            ("bh_cluster", "Cluster"), ("bh_server_params", "ServerParams"),
            ("bh_request", "Request"), ("bh_request_status", "RequestStatus"),
-           ("bh_server_stats", "ServerStats"), ("bh_tune_entry", "TuneEntry")]
+           ("bh_server_stats", "ServerStats"), ("bh_tune_entry", "TuneEntry"),
+           ("bh_block_params", "BlockParams"), ("bh_block_stats", "BlockStats")]
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -18,11 +18,14 @@ def _drifted(pos, vel, dt):
     return pos + vel * dt          # the same float64 operations as the device drift
 
 
-def test_refit_matches_the_oracle_refit():
+@pytest.mark.parametrize("dt", [1 / 64, 1 / 8])
+def test_refit_matches_the_oracle_refit(dt):
+    # three drifts, then a refit: moments, boxes, grown cell sides (the opening
+    # radii), counts and forces against the oracle's refit
     import torch
     pos, vel, m = workloads.plummer(30_000, 51)
-    theta, eps, dt = 0.6, 0.01, 1 / 64
-    say("case refit", pos.shape[0])
+    theta, eps = 0.6, 0.01
+    say("case refit", pos.shape[0], dt)
     ctx = gpu_build(pos, m, 16, 64)
     ctx.set_velocities(to_dev(vel))
     ctx.compute_forces(theta, eps, want=False)

@@ -1,5 +1,7 @@
 """Pins of the oracle's multipole-only update (Sect. 5: between rebuilds only the
-moments of the cells whose particles moved are recomputed)."""
+moments of the cells whose particles moved are recomputed; the walk of a refitted
+tree slows down because the cells' size l grows, so a refit also grows each
+cell's side to the extent of its particles)."""
 
 import numpy as np
 import pytest
@@ -18,11 +20,77 @@ def test_refit_at_the_build_positions_changes_nothing():
     t = oracle.Tree(pos, m)
     M0, c0, S0 = _moments(t)
     g0 = t.groups()
+    r0, _ = t.rcrit(0.6)
     t.refit(pos)
     M1, c1, S1 = _moments(t)
     g1 = t.groups()
+    r1, _ = t.rcrit(0.6)
     assert np.array_equal(M0, M1) and np.array_equal(c0, c1) and np.array_equal(S0, S1)
     assert np.array_equal(g0["centre"], g1["centre"]) and np.array_equal(g0["half"], g1["half"])
+    assert np.array_equal(r0, r1)
+
+
+def _grown_rcrit2(t, pos, theta):
+    """Eq. (1) radius of every cell with the side grown to its particles' extent,
+    from the exported cells, domain and sorted positions."""
+    c = t.cells()
+    perm, _ = t.order()
+    x = pos[perm]
+    lo, L, _ = t.domain()
+    l = L * np.ldexp(1.0, -c["level"].astype(np.int64))
+    ext = np.zeros(t.ncells)
+    for i in range(t.ncells):
+        p = x[c["first"][i]:c["first"][i] + c["count"][i]]
+        ext[i] = (p.max(axis=0) - p.min(axis=0)).max()
+    side = np.maximum(l, ext)
+    _, centre = t.rcrit(theta)
+    d = t.moments()["com"] - centre
+    delta = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
+    r = side / np.float64(np.float32(theta)) + delta
+    return (r * r).astype(np.float32), side, l
+
+
+@pytest.mark.parametrize("dt", [1 / 64, 1 / 8])
+def test_refit_grows_the_cell_side_to_the_particles_extent(dt):
+    pos, vel, m = workloads.plummer(4000, 36)
+    t = oracle.Tree(pos, m)
+    new = pos + vel * dt
+    t.refit(new)
+    want, side, l = _grown_rcrit2(t, new, 0.7)
+    got, _ = t.rcrit(0.7)
+    assert np.array_equal(got, want)
+    assert np.any(side > l)            # some cells have spread beyond their cube
+    if dt >= 1 / 8:
+        # the refitted tree's walk is costlier than a fresh build's (Sect. 5)
+        fresh = oracle.Tree(new, m)
+        npp0, npc0 = fresh.walk_counts(0.7)
+        npp1, npc1 = t.walk_counts(0.7)
+        i0 = (fresh.groups()["count"] * (npp0 + npc0)).sum()
+        i1 = (t.groups()["count"] * (npp1 + npc1)).sum()
+        assert i1 > 1.2 * i0
+
+
+def test_refit_side_of_a_spread_system():
+    # positions scaled by 3 about the first particle: every cell holding two or
+    # more distinct points now spans three times its former extent
+    pos, _, m = workloads.plummer(1500, 37)
+    t = oracle.Tree(pos, m)
+    new = pos[0] + 3.0 * (pos - pos[0])
+    t.refit(new)
+    _, side, l = _grown_rcrit2(t, new, 0.5)
+    c = t.cells()
+    perm, _ = t.order()
+    x = pos[perm]
+    grown = 0
+    for i in range(t.ncells):
+        p = x[c["first"][i]:c["first"][i] + c["count"][i]]
+        e = (p.max(axis=0) - p.min(axis=0)).max()
+        assert side[i] >= 3.0 * e * (1 - 1e-9)
+        if 3.0 * e * (1 + 1e-9) < l[i]:
+            assert side[i] == l[i]
+        else:
+            grown += 1
+    assert grown > t.ncells // 10
 
 
 def test_refit_equals_a_fresh_build_with_the_same_cells():

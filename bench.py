@@ -597,6 +597,61 @@ def bench_block(n=1 << 20, theta=0.75, eps=1.0 / 64, dt_max=1.0 / 16, levels=5, 
             "speedup": shared_ms / block_ms}
 
 
+def bench_merger(t_end=1000.0, dt=1.0 / 64, eps=0.1, thetas=(0.75, 0.5), sample=1.0):
+    """The long-run energy test of the paper's merger (Sect. 4.2.2, Table 2) on the
+    synthetic two-galaxy encounter of the same particle numbers: shared leapfrog
+    steps of dt to t_end (graph replays), energy sampled every `sample` time units;
+    dE = (E0 - Et) / E0 at the end and its largest magnitude on the way, the
+    black holes' separation, and the wall time."""
+    import numpy as np
+    import torch
+
+    import paper_1106_1900_amd as bh
+    import workloads
+    pos, vel, mass = workloads.merger()
+    n = pos.shape[0]
+    bhs = workloads.black_holes(n)
+    per = int(round(sample / dt))
+    out = {"workload": "two-galaxy encounter, %d bodies (2 x (1e5 halo + 2e4 stars + 1 black "
+                       "hole)), mass ratio 1:3, parabolic orbit d0 = 40, pericentre 4; eps = %g, "
+                       "dt = %g, T = %g" % (n, eps, dt, t_end), "runs": []}
+    for theta in thetas:
+        ctx = bh.Context()
+        ctx.batch_build([dict(n=n, theta=theta, eps=eps, dt=dt)], torch.from_numpy(pos).cuda(),
+                        torch.from_numpy(mass).cuda(), torch.from_numpy(vel).cuda())
+        ctx.batch_forces(want=False)
+        ctx.batch_energy()                 # E0
+        trace, sep = [], []
+        de_max = 0.0
+        steps = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = 0
+        while steps * dt < t_end - 1e-9:
+            ctx.batch_run(per)
+            steps += per
+            de = float(ctx.batch_energy()[0][6])
+            de_max = max(de_max, abs(de))
+            k += 1
+            if k % 10 == 0:
+                x = ctx.get_positions()[0][torch.as_tensor(bhs, device="cuda")].cpu().numpy()
+                trace.append([steps * dt, de])
+                sep.append([steps * dt, float(np.linalg.norm(x[0] - x[1]))])
+            if k % 100 == 0:
+                log("theta %g t %.0f dE %.3e dE_max %.3e (%.1f s)"
+                    % (theta, steps * dt, de, de_max, time.perf_counter() - t0))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = ctx.stats()
+        out["runs"].append({"theta": theta, "steps": steps, "dE_end": de, "dE_max": de_max,
+                            "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+                            "particle_steps_per_s": n * steps / wall,
+                            "graph_launches": st.graph_launches, "dE_every_10": trace,
+                            "black_hole_separation_every_10": sep})
+        ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -621,8 +676,11 @@ def main():
                     help="device memory for the server (0: 60%% of the free memory)")
     ap.add_argument("--serve-small-budget-gib", type=float, default=4.0,
                     help="a second, constrained budget for the same trace (0: skip)")
-    ap.add_argument("--only", choices=("batch", "serve", "galaxy", "sweep", "active", "mac", "block"),
+    ap.add_argument("--only", choices=("batch", "serve", "galaxy", "sweep", "active", "mac", "block",
+                                       "merger"),
                     help="run only that form and print its JSON (for profiling runs)")
+    ap.add_argument("--merger-time", type=float, default=1000.0,
+                    help="end time of the merger run (N-body units)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -650,6 +708,9 @@ def main():
         return
     if args.only == "mac":
         print(json.dumps(bench_mac()), flush=True)
+        return
+    if args.only == "merger":
+        print(json.dumps(bench_merger(t_end=args.merger_time)), flush=True)
         return
     if args.only == "block":
         print(json.dumps(bench_block()), flush=True)

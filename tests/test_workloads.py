@@ -80,3 +80,35 @@ def test_request_trace_is_poisson():
     assert np.mean(np.log(n)) == pytest.approx((np.log(1024) + np.log(2097152)) / 2, rel=0.02)
     assert {q["shape"] for q in tr} == {"plummer", "hernquist"}
     assert {q["theta"] for q in tr} == {0.5, 0.75}
+
+
+def test_merger_recipe():
+    # two galaxies of 10^5 halo + 2 x 10^4 star particles + one black hole each
+    # (the paper's 240,002 bodies), mass ratio 1:3, parabolic orbit of the two
+    # centres of mass with the requested pericentre, whole system at rest
+    pos, vel, mass = workloads.merger(seed=6, d0=40.0, rp=4.0)
+    n = pos.shape[0]
+    assert n == 240_002 and vel.shape == (n, 3) and mass.shape == (n,)
+    half = n // 2
+    a, b = slice(0, half), slice(half, n)
+    Ma, Mb = mass[a].sum(), mass[b].sum()
+    assert Mb / Ma == pytest.approx(1.0 / 3.0, rel=1e-12)
+    M = Ma + Mb
+    assert np.allclose((mass[:, None] * pos).sum(axis=0) / M, 0.0, atol=1e-12)
+    assert np.allclose((mass[:, None] * vel).sum(axis=0) / M, 0.0, atol=1e-12)
+    ca = (mass[a, None] * pos[a]).sum(axis=0) / Ma
+    cb = (mass[b, None] * pos[b]).sum(axis=0) / Mb
+    ua = (mass[a, None] * vel[a]).sum(axis=0) / Ma
+    ub = (mass[b, None] * vel[b]).sum(axis=0) / Mb
+    bh = workloads.black_holes(n)
+    assert np.allclose(pos[bh[0]], ca, atol=1e-9) and np.allclose(pos[bh[1]], cb, atol=1e-9)
+    r, u = cb - ca, ub - ua
+    assert np.linalg.norm(r) == pytest.approx(40.0, rel=1e-9)
+    # zero orbital energy and pericentre L^2 / (2 M) of a parabola
+    assert 0.5 * u @ u - M / np.linalg.norm(r) == pytest.approx(0.0, abs=1e-9)
+    L = np.linalg.norm(np.cross(r, u))
+    assert L * L / (2.0 * M) == pytest.approx(4.0, rel=1e-9)
+    assert r @ u < 0                                   # approaching
+    # each black hole holds 0.1% of its galaxy's particle mass
+    assert mass[bh[0]] == pytest.approx(1e-3 * (Ma - mass[bh[0]]), rel=1e-9)
+    assert mass[bh[1]] == pytest.approx(1e-3 * (Mb - mass[bh[1]]), rel=1e-9)

@@ -10,6 +10,7 @@ of shape (n,).
 
 from .batches import cluster_batch, cluster_sizes, hernquist, request_trace
 from .galaxy import galaxy
+from .merger import black_holes, merger, parabolic_orbit
 from .plummer import plummer, plummer_radii
 from .shapes import (
     two_body,
@@ -21,6 +22,9 @@ from .shapes import (
 )
 
 __all__ = [
+    "black_holes",
+    "merger",
+    "parabolic_orbit",
     "cluster_batch",
     "cluster_sizes",
     "hernquist",

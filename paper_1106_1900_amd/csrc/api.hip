@@ -144,7 +144,8 @@ Sizes sizes_for(bh_ctx *c, int64_t n, int64_t K, int nleaf_min)
     z.K = K;
     z.chunks = n / kChunk + K + 1;     // every layout with <= n particles, <= K clusters
     z.cells = cell_bound(n, K, nleaf_min);
-    z.blk = std::max(sort_blk_words(n), (int64_t)kLevels * ((n + kTreeTile - 1) / kTreeTile) + kLevels);
+    z.blk = std::max(sort_blk_words(n),
+                     (int64_t)(kLevels + 1) * ((n + kTreeTile - 1) / kTreeTile) + kLevels + 1);
     z.scan = scan_tmp_words(n);
     z.spill_waves = walk_grid_waves(c);
     return z;

@@ -276,7 +276,8 @@ __device__ __forceinline__ uint8_t split_level(uint64_t a, uint64_t b)
 }
 
 // Per particle: split level, leaf level; per block and level: number of cells
-// starting in the block.  blk layout: [level][block].  H is the largest leaf size
+// starting in the block.  blk layout: [level][block], then a row of the leaves
+// starting in each block.  H is the largest leaf size
 // of the batch (the halo); each particle uses its own cluster's leaf size.
 __global__ void __launch_bounds__(kTreeTile)
 split_leaf_kernel(const uint64_t *__restrict__ key, const uint32_t *__restrict__ pcl, int64_t n,
@@ -347,7 +348,9 @@ split_leaf_kernel(const uint64_t *__restrict__ key, const uint32_t *__restrict__
     }
     __syncthreads();
     if (t < kLevels) blk[(int64_t)t * nblk + blockIdx.x] = s_cnt[t];
-    if (t == 0 && s_leaves) atomicAdd(&m->nleaves, s_leaves);
+    // leaves started in this block: one more row of the count table, summed by
+    // scan_levels_kernel (a device-wide atomic per block serialises at one address)
+    if (t == 0) blk[(int64_t)kLevels * nblk + blockIdx.x] = s_leaves;
 }
 
 // level counts -> level offsets (level-major order), total cells, depth.
@@ -372,10 +375,11 @@ __device__ void level_finalize(const uint32_t *__restrict__ tot, DevMisc *m, int
     m->level_offset[kLevels] = (uint32_t)off;
     m->ncells = (uint32_t)off;
     m->depth = depth;
+    m->nleaves = __hip_atomic_load(&tot[kLevels], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// one block per level: exclusive scan of the level's block counts in place; the
-// last block to finish derives the level offsets
+// one block per level (and one for the leaf row): exclusive scan of the row's
+// block counts in place; the last block to finish derives the level offsets
 __global__ void scan_levels_kernel(uint32_t *__restrict__ blk, int nblk, uint32_t *__restrict__ tot,
                                    DevMisc *m, int64_t cap_c)
 {
@@ -890,14 +894,14 @@ hipError_t launch_tree(bh_ctx *c)
 {
     const int64_t n = c->n;
     const int nblk = grid_for(n, kTreeTile);
-    uint32_t *blk = c->blk;                       // [kLevels][nblk]
-    uint32_t *tot = c->blk + (int64_t)kLevels * nblk;
+    uint32_t *blk = c->blk;                       // [kLevels + 1][nblk]
+    uint32_t *tot = c->blk + (int64_t)(kLevels + 1) * nblk;
     const int H = c->max_nleaf;
     const size_t lds = (size_t)((kTreeTile + 2 * H + 15) & ~15) + (size_t)kTreeTile * H;
     hipLaunchKernelGGL(split_leaf_kernel, dim3(nblk), dim3(kTreeTile), lds, c->stream, c->key[0],
                        c->pcl, n, H, c->clus, c->split, c->lam, c->gflag, blk, nblk, c->misc);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(scan_levels_kernel, dim3(kLevels), dim3(256), 0, c->stream, blk, nblk, tot,
+    hipLaunchKernelGGL(scan_levels_kernel, dim3(kLevels + 1), dim3(256), 0, c->stream, blk, nblk, tot,
                        c->misc, c->cap_c);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(emit_cells_kernel, dim3(nblk), dim3(kTreeTile), 0, c->stream, c->split,

@@ -37,7 +37,8 @@
 // is summed in plain float32 and the tile sums are added to the particle's
 // totals with an error-free two-sum (compensated accumulation).
 //
-// Groups are handed out in Morton order from one device-wide counter, so at any
+// Groups are handed out in Morton order (a wavefront's first group is its own
+// index, the rest come from one device-wide counter), so at any
 // moment all 256 CUs work on neighbouring groups whose interaction lists overlap:
 // the active part of the tree stays small and shared in the Infinity Cache.
 // (Splitting the groups into per-XCD ranges, so that each XCD's L2 sees one
@@ -381,11 +382,19 @@ __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t 
     wave_sync();
 }
 
-// next group from the device-wide counter (false when all are taken)
-__device__ __forceinline__ bool next_group(const WalkArgs &a, uint32_t ngroups, uint32_t &g)
+// next group (false when all are taken): wavefront w of the grid's W starts
+// with group w; every later group comes from the device-wide counter, offset by
+// W (so the launch does not begin with W fetches at one address)
+__device__ __forceinline__ bool next_group(const WalkArgs &a, uint32_t ngroups, uint32_t &g,
+                                           bool &first, uint32_t wave_global, uint32_t waves)
 {
     uint32_t v = 0;
-    if (lane_id() == 0) v = atomicAdd(&a.misc->walk_next, 1u);
+    if (first) {
+        v = wave_global;
+        first = false;
+    } else if (lane_id() == 0) {
+        v = waves + atomicAdd(&a.misc->walk_next, 1u);
+    }
     g = readfirst(v);
     if (g >= ngroups) return false;
     if (a.glist) g = readfirst(a.glist[g]);
@@ -629,7 +638,9 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
     unsigned long long wave_pp = 0, wave_pc = 0;   // interaction totals of this wavefront
     bool wave_overflow = false;
     uint32_t g;
-    while (next_group(a, ngroups, g)) {
+    bool first = true;
+    const uint32_t waves = gridDim.x * kWalkWaves;
+    while (next_group(a, ngroups, g, first, (uint32_t)wave_global, waves)) {
         const uint32_t gs = a.g_first[g];
         const int gn = uniform((int)a.g_count[g]);
         const double4 gc = a.g_centre[g];
@@ -665,12 +676,28 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
         wave_overflow |= overflow;
         wave_sync();
     }
+    // the block's totals, added to the device-wide ones once per block
+    __shared__ unsigned long long s_tot[kWalkWaves][2];
+    __shared__ uint32_t s_over[kWalkWaves];
     if (lane == 0) {
-        atomicAdd(&a.misc->sum_npp, wave_pp);
-        atomicAdd(&a.misc->sum_npc, wave_pc);
-        atomicAdd(&a.misc->tot_npp, wave_pp);
-        atomicAdd(&a.misc->tot_npc, wave_pc);
-        if (wave_overflow) atomicOr(&a.misc->walk_overflow, 1u);
+        s_tot[w][0] = wave_pp;
+        s_tot[w][1] = wave_pc;
+        s_over[w] = wave_overflow ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long pp = 0, pc = 0;
+        uint32_t over = 0;
+        for (int i = 0; i < kWalkWaves; ++i) {
+            pp += s_tot[i][0];
+            pc += s_tot[i][1];
+            over |= s_over[i];
+        }
+        atomicAdd(&a.misc->sum_npp, pp);
+        atomicAdd(&a.misc->sum_npc, pc);
+        atomicAdd(&a.misc->tot_npp, pp);
+        atomicAdd(&a.misc->tot_npc, pc);
+        if (over) atomicOr(&a.misc->walk_overflow, 1u);
     }
 }
 

@@ -101,6 +101,7 @@ void free_buffers(bh_ctx *c)
     dfree(c->bins);
     dfree(c->due);
     dfree(c->walk_spill);
+    dfree(c->walk_part);
     dfree(c->g_first);
     dfree(c->g_count);
     dfree(c->g_npp);
@@ -190,6 +191,7 @@ hipError_t each_buffer(bh_ctx *c, const Sizes &z, F f)
     B(c->bins, z.n);
     B(c->due, z.n);
     B(c->walk_spill, walk_spill_words(z.spill_waves));
+    B(c->walk_part, 2 * z.spill_waves);
     B(c->g_first, z.n);
     B(c->g_count, z.n);
     B(c->g_npp, z.n);

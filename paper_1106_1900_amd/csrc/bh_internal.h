@@ -188,6 +188,7 @@ struct bh_ctx {
     uint8_t *bins = nullptr;                 // block time-step bin per particle (caller order)
     uint8_t *due = nullptr;                  // particles due for forces at a substep (caller order)
     uint32_t *walk_spill = nullptr;          // per-wave overflow of the walk stack
+    unsigned long long *walk_part = nullptr; // per-workgroup interaction totals of a walk [blocks][2]
     int64_t walk_spill_waves = 0;
 
     // ---- groups ----

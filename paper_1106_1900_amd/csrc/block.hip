@@ -33,10 +33,12 @@ using namespace bh;
 namespace {
 
 constexpr int kBlock = 256;
+constexpr unsigned kBinsGrid = 512;
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// bin of each particle from its float32 acceleration; histogram in misc
+// bin of each particle from its float32 acceleration; histogram in misc (a
+// small fixed grid: each workgroup adds its histogram to the device-wide one)
 __global__ void __launch_bounds__(kBlock)
 bins_kernel(int64_t n, const float4 *__restrict__ acc4, const uint32_t *__restrict__ pid,
             double dt_max, int levels, double k2, uint8_t *__restrict__ bins, DevMisc *m)
@@ -44,8 +46,8 @@ bins_kernel(int64_t n, const float4 *__restrict__ acc4, const uint32_t *__restri
     __shared__ uint32_t hist[kMaxBins];
     if (threadIdx.x < kMaxBins) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
         const float4 a = acc4[i];
         const double ax = (double)a.x, ay = (double)a.y, az = (double)a.z;
         const double a2 = (ax * ax + ay * ay) + az * az;
@@ -135,7 +137,8 @@ hipError_t enqueue_bins(bh_ctx *c, const bh_block_params *p)
 {
     hipLaunchKernelGGL(clear_bins_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
     BH_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(bins_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n, c->acc4,
+    const unsigned g = grid_for(c->n) < kBinsGrid ? grid_for(c->n) : kBinsGrid;
+    hipLaunchKernelGGL(bins_kernel, dim3(g), dim3(kBlock), 0, c->stream, c->n, c->acc4,
                        c->pid[c->cur], p->dt_max, (int)p->max_level, crit_k2(p), c->bins, c->misc);
     return hipGetLastError();
 }

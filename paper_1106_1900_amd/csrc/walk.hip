@@ -86,6 +86,7 @@ struct WalkArgs {
     uint32_t *g_npp;
     uint32_t *g_npc;
     uint32_t *spill;          // kSpillPerWave entries per wavefront of the grid
+    unsigned long long *part; // out: per-workgroup interaction totals (p-p, p-c)
     DevMisc *misc;            // group and cell counts, work counter, interaction totals
     const uint32_t *glist;    // groups to walk (misc->nactive of them), or null: all
 };
@@ -382,23 +383,14 @@ __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t 
     wave_sync();
 }
 
-// next group (false when all are taken): wavefront w of the grid's W starts
-// with group w; every later group comes from the device-wide counter, offset by
-// W (so the launch does not begin with W fetches at one address)
-__device__ __forceinline__ bool next_group(const WalkArgs &a, uint32_t ngroups, uint32_t &g,
-                                           bool &first, uint32_t wave_global, uint32_t waves)
+// the next group after the current one: from the device-wide counter, offset by
+// the W wavefronts of the grid (wavefront w starts with group w, so the launch
+// does not begin with W fetches at one address)
+__device__ __forceinline__ uint32_t next_slot(const WalkArgs &a, uint32_t waves)
 {
     uint32_t v = 0;
-    if (first) {
-        v = wave_global;
-        first = false;
-    } else if (lane_id() == 0) {
-        v = waves + atomicAdd(&a.misc->walk_next, 1u);
-    }
-    g = readfirst(v);
-    if (g >= ngroups) return false;
-    if (a.glist) g = readfirst(a.glist[g]);
-    return true;
+    if (lane_id() == 0) v = atomicAdd(&a.misc->walk_next, 1u);
+    return waves + readfirst(v);
 }
 
 // One group: walk its cluster's tree from the root, evaluate its lists, and
@@ -637,10 +629,10 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
 
     unsigned long long wave_pp = 0, wave_pc = 0;   // interaction totals of this wavefront
     bool wave_overflow = false;
-    uint32_t g;
-    bool first = true;
     const uint32_t waves = gridDim.x * kWalkWaves;
-    while (next_group(a, ngroups, g, first, (uint32_t)wave_global, waves)) {
+    for (uint32_t slot = readfirst((uint32_t)wave_global); slot < ngroups;
+         slot = next_slot(a, waves)) {
+        const uint32_t g = a.glist ? readfirst(a.glist[slot]) : slot;
         const uint32_t gs = a.g_first[g];
         const int gn = uniform((int)a.g_count[g]);
         const double4 gc = a.g_centre[g];
@@ -676,7 +668,8 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
         wave_overflow |= overflow;
         wave_sync();
     }
-    // the block's totals, added to the device-wide ones once per block
+    // the block's totals go to its own slot (summed by walk_sum_kernel): thousands
+    // of workgroups adding to one address at the end of the kernel serialise
     __shared__ unsigned long long s_tot[kWalkWaves][2];
     __shared__ uint32_t s_over[kWalkWaves];
     if (lane == 0) {
@@ -693,11 +686,37 @@ __attribute__((amdgpu_waves_per_eu(BH_WALK_WAVES_PER_EU))) walk_kernel(WalkArgs 
             pc += s_tot[i][1];
             over |= s_over[i];
         }
-        atomicAdd(&a.misc->sum_npp, pp);
-        atomicAdd(&a.misc->sum_npc, pc);
-        atomicAdd(&a.misc->tot_npp, pp);
-        atomicAdd(&a.misc->tot_npc, pc);
+        a.part[2 * (int64_t)blockIdx.x] = pp;
+        a.part[2 * (int64_t)blockIdx.x + 1] = pc;
         if (over) atomicOr(&a.misc->walk_overflow, 1u);
+    }
+}
+
+// the walk's interaction totals from its per-workgroup slots (fixed order)
+__global__ void __launch_bounds__(256)
+walk_sum_kernel(const unsigned long long *__restrict__ part, int blocks, DevMisc *m)
+{
+    __shared__ unsigned long long s[2][256];
+    unsigned long long pp = 0, pc = 0;
+    for (int b = threadIdx.x; b < blocks; b += 256) {
+        pp += part[2 * b];
+        pc += part[2 * b + 1];
+    }
+    s[0][threadIdx.x] = pp;
+    s[1][threadIdx.x] = pc;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + d];
+            s[1][threadIdx.x] += s[1][threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        m->sum_npp = s[0][0];
+        m->sum_npc = s[1][0];
+        m->tot_npp += s[0][0];
+        m->tot_npc += s[1][0];
     }
 }
 
@@ -824,6 +843,7 @@ hipError_t launch_walk(bh_ctx *c, bool timed, bool active_only)
     a.g_npp = c->g_npp;
     a.g_npc = c->g_npc;
     a.spill = c->walk_spill;
+    a.part = c->walk_part;
     a.misc = c->misc;
     a.glist = active_only ? c->val[1] : nullptr;
     hipEvent_t *ev = timed ? walk_timer_slot(c) : nullptr;
@@ -834,6 +854,9 @@ hipError_t launch_walk(bh_ctx *c, bool timed, bool active_only)
         hipLaunchKernelGGL(walk_kernel<false>, dim3((unsigned)blocks), dim3(kWalkBlock), 0, c->stream, a);
     BH_LAUNCH_CHECK();
     if (ev) BH_HIP_TRY(hipEventRecord(ev[1], c->stream));
+    hipLaunchKernelGGL(walk_sum_kernel, dim3(1), dim3(256), 0, c->stream, c->walk_part,
+                       (int)blocks, c->misc);
+    BH_LAUNCH_CHECK();
     return hipSuccess;
 }
 

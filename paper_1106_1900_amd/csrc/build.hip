@@ -942,12 +942,13 @@ hipError_t moments_launches(bh_ctx *c, double2 *box)
     BH_LAUNCH_CHECK();
     // nodes from their children, deepest level first (level 20 holds only leaves).
     // The level sizes are known on the device only; the host takes those seen at
-    // its last synchronisation as hints: levels more than two below the hinted
-    // depth (normally empty) share one workgroup, every other level gets a launch
-    // of its own with a grid sized for twice its hinted count.  The kernels read
-    // the true counts and loop over them, so any tree is handled whatever the hints.
+    // its last synchronisation as hints: levels below the hinted depth (normally
+    // empty; a tree that grew deeper since) share one workgroup, every other level
+    // gets a launch of its own with a grid sized for twice its hinted count.  The
+    // kernels read the true counts and loop over them, so any tree is handled
+    // whatever the hints.
     const DevMisc &hint = *c->misc_h;
-    const int deep = hint.depth ? std::min(kMaxLevel - 1, (int)hint.depth + 2) : kMaxLevel - 1;
+    const int deep = hint.depth ? std::min(kMaxLevel - 1, (int)hint.depth) : kMaxLevel - 1;
     if (deep < kMaxLevel - 1) {
         hipLaunchKernelGGL((moments_levels_kernel<kBox>), dim3(1), dim3(kLevelsBlock), 0, c->stream,
                            kMaxLevel - 1, deep + 1, c->misc, c->c_leaf, c->c_first, c->c_count,

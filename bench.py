@@ -103,6 +103,58 @@ def cpu_baseline(pos, mass, theta, eps, budget_s):
     }
 
 
+def cpu_worker(index, workers, n, theta, eps, budget_s):
+    """One process of the all-cores baseline: the single-threaded oracle on the
+    groups with index = `index` mod `workers` (seeded order), for budget_s seconds
+    of evaluation.  Touches no GPU."""
+    import numpy as np
+
+    import oracle
+    import workloads
+    pos, _, mass = workloads.plummer(n, 2)
+    t0 = time.perf_counter()
+    tree = oracle.Tree(pos, mass)
+    t_build = time.perf_counter() - t0
+    g = tree.groups()
+    mine = np.random.default_rng(11).permutation(tree.ngroups)[index::workers]
+    done_p = done_g = 0
+    t_walk = 0.0
+    while t_walk < budget_s and done_g < mine.size:
+        sel = np.sort(mine[done_g:done_g + 64])
+        t1 = time.perf_counter()
+        tree.forces(theta, eps, sel)
+        t_walk += time.perf_counter() - t1
+        done_g += sel.size
+        done_p += int(g["count"][sel].sum())
+    print(json.dumps({"t_build": t_build, "t_walk": t_walk, "done_p": done_p, "done_g": done_g}),
+          flush=True)
+
+
+def cpu_baseline_all_cores(n, theta, eps, budget_s, workers):
+    """The same oracle in one process per core over disjoint group sets: the
+    evaluation rates add up; the tree build (single-threaded) is counted once."""
+    import subprocess
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker",
+                               str(i), str(workers), str(n), repr(theta), repr(eps),
+                               repr(budget_s)], stdout=subprocess.PIPE, text=True)
+             for i in range(workers)]
+    res = []
+    for p in procs:
+        out_s, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError("oracle worker failed")
+        res.append(json.loads(out_s.strip().splitlines()[-1]))
+    rate = sum(r["done_p"] / r["t_walk"] for r in res if r["t_walk"] > 0)
+    t_build = min(r["t_build"] for r in res)
+    t_full = t_build + n / rate
+    return {"value": n / t_full, "unit": "particles/s", "cores": workers, "kind": "oracle",
+            "sample": ("the single-threaded C oracle in %d processes over disjoint seeded group "
+                       "sets of the same input, %.0f s of evaluation each (%d groups, %d particles "
+                       "in all); evaluation rates summed, one tree build (%.2f s) counted"
+                       % (workers, budget_s, sum(r["done_g"] for r in res),
+                          sum(r["done_p"] for r in res), t_build))}
+
+
 def accuracy_sample(pos, mass, acc_gpu, eps, ntarget=1024):
     """Relative acceleration error (Eq. (2)) of the GPU forces against the oracle's
     float64 direct summation on seeded targets."""
@@ -681,7 +733,14 @@ def main():
                     help="run only that form and print its JSON (for profiling runs)")
     ap.add_argument("--merger-time", type=float, default=1000.0,
                     help="end time of the merger run (N-body units)")
+    ap.add_argument("--cpu-worker", nargs=6, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-cores", type=int, default=0,
+                    help="processes of the all-cores oracle baseline (0: min(16, cpus); -1: skip)")
     args = ap.parse_args()
+    if args.cpu_worker:
+        i, w, n, th, ep, b = args.cpu_worker
+        cpu_worker(int(i), int(w), int(n), float(th), float(ep), float(b))
+        return
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -839,6 +898,11 @@ def main():
     if args.cpu_budget > 0 and rank == 0:
         log("timing the oracle on the host (%.0f s budget)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(pos, mass, args.theta, args.eps, args.cpu_budget)
+        cores = args.cpu_cores if args.cpu_cores > 0 else min(16, os.cpu_count() or 1)
+        if args.cpu_cores >= 0 and cores > 1:
+            log("timing the oracle on %d host cores" % cores)
+            out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(
+                n, args.theta, args.eps, min(10.0, args.cpu_budget), cores)
     if rank == 0:
         print(json.dumps(out), flush=True)
 

@@ -207,7 +207,10 @@ int bh_kick(bh_ctx *ctx, double dt, const uint8_t *active);
 
 /* Multipole-only update (Sect. 5): keep the cells, keys, domain and groups of
  * the last build; recompute every cell's moments and every group's tight box
- * from the current positions.  Opening radii follow at the next force call. */
+ * from the current positions, and take as each cell's side in the opening test
+ * the larger of its build side and the largest side of its particles' tight box
+ * (a refitted tree's cells grow, which is what slows its walk).  Opening radii
+ * follow at the next force call. */
 int bh_refit(bh_ctx *ctx);
 
 /* Forces of the groups that hold at least one particle with active[i] != 0

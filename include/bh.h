@@ -437,7 +437,16 @@ int bh_server_submit(bh_server *srv, const bh_request *req, int64_t *ticket);
  * *resident (may be NULL): requests resident during the iteration. */
 int bh_server_step(bh_server *srv, int64_t *resident);
 
+/* State of a request.  The record of a finished request (BH_REQ_DONE or
+ * BH_REQ_FAILED) is kept for polling until bh_server_release drops it. */
 int bh_server_poll(bh_server *srv, int64_t ticket, bh_request_status *out);
+
+/* Drop the record of a finished request, so that a long-running server keeps
+ * no memory per past request beyond its latency samples (16 bytes each, for the
+ * percentiles of bh_server_stats_get).  BH_ESTATE if the request is still
+ * queued or running (the record stays); BH_EINVAL for an unknown or already
+ * released ticket. */
+int bh_server_release(bh_server *srv, int64_t ticket);
 
 int bh_server_stats_get(bh_server *srv, bh_server_stats *out);
 

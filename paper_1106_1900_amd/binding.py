@@ -462,6 +462,7 @@ def _server_sigs(L):
         "bh_server_submit": (i32, [_vp, ctypes.POINTER(Request), ctypes.POINTER(i64)]),
         "bh_server_step": (i32, [_vp, ctypes.POINTER(i64)]),
         "bh_server_poll": (i32, [_vp, i64, ctypes.POINTER(RequestStatus)]),
+        "bh_server_release": (i32, [_vp, i64]),
         "bh_server_stats_get": (i32, [_vp, ctypes.POINTER(ServerStats)]),
         "bh_server_now": (i32, [_vp, ctypes.POINTER(ctypes.c_double)]),
         "bh_server_set_tuning": (i32, [_vp, ctypes.POINTER(TuneEntry), i64]),
@@ -556,6 +557,11 @@ class Server:
             self._keep.pop(int(ticket), None)
         return {"state": s.state, "units_done": s.units_done, "arrival": s.arrival,
                 "admitted": s.admitted, "completed": s.completed, "energy": list(s.energy)}
+
+    def release(self, ticket):
+        """Drop the record of a finished request (later polls of it fail)."""
+        self._check(self._L.bh_server_release(self._h, int(ticket)))
+        self._keep.pop(int(ticket), None)
 
     def stats(self):
         s = ServerStats()

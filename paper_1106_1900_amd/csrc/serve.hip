@@ -514,6 +514,18 @@ int bh_server_poll(bh_server *s, int64_t ticket, bh_request_status *out)
     return BH_OK;
 }
 
+int bh_server_release(bh_server *s, int64_t ticket)
+{
+    if (!s) return BH_EINVAL;
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return sfail(s, BH_EINVAL, "unknown ticket");
+    const int state = it->second.state;
+    if (state != BH_REQ_DONE && state != BH_REQ_FAILED)
+        return sfail(s, BH_ESTATE, "request still queued or running");
+    s->reqs.erase(it);
+    return BH_OK;
+}
+
 int bh_server_stats_get(bh_server *s, bh_server_stats *out)
 {
     if (!s) return BH_EINVAL;

@@ -163,3 +163,38 @@ def test_largest_request_alone_and_in_the_mix():
     for g, w in zip(got, (x, vv, a, pp)):
         assert np.array_equal(g, w)
     srv.close()
+
+
+def test_release_drops_finished_records_only():
+    import paper_1106_1900_amd as bh
+    from paper_1106_1900_amd.binding import BH_EINVAL, BH_ESTATE
+    reqs = _requests()[:2]
+    bad = dict(reqs[1])
+    bad["mass"] = bad["mass"].copy()
+    bad["mass"][3] = 0.0
+    srv, tickets, _, _ = _serve([reqs[0], bad], 1 << 30)
+    assert [srv.poll(t)["state"] for t in tickets] == [2, 3]
+    waiting = srv.submit(to_dev(reqs[0]["pos"]), to_dev(reqs[0]["mass"]), nsteps=1)
+    with pytest.raises(bh.BHError) as e:
+        srv.release(waiting)                   # still queued: kept
+    assert e.value.code == BH_ESTATE
+    assert srv.poll(waiting)["state"] == 0
+    for t in tickets:                          # done and failed records go
+        srv.release(t)
+        with pytest.raises(bh.BHError) as e:
+            srv.poll(t)
+        assert e.value.code == BH_EINVAL
+        with pytest.raises(bh.BHError) as e:
+            srv.release(t)
+        assert e.value.code == BH_EINVAL
+    st = srv.stats()                           # the statistics keep the released requests
+    assert st["completed"] == 1 and st["rejected"] == 1 and st["latency_p50"] > 0
+    srv.step()                                 # admitted: the force evaluation
+    assert srv.poll(waiting)["state"] == 1
+    with pytest.raises(bh.BHError) as e:
+        srv.release(waiting)                   # running: kept
+    assert e.value.code == BH_ESTATE
+    srv.step()                                 # its one leapfrog step
+    assert srv.poll(waiting)["state"] == 2
+    srv.release(waiting)
+    srv.close()

@@ -44,6 +44,20 @@ def test_bins_equal_the_oracle_bins_of_the_same_accelerations():
     ctx.close()
 
 
+def test_bin_boundary_is_inclusive_on_the_device():
+    # two bodies of mass 4 one unit apart, no softening: |a| = 4 exactly, and with
+    # dt_max = 1, eta = 1/2, l = 1 the criterion sqrt(2 eta l / |a|) = 1/2 is met
+    # with equality by bin 1
+    pos = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    m = np.array([4.0, 4.0])
+    ctx = _ctx(pos, np.zeros((2, 3)), m, 0.75, 0.0)
+    acc = _state(ctx)[2]
+    assert np.array_equal(np.abs(acc), np.array([[4.0, 0, 0], [4.0, 0, 0]], np.float32)), acc
+    bins, count = ctx.block_bins(1.0, 0.5, 1.0, 3)
+    assert list(bins.cpu().numpy()) == [1, 1] and count[1] == 2
+    ctx.close()
+
+
 def test_one_level_rebuilding_every_step_is_the_leapfrog():
     pos, vel, m = workloads.plummer(20_000, 72)
     a = _ctx(pos, vel, m, 0.6, 0.01)

@@ -33,6 +33,15 @@ def test_bins_against_the_closed_form():
     assert set(np.unique(bins)) == set(range(B + 1))
 
 
+def test_bin_boundary_is_inclusive():
+    # dt_max = 1, eta = 1/2, l = 1, |a| = 4: the criterion sqrt(2 eta l / |a|) is
+    # exactly 1/2 = dt_max 2^-1, and a step equal to it is taken; a hair more
+    # acceleration needs the next bin
+    acc = np.array([[4.0, 0, 0], [0, -4.0, 0], [4.0 * (1 + 2.0 ** -20), 0, 0], [0, 0, 3.99]],
+                   np.float32)
+    assert list(oracle.block_bins(acc, 1.0, 3, 0.5, 1.0)) == [1, 1, 2, 1]
+
+
 def test_one_level_always_rebuilding_is_the_leapfrog():
     pos, vel, m = workloads.plummer(2000, 41)
     b = oracle.Block(pos, vel, m, 0.6, 0.01)
@@ -138,3 +147,18 @@ def test_rebuild_rule_and_the_walk_it_measures():
     assert b.base == inter2 == (t1.groups()["count"] * (npp + npc)).sum() / 3000
     acc, pot, _, _ = t1.forces(0.6, 0.01)
     assert np.array_equal(b.acc, acc) and np.array_equal(b.pot, pot)
+
+
+def test_rebuild_threshold_is_one_plus_growth_times_the_base():
+    # the same block step with the growth limit just above and just below the
+    # growth it measures: kept, then rebuilt
+    pos, vel, m = workloads.plummer(3000, 46)
+    first = oracle.Block(pos, vel, m, 0.6, 0.01)
+    bins = oracle.block_bins(first.acc.astype(np.float32), 1 / 8, 3, 0.025, 0.01)
+    _, inter, _ = first.step(bins, 3, 1 / 8, 1e9)
+    grown = inter / first.base - 1.0
+    assert 0.0 < grown < 0.5
+    for limit, want in ((grown * 1.01, False), (grown * 0.99, True)):
+        b = oracle.Block(pos, vel, m, 0.6, 0.01)
+        rebuilt, _, _ = b.step(bins, 3, 1 / 8, limit)
+        assert bool(rebuilt) == want, (limit, grown)

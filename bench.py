@@ -65,6 +65,24 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
+def host_cpu():
+    """The host the oracle baselines ran on: CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(pos, mass, theta, eps, budget_s):
     """The oracle as it stands, single-threaded: full tree build plus the walk and
     float64 evaluation of a seeded sample of groups until about budget_s seconds
@@ -96,10 +114,11 @@ def cpu_baseline(pos, mass, theta, eps, budget_s):
         "unit": "particles/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": ("single-threaded C oracle on the same Plummer N=%d input: full tree build "
+        "sample": ("single-threaded C oracle on the same N=%d input: full tree build "
                    "(%.2f s) plus walk and float64 evaluation of %d randomly chosen groups "
                    "(%d particles, %.1f s), evaluation time scaled to all %d particles"
                    % (n, t_build, done_g, done_p, t_walk, n)),
+        "host": host_cpu(),
     }
 
 
@@ -152,7 +171,8 @@ def cpu_baseline_all_cores(n, theta, eps, budget_s, workers):
                        "sets of the same input, %.0f s of evaluation each (%d groups, %d particles "
                        "in all); evaluation rates summed, one tree build (%.2f s) counted"
                        % (workers, budget_s, sum(r["done_g"] for r in res),
-                          sum(r["done_p"] for r in res), t_build))}
+                          sum(r["done_p"] for r in res), t_build)),
+            "host": host_cpu()}
 
 
 def direct_fp64(pos, mass, eps, tgt):
@@ -425,7 +445,67 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
     }
 
 
-def bench_galaxy(steps, ntarget=1024):
+def bench_small(reps=20, with_oracle=True):
+    """The small Plummer workload (N = 4096, seed 1, theta 0.5, eps 0.01): one force
+    evaluation plus 10 leapfrog steps of dt 1/128, repeated; beside it the same
+    unit in the single-threaded oracle, and the oracle's direct sum."""
+    import numpy as np
+    import torch
+
+    import paper_1106_1900_amd as bh
+    import workloads
+    n, theta, eps, dt, steps = 4096, 0.5, 0.01, 1.0 / 128, 10
+    pos, vel, mass = workloads.plummer(n, 1)
+    dpos = torch.from_numpy(pos).cuda()
+    dvel = torch.from_numpy(vel).cuda()
+    dmass = torch.from_numpy(mass).cuda()
+    ctx = bh.Context()
+
+    def unit():
+        ctx.build_tree(dpos, dmass)
+        ctx.set_velocities(dvel)
+        ctx.compute_forces(theta, eps, want=False)
+        for _ in range(steps):
+            ctx.leapfrog_step(dt)
+
+    for _ in range(3):
+        unit()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        unit()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    ctx.close()
+    out = {"workload": "plummer N=4096 seed 1, theta 0.5, eps 0.01, nleaf 16, group 64: one force "
+                       "evaluation + 10 leapfrog steps of dt 1/128 (tree rebuilt each step)",
+           "value": n * (1 + steps) / el, "unit": "particles/s", "ms_per_unit": 1e3 * el,
+           "ms_per_force_evaluation": 1e3 * el / (1 + steps)}
+    if with_oracle:
+        import oracle
+        p, v = pos.copy(), vel.copy()
+        t0 = time.perf_counter()
+        tree = oracle.Tree(p, mass)
+        acc, pot, _, _ = tree.forces(theta, eps)
+        for _ in range(steps):
+            oracle.kdk_step(p, v, mass, acc, pot, dt, theta, eps)
+        t_bh = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.direct(pos, mass, eps)
+        t_direct = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * (1 + steps) / t_bh, "unit": "particles/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "the whole unit (tree, forces, 10 leapfrog steps) in the "
+                                         "single-threaded C oracle, %.2f s" % t_bh,
+                               "host": host_cpu()}
+        out["cpu_direct_sum"] = {"value": n / t_direct, "unit": "particles/s", "cores": 1,
+                                 "kind": "oracle",
+                                 "sample": "one float64 direct summation over all %d particles, "
+                                           "%.2f s" % (n, t_direct)}
+    return out
+
+
+def bench_galaxy(steps, ntarget=1024, cpu_budget=0.0):
     """The three-component galaxy of 4,194,304 particles at theta 0.4, eps 0.02:
     leapfrog steps of dt 1/128 with the walk kernel timed, and the force error of
     the first evaluation against float64 direct summation on seeded targets."""
@@ -462,7 +542,7 @@ def bench_galaxy(steps, ntarget=1024):
     pc = (s1.total_npc - s0.total_npc) / max(launches, 1)
     achieved = (FLOPS_PP * pp + FLOPS_PC * pc) / (walk_ms * 1e-3) / 1e12
     log("direct summation on %d targets" % ntarget)
-    return {
+    out = {
         "workload": "galaxy N=%d (disk 2^20, bulge 2^19, halo 2.5 2^20), theta %g, eps %g, dt 1/128"
                     % (n, theta, eps),
         "value": n * steps / el, "unit": "particles/s", "ms_per_step": 1e3 * el / steps,
@@ -471,6 +551,10 @@ def bench_galaxy(steps, ntarget=1024):
         "energy_error": float(e1[6]),
         "accuracy_vs_direct": pooled_accuracy([(pos, mass, acc0, eps)], ntarget, 16),
     }
+    if cpu_budget > 0:
+        log("timing the oracle on the galaxy (%.0f s budget)" % cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(pos, mass, theta, eps, cpu_budget)
+    return out
 
 
 def bench_sweep():
@@ -744,6 +828,7 @@ def main():
                     help="seconds of oracle evaluation for the CPU baseline (0: skip)")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the N = 4096 workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-clusters", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -805,7 +890,8 @@ def main():
                                          growth=growth, blocks=3, workload="galaxy")), flush=True)
         return
     if args.only == "galaxy":
-        print(json.dumps(bench_galaxy(args.steps if args.steps != 100 else 10)), flush=True)
+        print(json.dumps(bench_galaxy(args.steps if args.steps != 100 else 10,
+                                      cpu_budget=args.cpu_budget)), flush=True)
         return
     if args.only == "serve":
         budget = int(args.serve_budget_gib * (1 << 30)) or int(0.6 * torch.cuda.mem_get_info()[0])
@@ -907,6 +993,9 @@ def main():
                             "what": "tree traverse only, 1x GTX480, N=2^20 Plummer, theta=0.75"},
     }
     ctx.close()
+    if not args.no_small:
+        log("small workload (N = 4096)")
+        out["small"] = bench_small(with_oracle=args.cpu_budget > 0 and rank == 0)
     if not args.no_batch:
         out["batch"] = bench_batch(args.batch_clusters, args.batch_steps, 2)
     if not args.no_serve:

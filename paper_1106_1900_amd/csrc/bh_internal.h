@@ -337,20 +337,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan_add(uint32_t v)
     return (uint32_t)x;
 }
 
-// Inclusive prefix maximum over the 64 lanes (same pattern; lanes outside a row
-// or a disabled row contribute INT_MIN).
-__device__ __forceinline__ int wave_incl_scan_max(int x)
-{
-    const int lo = (int)0x80000000;
-    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x111, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x112, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x114, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x118, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x142, 0xa, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x143, 0xc, 0xf, false));
-    return x;
-}
-
 // value of lane i (i uniform across the wavefront)
 __device__ __forceinline__ uint32_t lane_value(uint32_t v, int i)
 {

@@ -144,11 +144,15 @@ __device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &e
     const int nfull = __popcll(ballot(full));
     const uint32_t total = lane_value(incl, m - 1);
     const int got = uniform(total < (uint32_t)kWave ? (int)total : kWave);
-    mark[lane] = -1;
+    // the lanes that take a range form a prefix with strictly increasing starts,
+    // so the range that output slot `lane` comes from is the number of range
+    // starts at or below it, minus one
+    mark[lane] = 0;
     wave_sync();
-    if (take > 0) mark[excl] = lane;
+    if (take > 0) mark[excl] = 1;
     wave_sync();
-    int src = wave_incl_scan_max(mark[lane]);
+    const unsigned long long starts = ballot(mark[lane] != 0);
+    int src = mask_rank(starts) + (int)((starts >> lane) & 1ull) - 1;
     src = src < 0 ? 0 : src;
     const uint32_t fs = __shfl(f, src, kWave);
     const uint32_t es = __shfl(excl, src, kWave);

@@ -79,3 +79,22 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(ImportError):
         binding.load_library()
+
+
+def test_create_validates_before_touching_the_device():
+    import torch
+    lib = bh.load_library()
+    for field, value in (("nleaf", 0), ("nleaf", 65), ("ncrit", 0), ("ncrit", 65), ("max_n", -1),
+                         ("hbm_budget_bytes", -1), ("max_clusters", -1)):
+        p = binding.Params()
+        lib.bh_default_params(ctypes.byref(p))
+        setattr(p, field, value)
+        h = ctypes.c_void_p()
+        assert lib.bh_create(ctypes.byref(h), ctypes.byref(p), None) == binding.BH_EINVAL, field
+        assert h.value is None
+    assert lib.bh_create(None, None, None) == binding.BH_EINVAL
+    if not torch.cuda.is_available():
+        # no device: a valid request fails with BH_EDEVICE and leaves no context
+        h = ctypes.c_void_p()
+        assert lib.bh_create(ctypes.byref(h), None, None) == binding.BH_EDEVICE
+        assert h.value is None

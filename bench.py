@@ -289,6 +289,13 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4, alone=True):
     accuracy = pooled_accuracy([(xs[starts[c]:starts[c] + cl[c]["n"]], cl[c]["mass"],
                                  acc_b[starts[c]:starts[c] + cl[c]["n"]], cl[c]["eps"]) for c in pick],
                                 256, 14)
+    # the batched walk against the FP32 roofline: one eager force evaluation (graph
+    # replays are not timed per kernel) at the same positions
+    ctx.batch_forces(want=False)
+    torch.cuda.synchronize()
+    sw = ctx.stats()
+    walk_flops = FLOPS_PP * sw.sum_npp + FLOPS_PC * sw.sum_npc
+    walk_tflops = walk_flops / (sw.ms_walk_kernel * 1e-3) / 1e12 if sw.ms_walk_kernel > 0 else 0.0
 
     # leaf and group sizes tuned per class (floor(log2 N), theta), then the same
     # clusters reloaded with the tuned sizes and timed again
@@ -316,6 +323,9 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4, alone=True):
         "max_abs_energy_error": float(np.abs(en[:, 6]).max()),
         "accuracy_vs_direct": accuracy,
         "graph_launches": int(st.graph_launches),
+        "walk": {"ms_per_launch": sw.ms_walk_kernel, "interactions": {"pp": sw.sum_npp,
+                                                                     "pc": sw.sum_npc},
+                 "tflops": walk_tflops, "frac_of_157_3": walk_tflops / PEAK_FP32_VECTOR_TFLOPS},
         "tuned_value": ntot / t_tuned,
         "tuned_ms_per_step": 1e3 * t_tuned,
         "autotune_seconds": t_tune,

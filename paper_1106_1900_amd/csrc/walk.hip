@@ -439,6 +439,11 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
     uint32_t iters = 0;
 
     while (top > 0) {
+        // Traversal (pop, opening test, list appends) runs at a raised wave
+        // priority and evaluation at the normal one: a wavefront's next loads then
+        // issue ahead of the arithmetic of the other wavefronts on its SIMD, which
+        // hides more of the traversal's latency behind that arithmetic.
+        __builtin_amdgcn_s_setprio(1);
         // a correct tree visits each cell at most once per group
         if (++iters > ncells + 1u) {
             overflow = true;
@@ -512,6 +517,7 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
         }
         stack.sync();
         if (pc_n >= kWave) {     // pc_n < 128: one tile of the last 64 entries
+            __builtin_amdgcn_s_setprio(0);
             eval_pc<kEps0, M>(L, pc_n - kWave, kWave, t, eps2, acc);
             pc_n -= kWave;
         }
@@ -523,11 +529,13 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
                 pend = 0;
                 break;
             }
+            __builtin_amdgcn_s_setprio(0);
             eval_pp<kEps0, M>(a, L, idx, n, gc, t, eps2, acc);
             pend -= (uint32_t)n;
         }
         if (overflow) break;
     }
+    __builtin_amdgcn_s_setprio(0);
     if (pc_n > 0) eval_pc<kEps0, M>(L, 0, pc_n, t, eps2, acc);
     while (pend > 0) {
         uint32_t idx;

@@ -239,20 +239,23 @@ typedef struct {
     double eta;         /* accuracy parameter of the criterion (> 0) */
     double length;      /* length of the criterion, e.g. the softening (> 0) */
     int32_t max_level;  /* B: bins 0..B, 2^B substeps per block step (0..15) */
-    float growth;       /* rebuild at the end of a block step when the refitted tree's
-                           walk has more than (1 + growth) times the interactions per
-                           particle of the walk right after the last rebuild; <= 0:
-                           rebuild every block step (with B = 0: the leapfrog step) */
+    float growth;       /* each particle's base is its group's interaction count in
+                           the last walk that covered it on a freshly built tree; when
+                           a walk of the refitted tree has more than (1 + growth) times
+                           the summed base of the particles it covered, the next force
+                           evaluation rebuilds the tree instead of refitting it.  <= 0:
+                           every force evaluation rebuilds (with B = 0: the leapfrog
+                           step).  On a batch the sums run over the whole forest. */
 } bh_block_params;
 
 typedef struct {
     int64_t substeps;           /* 2^B */
-    int64_t rebuilt;            /* 1 if the tree was rebuilt at the end of the step */
+    int64_t rebuilt;            /* force evaluations of the step on a rebuilt tree */
     int64_t updates;            /* particle steps completed: sum over particles of 2^bin */
     int64_t walked_groups;      /* groups walked over the step (partial and full walks) */
-    double sync_interactions;   /* interactions per particle of the walk that gave the
-                                   final forces */
-    double base_interactions;   /* the same for the walk right after the last rebuild */
+    double sync_interactions;   /* interactions per particle of the final walk (every
+                                   group, every particle due) */
+    double base_interactions;   /* mean base over the particles after the step */
     int64_t bin_count[16];      /* particles per bin during the step */
 } bh_block_stats;
 
@@ -262,10 +265,13 @@ typedef struct {
 int bh_block_bins(bh_ctx *ctx, const bh_block_params *p, uint8_t *bins, int64_t *count);
 
 /* One block step of dt_max: bins from the current accelerations, 2^B substeps,
- * rebuild test at the end.  Needs current forces of every particle (a force
- * call, leapfrog step or earlier block step, and no drift since).  out: host,
- * may be NULL.  Synchronous (once at the end; once more at the end when
- * growth > 0, for the rebuild test). */
+ * each force evaluation on a refitted or a rebuilt tree by the growth rule.
+ * Needs current forces of every particle (a force call, leapfrog step or earlier
+ * block step, and no drift since); if the tree has not been refitted since it
+ * was built, the counts of its last walk become every particle's base.  Whether
+ * the next evaluation rebuilds is kept in the context across block steps (reset
+ * by loads and bh_set_state).  out: host, may be NULL.  Synchronous: after the
+ * bins, after each walk of a refitted tree (for the rule) and at the end. */
 int bh_block_step(bh_ctx *ctx, const bh_block_params *p, bh_block_stats *out);
 
 /* ---------------------------------------------------------------------------

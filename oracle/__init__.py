@@ -97,6 +97,7 @@ def lib():
                                ctypes.c_int]),
         "orc_block_free": (None, [vp]),
         "orc_block_base": (d, [vp]),
+        "orc_block_rebuild_next": (ctypes.c_int, [vp]),
         "orc_block_step": (ctypes.c_int, [vp, vp, ctypes.c_int, d, d, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -349,11 +350,18 @@ class Block:
 
     @property
     def base(self):
+        """Mean over the particles of their base (interactions of their group in
+        the last walk covering them on a freshly built tree)."""
         return float(lib().orc_block_base(self._h))
 
+    @property
+    def rebuild_next(self):
+        """True if the next force evaluation will be on a rebuilt tree."""
+        return bool(lib().orc_block_rebuild_next(self._h))
+
     def step(self, bins, max_level, dt_max, growth):
-        """One block step; returns (rebuilt, interactions per particle of the last
-        walk, completed steps per particle)."""
+        """One block step; returns (rebuilds during the step, interactions per
+        particle of the final walk, completed steps per particle)."""
         b = np.ascontiguousarray(bins, dtype=np.uint8)
         rebuilt = ctypes.c_int()
         inter = ctypes.c_double()
@@ -362,4 +370,4 @@ class Block:
                                   ctypes.byref(rebuilt), ctypes.byref(inter), _ptr(kicks))
         if st:
             raise ValueError("oracle block step failed (%d)" % st)
-        return bool(rebuilt.value), float(inter.value), kicks
+        return int(rebuilt.value), float(inter.value), kicks

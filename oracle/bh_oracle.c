@@ -770,10 +770,13 @@ int orc_kdk_step(double *pos, double *vel, const double *mass, int64_t n,
 /*  - kick-drift-kick per bin: every particle drifts every substep of           */
 /*    dt_max 2^-B; a particle of bin b is kicked (half, then half again) at     */
 /*    the end of each of its 2^b steps, with forces recomputed for the groups   */
-/*    that hold it on the tree refitted to the current positions;               */
-/*  - at the end of the block step (all particles due) the refitted tree's     */
-/*    walk is compared with the walk right after the last rebuild: more than    */
-/*    (1 + growth) times as many interactions per particle -> rebuild.          */
+/*    that hold it; at the end of the block step every particle is due;         */
+/*  - the cost of a walk: each particle carries the interaction count of its   */
+/*    group in the last walk that covered it on a freshly built tree (its       */
+/*    base).  A walk on a refitted tree is compared with the base of the        */
+/*    particles it covers: more than (1 + growth) times their summed base and   */
+/*    the tree is rebuilt, instead of refitted, before the next force           */
+/*    evaluation.  growth <= 0: rebuilt before every force evaluation.          */
 
 void orc_block_bins(const float *acc, int64_t n, double dt_max, int max_level, double eta,
                     double length, uint8_t *bins)
@@ -801,22 +804,9 @@ struct orc_block {
     int64_t n;
     float theta, eps;
     int nleaf, ncrit, mac;
-    double base;                     /* interactions per particle after the last rebuild */
+    int64_t *pbase;                  /* per particle (caller order): its base */
+    int rebuild_next;                /* the last walk of a refitted tree grew too much */
 };
-
-/* interactions per particle of the tree's walk (npp + npc summed over group members) */
-static int walk_per_particle(const orc_tree *t, float theta, double *out)
-{
-    int64_t *npp = (int64_t *)malloc(sizeof(int64_t) * (size_t)t->ngroups);
-    int64_t *npc = (int64_t *)malloc(sizeof(int64_t) * (size_t)t->ngroups);
-    if (!npp || !npc) { free(npp); free(npc); return -2; }
-    int st = orc_walk_counts(t, theta, npp, npc);
-    int64_t s = 0;
-    for (int64_t g = 0; g < t->ngroups && !st; ++g) s += t->gcount[g] * (npp[g] + npc[g]);
-    free(npp); free(npc);
-    *out = (double)s / (double)t->n;
-    return st;
-}
 
 static int block_rebuild(orc_block *b)
 {
@@ -824,7 +814,40 @@ static int block_rebuild(orc_block *b)
     b->t = orc_build(b->pos, b->mass, b->n, b->nleaf, b->ncrit);
     if (!b->t) return -2;
     orc_set_mac(b->t, b->mac);
-    return walk_per_particle(b->t, b->theta, &b->base);
+    return 0;
+}
+
+/* Forces of the groups gl[0..ng) (every group if gl is NULL), then: on a fresh
+ * tree, each covered particle's base becomes its group's interaction count; on
+ * a refitted tree, the interactions of the walk (sum over the covered
+ * particles) are compared with the covered particles' summed base.  *inter
+ * (optional): interactions of the walk per particle of the system. */
+static int block_walk(orc_block *b, const int64_t *gl, int64_t ng, int fresh, double growth,
+                      double *inter)
+{
+    const orc_tree *t = b->t;
+    int st = orc_forces(t, b->theta, b->eps, gl, ng, b->acc, b->pot, NULL, NULL);
+    if (st) return st;
+    int64_t *npp = (int64_t *)malloc(sizeof(int64_t) * (size_t)t->ngroups);
+    int64_t *npc = (int64_t *)malloc(sizeof(int64_t) * (size_t)t->ngroups);
+    if (!npp || !npc) { free(npp); free(npc); return -2; }
+    st = orc_walk_counts(t, b->theta, npp, npc);
+    int64_t now = 0, base = 0;
+    const int64_t cnt = gl ? ng : t->ngroups;
+    for (int64_t k = 0; k < cnt && !st; ++k) {
+        const int64_t g = gl ? gl[k] : k;
+        const int64_t c = npp[g] + npc[g];
+        for (int64_t j = t->gfirst[g]; j < t->gfirst[g] + t->gcount[g]; ++j) {
+            if (fresh) b->pbase[t->perm[j]] = c;
+            else base += b->pbase[t->perm[j]];
+        }
+        now += t->gcount[g] * c;
+    }
+    free(npp);
+    free(npc);
+    b->rebuild_next = !fresh && (double)now > (1.0 + growth) * (double)base;
+    if (inter) *inter = (double)now / (double)b->n;
+    return st;
 }
 
 orc_block *orc_block_new(double *pos, double *vel, const double *mass, int64_t n, double *acc,
@@ -834,7 +857,8 @@ orc_block *orc_block_new(double *pos, double *vel, const double *mass, int64_t n
     if (!b) return NULL;
     b->pos = pos; b->vel = vel; b->mass = mass; b->acc = acc; b->pot = pot; b->n = n;
     b->theta = theta; b->eps = eps; b->nleaf = nleaf; b->ncrit = ncrit; b->mac = mac;
-    if (block_rebuild(b) || orc_forces(b->t, theta, eps, NULL, 0, acc, pot, NULL, NULL)) {
+    b->pbase = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    if (!b->pbase || block_rebuild(b) || block_walk(b, NULL, 0, 1, 0.0, NULL)) {
         orc_block_free(b);
         return NULL;
     }
@@ -845,18 +869,26 @@ void orc_block_free(orc_block *b)
 {
     if (!b) return;
     orc_free(b->t);
+    free(b->pbase);
     free(b);
 }
 
-double orc_block_base(const orc_block *b) { return b->base; }
+double orc_block_base(const orc_block *b)
+{
+    int64_t s = 0;
+    for (int64_t i = 0; i < b->n; ++i) s += b->pbase[i];
+    return (double)s / (double)b->n;
+}
+
+int orc_block_rebuild_next(const orc_block *b) { return b->rebuild_next; }
 
 int orc_block_step(orc_block *b, const uint8_t *bins, int max_level, double dt_max,
                    double growth, int *rebuilt, double *sync_inter, int64_t *kicks)
 {
     const int64_t n = b->n;
+    if (max_level < 0 || max_level > 30) return -1;
     const int64_t S = (int64_t)1 << max_level;
     const double dtm = ldexp(dt_max, -max_level);
-    if (max_level < 0 || max_level > 30) return -1;
     for (int64_t i = 0; i < n; ++i)
         if (bins[i] > max_level) return -1;
     if (kicks) memset(kicks, 0, sizeof(int64_t) * (size_t)n);
@@ -865,26 +897,41 @@ int orc_block_step(orc_block *b, const uint8_t *bins, int max_level, double dt_m
         double h = 0.5 * ldexp(dt_max, -bins[i]);
         for (int k = 0; k < 3; ++k) b->vel[3 * i + k] = b->vel[3 * i + k] + b->acc[3 * i + k] * h;
     }
-    int64_t *gl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(b->t->ngroups + 1));
+    int64_t *gl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
     uint8_t *due = (uint8_t *)malloc((size_t)n);
     if (!gl || !due) { free(gl); free(due); return -2; }
     int st = 0;
     *rebuilt = 0;
     for (int64_t s = 1; s <= S && !st; ++s) {
         for (int64_t i = 0; i < 3 * n; ++i) b->pos[i] = b->pos[i] + b->vel[i] * dtm;
-        if (s < S) {
-            /* the particles whose step ends now; forces for the groups holding them */
-            for (int64_t i = 0; i < n; ++i) due[i] = (s % ((int64_t)1 << (max_level - bins[i]))) == 0;
+        /* the particles whose step ends now (all of them at the end) */
+        int64_t ndue = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            due[i] = (s % ((int64_t)1 << (max_level - bins[i]))) == 0;
+            ndue += due[i];
+        }
+        if (ndue == 0) continue;
+        /* the tree for this force evaluation: rebuilt, or refitted to the
+           current positions */
+        const int fresh = growth <= 0.0 || b->rebuild_next;
+        if (fresh) {
+            st = block_rebuild(b);
+            *rebuilt += 1;
+        } else {
             st = orc_refit(b->t, b->pos);
-            if (st) break;
+        }
+        if (st) break;
+        if (s < S) {
+            /* forces for the groups holding a due particle */
+            const orc_tree *t = b->t;
             int64_t ng = 0;
-            for (int64_t g = 0; g < b->t->ngroups; ++g) {
+            for (int64_t g = 0; g < t->ngroups; ++g) {
                 int any = 0;
-                for (int64_t j = b->t->gfirst[g]; j < b->t->gfirst[g] + b->t->gcount[g]; ++j)
-                    any |= due[b->t->perm[j]];
+                for (int64_t j = t->gfirst[g]; j < t->gfirst[g] + t->gcount[g]; ++j)
+                    any |= due[t->perm[j]];
                 if (any) gl[ng++] = g;
             }
-            if (ng > 0) st = orc_forces(b->t, b->theta, b->eps, gl, ng, b->acc, b->pot, NULL, NULL);
+            st = block_walk(b, gl, ng, fresh, growth, NULL);
             if (st) break;
             /* closing half kick of the step that ends, opening half kick of the next */
             for (int64_t i = 0; i < n; ++i) {
@@ -895,23 +942,8 @@ int orc_block_step(orc_block *b, const uint8_t *bins, int max_level, double dt_m
                 if (kicks) kicks[i] += 1;
             }
         } else {
-            /* every particle is due: rebuild if the refitted tree's walk has grown */
-            int rb = 1;
-            double inter = 0.0;
-            if (growth > 0.0) {
-                st = orc_refit(b->t, b->pos);
-                if (!st) st = walk_per_particle(b->t, b->theta, &inter);
-                if (st) break;
-                rb = inter > (1.0 + growth) * b->base;
-            }
-            if (rb) {
-                st = block_rebuild(b);
-                if (st) break;
-                inter = b->base;
-            }
-            *rebuilt = rb;
-            if (sync_inter) *sync_inter = inter;
-            st = orc_forces(b->t, b->theta, b->eps, NULL, 0, b->acc, b->pot, NULL, NULL);
+            /* every particle is due: every group, then the closing half kicks */
+            st = block_walk(b, NULL, 0, fresh, growth, sync_inter);
             if (st) break;
             for (int64_t i = 0; i < n; ++i) {
                 double h = 0.5 * ldexp(dt_max, -bins[i]);

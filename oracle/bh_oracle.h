@@ -156,12 +156,16 @@ typedef struct orc_block orc_block;
 orc_block *orc_block_new(double *pos, double *vel, const double *mass, int64_t n, double *acc,
                          double *pot, float theta, float eps, int nleaf, int ncrit, int mac);
 void orc_block_free(orc_block *b);
-/* interactions per particle of the walk right after the last rebuild */
+/* mean over the particles of their base: the interaction count of the group
+ * that held them in the last walk covering them on a freshly built tree */
 double orc_block_base(const orc_block *b);
+/* 1 if the next force evaluation will be on a rebuilt tree */
+int orc_block_rebuild_next(const orc_block *b);
 /* One block step of dt_max with the given bins (caller order): 2^max_level
- * substeps; see bh_oracle.c for the schedule.  *rebuilt: the tree was rebuilt at
- * the end; *sync_inter: interactions per particle of the walk that gave the
- * final forces; kicks (optional, [n]): steps completed per particle. */
+ * substeps; see bh_oracle.c for the schedule and the rebuild rule.  *rebuilt:
+ * the number of rebuilds during the step; *sync_inter: interactions per
+ * particle of the final walk (every group); kicks (optional, [n]): steps
+ * completed per particle. */
 int orc_block_step(orc_block *b, const uint8_t *bins, int max_level, double dt_max,
                    double growth, int *rebuilt, double *sync_inter, int64_t *kicks);
 

@@ -100,6 +100,7 @@ void free_buffers(bh_ctx *c)
     dfree(c->c_box);
     dfree(c->bins);
     dfree(c->due);
+    dfree(c->pbase);
     dfree(c->walk_spill);
     dfree(c->walk_part);
     dfree(c->g_first);
@@ -190,6 +191,7 @@ hipError_t each_buffer(bh_ctx *c, const Sizes &z, F f)
     B(c->c_box, 6 * z.cells);
     B(c->bins, z.n);
     B(c->due, z.n);
+    B(c->pbase, z.n);
     B(c->walk_spill, walk_spill_words(z.spill_waves));
     B(c->walk_part, 2 * z.spill_waves);
     B(c->g_first, z.n);
@@ -479,7 +481,6 @@ hipError_t enqueue_forces(bh_ctx *c, float *acc, float *pot)
     BH_HIP_TRY(rec(c, 6));
     BH_HIP_TRY(launch_rcrit(c));
     BH_HIP_TRY(launch_walk(c, !c->capturing));
-    if (!c->refitted) BH_HIP_TRY(launch_walk_base(c));
     BH_HIP_TRY(launch_scatter(c, acc, pot));
     BH_HIP_TRY(rec(c, 7));
     return hipSuccess;
@@ -591,6 +592,8 @@ int load(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n, const double *
     c->have_forces = false;
     c->energy_current = false;
     c->moved = false;
+    c->pbase_valid = false;
+    c->rebuild_next = false;
     TRY_ST(load_table(c, cl, n));
     reset_e0(c);
     TRY_HIP(c, enqueue_load(c, pos, mass, vel));
@@ -987,6 +990,8 @@ int bh_set_state(bh_ctx *c, const double *pos, const double *vel)
     c->have_forces = false;
     c->energy_current = false;
     c->moved = false;
+    c->pbase_valid = false;
+    c->rebuild_next = false;
     TRY_HIP(c, enqueue_rebuild(c));
     return sync_check(c);
 }

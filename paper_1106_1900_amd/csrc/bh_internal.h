@@ -103,11 +103,9 @@ struct DevMisc {
     unsigned long long sum_npc;
     unsigned long long tot_npp;        // never reset: totals over all walks
     unsigned long long tot_npc;
-    // block time-steps: interactions per particle of the full walk right after
-    // the last rebuild (valid if base_valid), particles per time-step bin
-    double base_inter;
-    uint32_t base_valid;
-    uint32_t pad1;
+    // block time-steps: the summed base of the particles a walk covered,
+    // particles per time-step bin
+    unsigned long long base_sum;
     uint32_t bin_count[kMaxBins];
     unsigned long long walked_groups;  // groups walked by the partial walks of a block step
 };
@@ -187,6 +185,10 @@ struct bh_ctx {
     double *c_box = nullptr;                 // [c][6] tight box of a refitted cell: lo x, y, z, hi x, y, z
     uint8_t *bins = nullptr;                 // block time-step bin per particle (caller order)
     uint8_t *due = nullptr;                  // particles due for forces at a substep (caller order)
+    uint32_t *pbase = nullptr;               // per particle (caller order): interactions of its group
+                                             // in the last walk covering it on a freshly built tree
+    bool pbase_valid = false;                // pbase recorded for the current system
+    bool rebuild_next = false;               // a refitted tree's walk grew past the block-step limit
     uint32_t *walk_spill = nullptr;          // per-wave overflow of the walk stack
     unsigned long long *walk_part = nullptr; // per-workgroup interaction totals of a walk [blocks][2]
     int64_t walk_spill_waves = 0;
@@ -276,7 +278,6 @@ hipError_t ctx_enqueue_refit(bh_ctx *c);     // group boxes and moments of the e
 hipError_t ctx_enqueue_forces(bh_ctx *c);    // opening radii and the full walk
 
 // block.hip
-hipError_t launch_walk_base(bh_ctx *c);      // records the walk after a rebuild
 
 // integrate.hip (per-cluster dt from the cluster table)
 hipError_t launch_kick_drift(bh_ctx *c);

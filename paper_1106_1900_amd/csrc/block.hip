@@ -1,7 +1,7 @@
 // block.hip - block time-steps (Sect. 5): between synchronisation points only the
 // particles due for an update get new forces, walked on the tree whose moments
 // are refitted to the current positions, and the tree is rebuilt once its walk
-// has become considerably more expensive than right after the last rebuild.
+// has become considerably more expensive than on a freshly built tree.
 //
 // The paper gives neither the time-step criterion nor the schedule.  Here:
 //  - each particle's step is dt_i = sqrt(2 eta l / |a_i|) rounded down to a
@@ -13,14 +13,17 @@
 //  - kick-drift-kick per bin: an opening half kick of every particle, then
 //    2^B substeps of dt_max 2^-B, each drifting every particle; at the end of
 //    substep s the particles of the bins with s a multiple of 2^(B - b) are due:
-//    the tree is refitted, the groups holding a due particle are walked, and
-//    each due particle gets its closing half kick and the opening half kick of
-//    its next step (a substep at which no particle is due only drifts);
-//  - at the last substep every particle is due.  The refitted tree is walked in
-//    full and its interactions per particle are compared with those of the walk
-//    right after the last rebuild: more than (1 + growth) times as many and the
-//    tree is rebuilt and walked again (growth <= 0: rebuilt every block step,
-//    which with B = 0 is exactly the leapfrog step).
+//    the groups holding a due particle are walked, and each due particle gets
+//    its closing half kick and the opening half kick of its next step (a
+//    substep at which no particle is due only drifts); at the last substep
+//    every particle is due and every group is walked;
+//  - the tree of each force evaluation: each particle carries a base, the
+//    interaction count of its group in the last walk that covered it on a
+//    freshly built tree.  A walk on a refitted tree is compared with the summed
+//    base of the particles it covered: more than (1 + growth) times as many
+//    interactions and the next force evaluation rebuilds the tree instead of
+//    refitting it (growth <= 0: every force evaluation rebuilds, which with
+//    B = 0 is exactly the leapfrog step).
 #include <cmath>
 #include <cstring>
 
@@ -112,12 +115,51 @@ kick_bins_kernel(int64_t n, const uint32_t *__restrict__ pid, const uint8_t *__r
     v4[i] = v;
 }
 
-// interactions per particle of the walk just finished (on a freshly built tree)
-__global__ void walk_base_kernel(DevMisc *m, int64_t n)
+// base of the particles of the walked groups (the active list, or every group):
+// their group's interaction count in the walk just finished on a fresh tree
+__global__ void __launch_bounds__(kBlock)
+base_record_kernel(const DevMisc *__restrict__ m, const uint32_t *__restrict__ glist,
+                   const uint32_t *__restrict__ g_first, const uint32_t *__restrict__ g_count,
+                   const uint32_t *__restrict__ g_npp, const uint32_t *__restrict__ g_npc,
+                   const uint32_t *__restrict__ pid, uint32_t *__restrict__ pbase)
 {
-    if (threadIdx.x != 0) return;
-    m->base_inter = (double)(m->sum_npp + m->sum_npc) / (double)n;
-    m->base_valid = 1u;
+    const uint32_t ng = glist ? m->nactive : m->ngroups;
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < ng; k += gridDim.x * kBlock) {
+        const uint32_t g = glist ? glist[k] : k;
+        const uint32_t cnt = g_npp[g] + g_npc[g];
+        const uint32_t s = g_first[g], e = s + g_count[g];
+        for (uint32_t i = s; i < e; ++i) pbase[pid[i]] = cnt;
+    }
+}
+
+__global__ void clear_base_sum_kernel(DevMisc *m)
+{
+    if (threadIdx.x == 0) m->base_sum = 0ull;
+}
+
+// summed base of the particles of the walked groups -> m->base_sum (a small
+// fixed grid: one addition per workgroup)
+__global__ void __launch_bounds__(kBlock)
+base_sum_kernel(DevMisc *__restrict__ m, const uint32_t *__restrict__ glist,
+                const uint32_t *__restrict__ g_first, const uint32_t *__restrict__ g_count,
+                const uint32_t *__restrict__ pid, const uint32_t *__restrict__ pbase)
+{
+    __shared__ unsigned long long s_sum[kBlock / kWave];
+    const uint32_t ng = glist ? m->nactive : m->ngroups;
+    unsigned long long sum = 0;
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < ng; k += gridDim.x * kBlock) {
+        const uint32_t g = glist ? glist[k] : k;
+        const uint32_t s = g_first[g], e = s + g_count[g];
+        for (uint32_t i = s; i < e; ++i) sum += pbase[pid[i]];
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, kWave);
+    if (threadIdx.x % kWave == 0) s_sum[threadIdx.x / kWave] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kBlock / kWave; ++i) t += s_sum[i];
+        if (t) atomicAdd(&m->base_sum, t);
+    }
 }
 
 bool bad_params(const bh_block_params *p)
@@ -174,17 +216,25 @@ int check_state(bh_ctx *c, const bh_block_params *p)
     return BH_OK;
 }
 
-}  // namespace
-
-namespace bh {
-
-hipError_t launch_walk_base(bh_ctx *c)
+hipError_t enqueue_base_record(bh_ctx *c, bool active)
 {
-    hipLaunchKernelGGL(walk_base_kernel, dim3(1), dim3(64), 0, c->stream, c->misc, c->n);
+    hipLaunchKernelGGL(base_record_kernel, dim3(kBinsGrid), dim3(kBlock), 0, c->stream, c->misc,
+                       active ? c->val[1] : nullptr, c->g_first, c->g_count, c->g_npp, c->g_npc,
+                       c->pid[c->cur], c->pbase);
     return hipGetLastError();
 }
 
-}  // namespace bh
+hipError_t enqueue_base_sum(bh_ctx *c, bool active)
+{
+    hipLaunchKernelGGL(clear_base_sum_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
+    BH_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(base_sum_kernel, dim3(kBinsGrid), dim3(kBlock), 0, c->stream, c->misc,
+                       active ? c->val[1] : nullptr, c->g_first, c->g_count, c->pid[c->cur],
+                       c->pbase);
+    return hipGetLastError();
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -207,71 +257,79 @@ int bh_block_step(bh_ctx *c, const bh_block_params *p, bh_block_stats *out)
     const int B = p->max_level;
     const int64_t S = (int64_t)1 << B;
     const double dtm = ldexp(p->dt_max, -B);
+    const bool always = !(p->growth > 0.0f);
+    const double limit = 1.0 + (double)p->growth;
     bh_block_stats st;
     memset(&st, 0, sizeof(st));
     st.substeps = S;
 
+    // on a freshly built tree the counts of its last walk are every particle's base
+    if (!c->pbase_valid || !c->refitted) {
+        BTRY(enqueue_base_record(c, false));
+        c->pbase_valid = true;
+    }
     BTRY(enqueue_bins(c, p));
     BTRY(enqueue_kick(c, p, 0));
     // the occupied bins: a substep at which none of them is due only drifts
     BTRY_ST(ctx_sync_check(c));
     uint32_t occupied[kMaxBins];
     for (int b = 0; b < kMaxBins; ++b) occupied[b] = c->misc_h->bin_count[b];
-    int64_t walked = 0;
     for (int64_t s = 1; s <= S; ++s) {
         BTRY(launch_drift(c, dtm));
         c->energy_current = false;
-        if (s < S) {
+        const bool last = s == S;     // every particle is due
+        if (!last) {
             bool any = false;
             for (int b = 0; b <= B; ++b)
                 any |= occupied[b] != 0 && (s & (((int64_t)1 << (B - b)) - 1)) == 0;
             if (!any) continue;
+        }
+        // the tree of this force evaluation: rebuilt, or refitted to the positions
+        const bool fresh = always || c->rebuild_next;
+        if (fresh) {
+            BTRY(ctx_enqueue_rebuild(c));
+            st.rebuilt += 1;
+        } else {
+            BTRY(ctx_enqueue_refit(c));
+        }
+        if (!last) {
             hipLaunchKernelGGL(due_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
                                c->bins, s, B, c->due);
             BTRY(hipGetLastError());
-            BTRY(ctx_enqueue_refit(c));
             BTRY(launch_rcrit(c));
             BTRY(launch_active_groups(c, c->due));
             BTRY(launch_walk(c, false, true));
             hipLaunchKernelGGL(count_walked_kernel, dim3(1), dim3(64), 0, c->stream, c->misc);
             BTRY(hipGetLastError());
-            BTRY(enqueue_kick(c, p, s));
-            continue;
-        }
-        // the synchronisation point: every particle is due
-        bool rebuild = true;
-        if (p->growth > 0.0f) {
-            BTRY(ctx_enqueue_refit(c));
+        } else {
             BTRY(ctx_enqueue_forces(c));
+        }
+        // a fresh tree's counts become the walked particles' base; a refitted
+        // tree's walk is judged against the base of the particles it covered
+        if (fresh) {
+            BTRY(enqueue_base_record(c, !last));
+            c->rebuild_next = false;
+        } else {
+            BTRY(enqueue_base_sum(c, !last));
             BTRY_ST(ctx_sync_check(c));
             const DevMisc &m = *c->misc_h;
-            st.sync_interactions = (double)(m.sum_npp + m.sum_npc) / (double)c->n;
-            st.base_interactions = m.base_inter;
-            rebuild = !m.base_valid ||
-                      st.sync_interactions > (1.0 + (double)p->growth) * m.base_inter;
-            walked += c->ngroups;
+            c->rebuild_next = !always && (double)(m.sum_npp + m.sum_npc) > limit * (double)m.base_sum;
         }
-        if (rebuild) {
-            BTRY(ctx_enqueue_rebuild(c));
-            BTRY(ctx_enqueue_forces(c));
-        }
-        st.rebuilt = rebuild ? 1 : 0;
-        BTRY(enqueue_kick(c, p, 0));
+        BTRY(enqueue_kick(c, p, last ? 0 : s));
     }
     c->moved = false;
     c->have_forces = true;
+    // the mean base over all particles, then the statistics
+    BTRY(enqueue_base_sum(c, false));
     BTRY_ST(ctx_sync_check(c));
     const DevMisc &m = *c->misc_h;
-    if (st.rebuilt) {
-        st.sync_interactions = m.base_inter;
-        st.base_interactions = m.base_inter;
-        walked += c->ngroups;
-    }
+    st.sync_interactions = (double)(m.sum_npp + m.sum_npc) / (double)c->n;
+    st.base_interactions = (double)m.base_sum / (double)c->n;
     for (int b = 0; b < kMaxBins; ++b) {
         st.bin_count[b] = (int64_t)m.bin_count[b];
         st.updates += st.bin_count[b] << b;
     }
-    st.walked_groups = walked + (int64_t)m.walked_groups;
+    st.walked_groups = (int64_t)c->ngroups + (int64_t)m.walked_groups;
     if (out) *out = st;
     return BH_OK;
 }

@@ -125,40 +125,101 @@ def test_second_order_with_mixed_bins(bins):
 
 
 def test_rebuild_rule_and_the_walk_it_measures():
+    # one level (B = 0): each block step is one force evaluation with every
+    # particle due, on the tree refitted to the new positions unless the walk
+    # before it had grown past the limit
     pos, vel, m = workloads.plummer(3000, 46)
     b = oracle.Block(pos, vel, m, 0.6, 0.01)
     base0 = b.base
     t0 = oracle.Tree(pos, m)
     npp, npc = t0.walk_counts(0.6)
     assert base0 == (t0.groups()["count"] * (npp + npc)).sum() / 3000
-    bins = oracle.block_bins(b.acc.astype(np.float32), 1 / 8, 3, 0.025, 0.01)
-    # a growth limit that cannot be reached: the walk of the refitted tree
-    rebuilt, inter, _ = b.step(bins, 3, 1 / 8, 1e9)
-    assert not rebuilt and b.base == base0
+    assert not b.rebuild_next
+    zero = np.zeros(3000, np.uint8)
+    # a limit that cannot be reached: refitted, and the walk is the refitted tree's
+    rebuilt, inter, _ = b.step(zero, 0, 1 / 8, 1e9)
+    assert rebuilt == 0 and b.base == base0 and not b.rebuild_next
     t0.refit(b.pos)
     npp, npc = t0.walk_counts(0.6)
     assert inter == (t0.groups()["count"] * (npp + npc)).sum() / 3000
     assert inter > base0        # the refitted cells have grown
-    # a limit below the growth: rebuilt, and the new base is the new tree's walk
-    rebuilt, inter2, _ = b.step(bins, 3, 1 / 8, 1e-9)
-    assert rebuilt
-    t1 = oracle.Tree(b.pos, m)
-    npp, npc = t1.walk_counts(0.6)
-    assert b.base == inter2 == (t1.groups()["count"] * (npp + npc)).sum() / 3000
-    acc, pot, _, _ = t1.forces(0.6, 0.01)
+    acc, pot, _, _ = t0.forces(0.6, 0.01)
     assert np.array_equal(b.acc, acc) and np.array_equal(b.pot, pot)
+    # a limit below the growth: the next evaluation is on a rebuilt tree, whose
+    # walk becomes the new base; then the refit again
+    c = oracle.Block(pos, vel, m, 0.6, 0.01)
+    rebuilt, inter1, _ = c.step(zero, 0, 1 / 8, 1e-9)
+    assert rebuilt == 0 and inter1 == inter and c.rebuild_next
+    rebuilt, inter2, _ = c.step(zero, 0, 1 / 8, 1e-9)
+    assert rebuilt == 1 and not c.rebuild_next
+    t1 = oracle.Tree(c.pos, m)
+    npp, npc = t1.walk_counts(0.6)
+    assert c.base == inter2 == (t1.groups()["count"] * (npp + npc)).sum() / 3000
+    acc, pot, _, _ = t1.forces(0.6, 0.01)
+    assert np.array_equal(c.acc, acc) and np.array_equal(c.pot, pot)
+    rebuilt, _, _ = c.step(zero, 0, 1 / 8, 1e-9)
+    assert rebuilt == 0 and c.rebuild_next
+
+
+def test_growth_zero_rebuilds_before_every_force_evaluation():
+    # all particles in the finest of 3 levels: 8 evaluations, 8 rebuilds, and the
+    # final forces are those of a fresh tree
+    pos, vel, m = workloads.plummer(2000, 47)
+    b = oracle.Block(pos, vel, m, 0.6, 0.01)
+    rebuilt, inter, kicks = b.step(np.full(2000, 3, np.uint8), 3, 1 / 8, 0.0)
+    assert rebuilt == 8 and np.all(kicks == 8) and not b.rebuild_next
+    t = oracle.Tree(b.pos, m)
+    acc, pot, _, _ = t.forces(0.6, 0.01)
+    assert np.array_equal(b.acc, acc) and np.array_equal(b.pot, pot)
+    assert b.base == inter
 
 
 def test_rebuild_threshold_is_one_plus_growth_times_the_base():
-    # the same block step with the growth limit just above and just below the
-    # growth it measures: kept, then rebuilt
+    # the same walk judged with the limit just above and just below the growth it
+    # measures: kept, then rebuilt before the next evaluation
     pos, vel, m = workloads.plummer(3000, 46)
+    zero = np.zeros(3000, np.uint8)
     first = oracle.Block(pos, vel, m, 0.6, 0.01)
-    bins = oracle.block_bins(first.acc.astype(np.float32), 1 / 8, 3, 0.025, 0.01)
-    _, inter, _ = first.step(bins, 3, 1 / 8, 1e9)
+    _, inter, _ = first.step(zero, 0, 1 / 8, 1e9)
     grown = inter / first.base - 1.0
     assert 0.0 < grown < 0.5
     for limit, want in ((grown * 1.01, False), (grown * 0.99, True)):
         b = oracle.Block(pos, vel, m, 0.6, 0.01)
-        rebuilt, _, _ = b.step(bins, 3, 1 / 8, limit)
-        assert bool(rebuilt) == want, (limit, grown)
+        b.step(zero, 0, 1 / 8, limit)
+        assert b.rebuild_next == want, (limit, grown)
+
+
+def test_walks_of_due_groups_compare_with_the_base_of_the_particles_they_cover():
+    # two levels, the finest holding a few particles: the substep's walk covers only
+    # their groups, and its growth is judged against those particles' base alone
+    pos, vel, m = workloads.plummer(3000, 48)
+    bins = np.zeros(3000, np.uint8)
+    bins[:40] = 1
+    # replay the substep by hand: opening kicks, drift half the step, refit, walk
+    # the groups holding the 40 particles
+    b = oracle.Block(pos, vel, m, 0.6, 0.01)
+    t = oracle.Tree(pos, m)
+    npp0, npc0 = t.walk_counts(0.6)
+    g = t.groups()
+    perm, _ = t.order()
+    gid = np.repeat(np.arange(g["count"].shape[0]), g["count"])
+    pbase = np.zeros(3000, np.int64)
+    pbase[perm] = (npp0 + npc0)[gid]
+    v = vel + b.acc * (0.5 / 4)                     # opening half kicks (bins 0 and 1)
+    v[:40] = vel[:40] + b.acc[:40] * (0.5 / 8)
+    p = pos + v * (1 / 8)
+    t.refit(p)
+    npp, npc = t.walk_counts(0.6)
+    walked = np.unique(gid[np.isin(perm, np.arange(40))])
+    now = (g["count"][walked] * (npp + npc)[walked]).sum()
+    cover = np.isin(gid, walked)
+    base_cov = pbase[perm[cover]].sum()
+    grown = now / base_cov - 1.0
+    assert grown > 0.0
+    # the decision at the substep picks the tree of the final evaluation: rebuilt
+    # with a limit just below the growth of the covered particles, refitted just
+    # above it
+    for limit, want in ((grown * 0.99, 1), (grown * 1.01, 0)):
+        d = oracle.Block(pos, vel, m, 0.6, 0.01)
+        rebuilt, _, _ = d.step(bins, 1, 1 / 4, limit)
+        assert rebuilt == want, (limit, grown)

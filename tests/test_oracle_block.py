@@ -223,3 +223,27 @@ def test_walks_of_due_groups_compare_with_the_base_of_the_particles_they_cover()
         d = oracle.Block(pos, vel, m, 0.6, 0.01)
         rebuilt, _, _ = d.step(bins, 1, 1 / 4, limit)
         assert rebuilt == want, (limit, grown)
+
+
+def test_a_walk_that_has_not_grown_is_kept():
+    # a block step too short to move anything: the refitted walk equals the base,
+    # and with 1 + growth == 1 in float64 only strictly more would rebuild
+    pos, vel, m = workloads.plummer(2000, 49)
+    b = oracle.Block(pos, vel, m, 0.6, 0.01)
+    base = b.base
+    rebuilt, inter, _ = b.step(np.zeros(2000, np.uint8), 0, 1e-300, 1e-30)
+    assert np.array_equal(b.pos, pos)
+    assert rebuilt == 0 and inter == base and not b.rebuild_next
+
+
+def test_substeps_with_nothing_due_leave_the_decision_alone():
+    # every particle in bin 1 of a 2-level block: substeps 1 and 3 only drift; the
+    # decision of the walk at substep 2 picks the tree at substep 4, which is then
+    # a fresh tree at the final positions
+    pos, vel, m = workloads.plummer(2000, 50)
+    b = oracle.Block(pos, vel, m, 0.6, 0.01)
+    rebuilt, _, kicks = b.step(np.ones(2000, np.uint8), 2, 1 / 8, 1e-9)
+    assert rebuilt == 1 and np.all(kicks == 2) and not b.rebuild_next
+    t = oracle.Tree(b.pos, m)
+    acc, pot, _, _ = t.forces(0.6, 0.01)
+    assert np.array_equal(b.acc, acc) and np.array_equal(b.pot, pot)

@@ -767,10 +767,12 @@ int orc_kdk_step(double *pos, double *vel, const double *mass, int64_t n,
 /*  - step of particle i: dt_i = sqrt(2 eta l / |a_i|), l a length (the        */
 /*    softening), rounded down to a power-of-two fraction dt_max 2^-b of the    */
 /*    block step, b in [0, B];                                                  */
-/*  - kick-drift-kick per bin: every particle drifts every substep of           */
-/*    dt_max 2^-B; a particle of bin b is kicked (half, then half again) at     */
-/*    the end of each of its 2^b steps, with forces recomputed for the groups   */
-/*    that hold it; at the end of the block step every particle is due;         */
+/*  - kick-drift-kick per bin: substeps of dt_max 2^-B; a particle of bin b is  */
+/*    kicked (half, then half again) at the end of each of its 2^b steps, with  */
+/*    forces recomputed for the groups that hold it; at the end of the block    */
+/*    step every particle is due.  Every particle drifts before each force      */
+/*    evaluation, over the substeps since the previous one (k dt_max 2^-B in    */
+/*    one step: no velocity changes in between);                                */
 /*  - the cost of a walk: each particle carries the interaction count of its   */
 /*    group in the last walk that covered it on a freshly built tree (its       */
 /*    base).  A walk on a refitted tree is compared with the base of the        */
@@ -902,8 +904,9 @@ int orc_block_step(orc_block *b, const uint8_t *bins, int max_level, double dt_m
     if (!gl || !due) { free(gl); free(due); return -2; }
     int st = 0;
     *rebuilt = 0;
+    int64_t pending = 0;   /* substeps since the last drift */
     for (int64_t s = 1; s <= S && !st; ++s) {
-        for (int64_t i = 0; i < 3 * n; ++i) b->pos[i] = b->pos[i] + b->vel[i] * dtm;
+        ++pending;
         /* the particles whose step ends now (all of them at the end) */
         int64_t ndue = 0;
         for (int64_t i = 0; i < n; ++i) {
@@ -911,6 +914,11 @@ int orc_block_step(orc_block *b, const uint8_t *bins, int max_level, double dt_m
             ndue += due[i];
         }
         if (ndue == 0) continue;
+        /* no velocity changes between force evaluations: one drift over the
+           substeps since the last one */
+        const double span = (double)pending * dtm;
+        pending = 0;
+        for (int64_t i = 0; i < 3 * n; ++i) b->pos[i] = b->pos[i] + b->vel[i] * span;
         /* the tree for this force evaluation: rebuilt, or refitted to the
            current positions */
         const int fresh = growth <= 0.0 || b->rebuild_next;

@@ -11,11 +11,12 @@
 //    IEEE machine); bins are assigned at the start of each block step, when
 //    every particle is synchronised, and held for the block step;
 //  - kick-drift-kick per bin: an opening half kick of every particle, then
-//    2^B substeps of dt_max 2^-B, each drifting every particle; at the end of
-//    substep s the particles of the bins with s a multiple of 2^(B - b) are due:
+//    2^B substeps of dt_max 2^-B; at the end of substep s the particles of the
+//    bins with s a multiple of 2^(B - b) are due (every particle is first
+//    drifted over the substeps since the previous force evaluation, in one step):
 //    the groups holding a due particle are walked, and each due particle gets
 //    its closing half kick and the opening half kick of its next step (a
-//    substep at which no particle is due only drifts); at the last substep
+//    substep at which no particle is due does nothing); at the last substep
 //    every particle is due and every group is walked;
 //  - the tree of each force evaluation: each particle carries a base, the
 //    interaction count of its group in the last walk that covered it on a
@@ -274,9 +275,9 @@ int bh_block_step(bh_ctx *c, const bh_block_params *p, bh_block_stats *out)
     BTRY_ST(ctx_sync_check(c));
     uint32_t occupied[kMaxBins];
     for (int b = 0; b < kMaxBins; ++b) occupied[b] = c->misc_h->bin_count[b];
+    int64_t pending = 0;              // substeps since the last drift
     for (int64_t s = 1; s <= S; ++s) {
-        BTRY(launch_drift(c, dtm));
-        c->energy_current = false;
+        ++pending;
         const bool last = s == S;     // every particle is due
         if (!last) {
             bool any = false;
@@ -284,6 +285,11 @@ int bh_block_step(bh_ctx *c, const bh_block_params *p, bh_block_stats *out)
                 any |= occupied[b] != 0 && (s & (((int64_t)1 << (B - b)) - 1)) == 0;
             if (!any) continue;
         }
+        // velocities change only at force evaluations: one drift over the
+        // substeps since the last one
+        BTRY(launch_drift(c, (double)pending * dtm));
+        pending = 0;
+        c->energy_current = false;
         // the tree of this force evaluation: rebuilt, or refitted to the positions
         const bool fresh = always || c->rebuild_next;
         if (fresh) {

@@ -43,8 +43,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_plummer_1m_traffic.json")
 WALK_SRC = os.path.join(ROOT, "paper_1106_1900_amd", "csrc", "walk.hip")
 
 
+_T0 = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print("[%7.1f s]" % (time.perf_counter() - _T0), *a, file=sys.stderr, flush=True)
 
 
 def walk_source_hash():

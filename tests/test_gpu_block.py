@@ -172,3 +172,35 @@ def test_block_energy_and_errors():
     with pytest.raises(bh.BHError):
         ctx.block_step(1 / 32, ETA, LENGTH, 3, 0.0)
     ctx.close()
+
+
+def test_block_steps_at_full_size():
+    # N = 2^20 Plummer, theta 0.75, eps 1/64 (the headline workload): one level with
+    # a rebuild before every evaluation is the leapfrog step bit for bit, and a
+    # refit-only block step of 5 levels walks exactly the groups holding due particles
+    n = 1 << 20
+    pos, vel, m = workloads.plummer(n, 2)
+    say("case block full size", n)
+    a = _ctx(pos, vel, m, 0.75, 1 / 64)
+    b = _ctx(pos, vel, m, 0.75, 1 / 64)
+    st = a.block_step(1 / 64, ETA, 1 / 64, 0, 0.0)
+    b.leapfrog_step(1 / 64)
+    assert st["rebuilt"] == 1 and st["updates"] == n
+    for x, y in zip(_state(a), _state(b)):
+        assert np.array_equal(x, y)
+    b.close()
+    ex = a.export_tree()
+    bins, _ = a.block_bins(1 / 16, 0.01, 1 / 64, 5)
+    pb = bins.cpu().numpy()[ex["perm"]]
+    gid = np.repeat(np.arange(ex["gfirst"].shape[0]), ex["gcount"])
+    want = ex["gfirst"].shape[0]                 # the final walk of every group
+    for s in range(1, 32):
+        due = (s % (1 << (5 - pb.astype(np.int64)))) == 0
+        if due.any():
+            want += np.unique(gid[due]).shape[0]
+    st = a.block_step(1 / 16, 0.01, 1 / 64, 5, 1e9)
+    assert st["rebuilt"] == 0 and st["walked_groups"] == want
+    assert st["updates"] == int((1 << bins.cpu().numpy().astype(np.int64)).sum())
+    x, v, acc, pot = _state(a)
+    assert np.isfinite(x).all() and np.isfinite(acc).all()
+    a.close()

@@ -269,8 +269,9 @@ int bh_block_bins(bh_ctx *ctx, const bh_block_params *p, uint8_t *bins, int64_t 
  * Needs current forces of every particle (a force call, leapfrog step or earlier
  * block step, and no drift since); if the tree has not been refitted since it
  * was built, the counts of its last walk become every particle's base.  Whether
- * the next evaluation rebuilds is kept in the context across block steps (reset
- * by loads and bh_set_state).  out: host, may be NULL.  Synchronous: after the
+ * the next evaluation rebuilds is kept in the context across block steps (and
+ * dropped when the tree has been rebuilt since: loads, bh_set_state, leapfrog
+ * steps).  out: host, may be NULL.  Synchronous: after the
  * bins, after each walk of a refitted tree (for the rule) and at the end. */
 int bh_block_step(bh_ctx *ctx, const bh_block_params *p, bh_block_stats *out);
 

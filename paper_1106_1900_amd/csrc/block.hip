@@ -264,11 +264,13 @@ int bh_block_step(bh_ctx *c, const bh_block_params *p, bh_block_stats *out)
     memset(&st, 0, sizeof(st));
     st.substeps = S;
 
-    // on a freshly built tree the counts of its last walk are every particle's base
+    // on a freshly built tree the counts of its last walk are every particle's base,
+    // and nothing calls for a rebuild
     if (!c->pbase_valid || !c->refitted) {
         BTRY(enqueue_base_record(c, false));
         c->pbase_valid = true;
     }
+    if (!c->refitted) c->rebuild_next = false;
     BTRY(enqueue_bins(c, p));
     BTRY(enqueue_kick(c, p, 0));
     // the occupied bins: a substep at which none of them is due only drifts

@@ -204,3 +204,19 @@ def test_block_steps_at_full_size():
     x, v, acc, pot = _state(a)
     assert np.isfinite(x).all() and np.isfinite(acc).all()
     a.close()
+
+
+def test_pending_rebuild_kept_across_block_steps_and_dropped_by_a_rebuild():
+    # one level, a tiny growth limit: the refitted walk of a block step sets the
+    # decision, which the next block step acts on; a leapfrog step in between
+    # rebuilds the tree and the decision lapses
+    pos, vel, m = workloads.plummer(20_000, 76)
+    for between in (False, True):
+        ctx = _ctx(pos, vel, m, 0.6, 0.01)
+        st = ctx.block_step(1 / 16, ETA, LENGTH, 0, np.float32(1e-6))
+        assert st["rebuilt"] == 0
+        if between:
+            ctx.leapfrog_step(1 / 64)
+        st = ctx.block_step(1 / 16, ETA, LENGTH, 0, np.float32(1e-6))
+        assert st["rebuilt"] == (0 if between else 1), between
+        ctx.close()

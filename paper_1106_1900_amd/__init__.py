@@ -10,6 +10,10 @@ import of ``Context`` fails.
 from .binding import (  # noqa: F401
     MAC_EQ1,
     MAC_MIN_DIST,
+    REQ_DONE,
+    REQ_FAILED,
+    REQ_QUEUED,
+    REQ_RUNNING,
     BHError,
     Cluster,
     Context,
@@ -20,4 +24,4 @@ from .binding import (  # noqa: F401
     declared_functions,
 )
 
-__all__ = ["MAC_EQ1", "MAC_MIN_DIST", "BHError", "Cluster", "Context", "Server", "Stats", "library_path", "load_library", "declared_functions"]
+__all__ = ["MAC_EQ1", "MAC_MIN_DIST", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "REQ_FAILED", "BHError", "Cluster", "Context", "Server", "Stats", "library_path", "load_library", "declared_functions"]

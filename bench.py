@@ -369,7 +369,7 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4, alone=True):
     return out
 
 
-def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
+def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256, max_resident=0):
     """The serving loop on a Poisson trace: latency (completion - arrival, with
     queueing) percentiles, offered and served particle-force-evaluation rates."""
     import numpy as np
@@ -396,7 +396,7 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
     check = set(np.random.default_rng(seed + 2).choice(small, min(4, len(small)),
                                                       replace=False).tolist())
     kept = {}
-    srv = bh.Server(budget, max_requests=max_requests)
+    srv = bh.Server(budget, max_requests=max_requests, max_resident=max_resident)
     cap = srv.stats()["capacity_particles"]
     torch.cuda.synchronize()
     t0 = srv.now()
@@ -446,6 +446,7 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256):
                     "N log-uniform in [1024, 2097152], theta 0.5 or 0.75, eps 0.01, 1 force "
                     "evaluation + %d leapfrog steps of dt 1/128" % (count, rate, steps),
         "hbm_budget_bytes": int(budget), "capacity_particles": int(cap),
+        "max_resident": int(max_resident),
         "latency_p50_s": st["latency_p50"], "latency_p99_s": st["latency_p99"],
         "latency_max_s": st["latency_max"],
         "queue_wait_p50_s": st["queue_wait_p50"], "queue_wait_p99_s": st["queue_wait_p99"],
@@ -849,6 +850,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the served trace (2000: the full 10 s trace)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-max-resident", type=int, default=1 << 25,
+                    help="resident-particle limit of the served run (0: the memory budget only)")
     ap.add_argument("--serve-budget-gib", type=float, default=0.0,
                     help="device memory for the server (0: 60%% of the free memory)")
     ap.add_argument("--serve-small-budget-gib", type=float, default=4.0,
@@ -908,7 +911,8 @@ def main():
         return
     if args.only == "serve":
         budget = int(args.serve_budget_gib * (1 << 30)) or int(0.6 * torch.cuda.mem_get_info()[0])
-        print(json.dumps(bench_serve(args.serve_requests, args.serve_rate, budget)), flush=True)
+        print(json.dumps(bench_serve(args.serve_requests, args.serve_rate, budget,
+                                     max_resident=args.serve_max_resident)), flush=True)
         return
 
     n = args.n
@@ -1016,7 +1020,8 @@ def main():
         if budget <= 0:
             budget = int(0.6 * torch.cuda.mem_get_info()[0])
         log("serving %d requests" % args.serve_requests)
-        out["served"] = bench_serve(args.serve_requests, args.serve_rate, budget)
+        out["served"] = bench_serve(args.serve_requests, args.serve_rate, budget,
+                                    max_resident=args.serve_max_resident)
         # the same trace under a budget that makes requests wait for admission
         small = int(args.serve_small_budget_gib * (1 << 30))
         if small > 0:

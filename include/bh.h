@@ -362,7 +362,7 @@ int bh_set_tuning(bh_ctx *ctx, const bh_tune_entry *entries, int64_t count);
  * and advances them together.  A request is one system: a force evaluation
  * followed by nsteps leapfrog steps.  Admission is first come, first served,
  * while the resident particles and requests fit the capacity derived from the
- * memory budget; every iteration (bh_server_step) advances each resident request
+ * memory budget and the resident-particle limit; every iteration (bh_server_step) advances each resident request
  * by one unit (its force evaluation, then one step), so requests join and leave
  * the batch between iterations (continuous batching at iteration level).
  */
@@ -377,6 +377,11 @@ typedef struct {
     int32_t min_nleaf;          /* smallest leaf size a request may use (1..nleaf; the
                                    cell storage is sized for it; 0: min(8, nleaf)) */
     int32_t pad;
+    int64_t max_resident;       /* most resident particles (0: as many as the budget
+                                   holds).  A bounded working set keeps iterations short
+                                   under overload, so requests finish closer to arrival
+                                   order; a request larger than the limit is admitted
+                                   when nothing else is resident. */
 } bh_server_params;
 
 typedef struct {

@@ -422,7 +422,8 @@ class Context:
 class ServerParams(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_requests", ctypes.c_int64),
                 ("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
-                ("min_nleaf", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("min_nleaf", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("max_resident", ctypes.c_int64)]
 
 
 class Request(ctypes.Structure):
@@ -479,7 +480,7 @@ class Server:
     memory budget and advanced together one unit per iteration."""
 
     def __init__(self, hbm_budget_bytes, max_requests=256, nleaf=16, ncrit=64, min_nleaf=0,
-                 stream=None):
+                 stream=None, max_resident=0):
         import torch
         self._L = load_library()
         _server_sigs(self._L)
@@ -487,7 +488,7 @@ class Server:
             stream = torch.cuda.current_stream()
         self.stream = stream
         p = ServerParams(int(hbm_budget_bytes), int(max_requests), int(nleaf), int(ncrit),
-                         int(min_nleaf), 0)
+                         int(min_nleaf), 0, int(max_resident))
         h = _vp()
         st = self._L.bh_server_create(ctypes.byref(h), ctypes.byref(p), _vp(stream.cuda_stream))
         if st:

@@ -233,6 +233,8 @@ int admit(bh_server *s, double t)
     for (int64_t tk : s->queue) {
         const Req &q = s->reqs[tk];
         if (n + q.r.n > s->cap_n || (int64_t)k >= s->p.max_requests) break;
+        // the working-set limit, which a lone request may exceed
+        if (s->p.max_resident > 0 && n > 0 && n + q.r.n > s->p.max_resident) break;
         cand.push_back(tk);
         n += q.r.n;
         k += 1;
@@ -316,7 +318,7 @@ int bh_server_create(bh_server **out, const bh_server_params *p, void *hip_strea
     *out = nullptr;
     if (p->hbm_budget_bytes <= 0 || p->max_requests < 1 || p->max_requests > (1 << 20) ||
         p->nleaf < 1 || p->nleaf > 64 || p->ncrit < 1 || p->ncrit > 64 || p->min_nleaf < 0 ||
-        p->min_nleaf > p->nleaf)
+        p->min_nleaf > p->nleaf || p->max_resident < 0)
         return BH_EINVAL;
     bh_server *s = new (std::nothrow) bh_server();
     if (!s) return BH_ENOMEM;

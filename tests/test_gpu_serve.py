@@ -42,11 +42,12 @@ def _alone(q):
     return out, e
 
 
-def _serve(reqs, budget, max_requests=16, stagger=False):
+def _serve(reqs, budget, max_requests=16, stagger=False, max_resident=0):
     import torch
 
     import paper_1106_1900_amd as bh
-    srv = bh.Server(budget, max_requests=max_requests)
+    srv = bh.Server(budget, max_requests=max_requests, max_resident=max_resident)
+    largest = max(q["pos"].shape[0] for q in reqs)
     outs, tickets = [], []
     pending = list(range(len(reqs)))
     steps = 0
@@ -71,6 +72,8 @@ def _serve(reqs, budget, max_requests=16, stagger=False):
         st = srv.stats()
         cap = st["capacity_particles"]
         assert st["resident_particles"] <= cap
+        if max_resident:
+            assert st["resident_particles"] <= max(max_resident, largest)
         steps += 1
         assert steps < 500
     torch.cuda.synchronize()
@@ -197,4 +200,19 @@ def test_release_drops_finished_records_only():
     srv.step()                                 # its one leapfrog step
     assert srv.poll(waiting)["state"] == 2
     srv.release(waiting)
+    srv.close()
+
+
+def test_resident_limit_bounds_the_working_set():
+    # a limit below the largest request (20,000 particles): that request is admitted
+    # alone, the others never exceed the limit together, and every result is the
+    # same as the request run alone
+    reqs = _requests()
+    srv, tickets, outs, _ = _serve(reqs, 1 << 30, max_resident=15_000)
+    assert all(srv.poll(t)["state"] == 2 for t in tickets)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["iterations"] > 1 + max(q["nsteps"] for q in reqs)
+    for q, o in zip(reqs, outs):
+        (x, v, a, p), _ = _alone(q)
+        assert np.array_equal(o[0].cpu().numpy(), x) and np.array_equal(o[2].cpu().numpy(), a)
     srv.close()

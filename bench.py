@@ -614,6 +614,9 @@ def bench_sweep():
         st = ctx.stats()
         scaling.append({"n": n, "ms_per_eval": ms, "particles_per_s": n / (ms * 1e-3),
                         "build_ms": st.ms_keys + st.ms_sort + st.ms_move + st.ms_tree + st.ms_moments,
+                        "phases_ms": {"keys": st.ms_keys, "sort": st.ms_sort, "move": st.ms_move,
+                                      "tree": st.ms_tree, "moments": st.ms_moments,
+                                      "walk": st.ms_walk_kernel},
                         "walk_ms": st.ms_walk_kernel})
         log(scaling[-1])
         ctx.close()

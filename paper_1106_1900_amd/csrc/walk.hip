@@ -69,8 +69,13 @@ constexpr float kFar = 1.0e30f;
 #define BH_WALK_WAVES_PER_EU 4
 #endif
 constexpr int kUnroll = BH_WALK_UNROLL;   // tile entries per loop trip
+// Workgroups of the persistent grid per CU: as many as are resident at once (LDS
+// and registers allow four).  A larger grid leaves workgroups waiting for a slot,
+// and the groups those hold from the start (each wavefront's first group is its
+// own index) are then walked only at the end, after the rest of the tree has
+// left the caches.
 #ifndef BH_WALK_BLOCKS_PER_CU
-#define BH_WALK_BLOCKS_PER_CU 8
+#define BH_WALK_BLOCKS_PER_CU 4
 #endif
 
 struct WalkArgs {

@@ -273,7 +273,7 @@ int bh_block_step(bh_ctx *c, const bh_block_params *p, bh_block_stats *out)
     if (!c->refitted) c->rebuild_next = false;
     BTRY(enqueue_bins(c, p));
     BTRY(enqueue_kick(c, p, 0));
-    // the occupied bins: a substep at which none of them is due only drifts
+    // the occupied bins: a substep at which none of them is due does nothing
     BTRY_ST(ctx_sync_check(c));
     uint32_t occupied[kMaxBins];
     for (int b = 0; b < kMaxBins; ++b) occupied[b] = c->misc_h->bin_count[b];
@@ -292,6 +292,7 @@ int bh_block_step(bh_ctx *c, const bh_block_params *p, bh_block_stats *out)
         BTRY(launch_drift(c, (double)pending * dtm));
         pending = 0;
         c->energy_current = false;
+        c->moved = true;              // until the step completes: forces are stale
         // the tree of this force evaluation: rebuilt, or refitted to the positions
         const bool fresh = always || c->rebuild_next;
         if (fresh) {

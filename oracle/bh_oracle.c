@@ -19,6 +19,7 @@ struct orc_tree {
     int64_t n;
     int nleaf, ncrit;
     double lo[3], L, scale;
+    double hi[3];       /* per-axis maximum of the build's positions */
     /* particles in sorted order */
     int64_t *perm;
     uint64_t *key;
@@ -33,8 +34,10 @@ struct orc_tree {
     uint8_t *leaf;
     int32_t *nchild;
     double *M, *com, *S; /* [c], [c][3], [c][6] */
-    double *side;        /* [c] side l of the opening test: L 2^-level after a build,
-                            grown to the extent of the cell's particles by a refit */
+    double *side;        /* [c] side l of the opening test: L 2^-level after a build;
+                            after a refit see orc_refit */
+    double *cen;         /* [c][3] centre of the opening test: the geometric centre
+                            after a build; after a refit see orc_refit */
     /* groups */
     int64_t ngroups;
     int64_t *gfirst, *gcount;
@@ -319,13 +322,15 @@ static void build_moments(orc_tree *t)
 
 /* ------------------------------------------------------------------------- */
 
+static double cell_geometry(const orc_tree *t, int64_t c, double g[3]);
+
 void orc_free(orc_tree *t)
 {
     if (!t) return;
     free(t->perm); free(t->key); free(t->q); free(t->x); free(t->m);
     free(t->level); free(t->prefix); free(t->first); free(t->count);
     free(t->parent); free(t->child); free(t->leaf); free(t->nchild);
-    free(t->M); free(t->com); free(t->S); free(t->side);
+    free(t->M); free(t->com); free(t->S); free(t->side); free(t->cen);
     free(t->gfirst); free(t->gcount); free(t->gc); free(t->gh);
     free(t);
 }
@@ -337,6 +342,11 @@ orc_tree *orc_build(const double *pos, const double *mass, int64_t n, int nleaf,
     if (!t) return NULL;
     t->n = n; t->nleaf = nleaf; t->ncrit = ncrit;
     if (orc_domain(pos, n, t->lo, &t->L, &t->scale)) { orc_free(t); return NULL; }
+    for (int k = 0; k < 3; ++k) {
+        t->hi[k] = -INFINITY;
+        for (int64_t i = 0; i < n; ++i)
+            if (pos[3 * i + k] > t->hi[k]) t->hi[k] = pos[3 * i + k];
+    }
     uint64_t *key_in = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
     uint32_t *q_in = (uint32_t *)malloc(sizeof(uint32_t) * 3 * (size_t)n);
     t->perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
@@ -363,8 +373,9 @@ orc_tree *orc_build(const double *pos, const double *mass, int64_t n, int nleaf,
     t->com = (double *)malloc(sizeof(double) * 3 * (size_t)t->ncells);
     t->S = (double *)malloc(sizeof(double) * 6 * (size_t)t->ncells);
     t->side = (double *)malloc(sizeof(double) * (size_t)t->ncells);
-    if (!t->M || !t->com || !t->S || !t->side) goto fail;
-    for (int64_t c = 0; c < t->ncells; ++c) t->side[c] = ldexp(t->L, -t->level[c]);
+    t->cen = (double *)malloc(sizeof(double) * 3 * (size_t)t->ncells);
+    if (!t->M || !t->com || !t->S || !t->side || !t->cen) goto fail;
+    for (int64_t c = 0; c < t->ncells; ++c) t->side[c] = cell_geometry(t, c, t->cen + 3 * c);
     build_moments(t);
     if (build_groups(t)) goto fail;
     return t;
@@ -380,8 +391,13 @@ fail:
  * build stay; the particles take the new positions (input order) and every
  * cell's moments and every group's box are recomputed from them.  The paper
  * names the growth of the cell size l as what makes the walk of a refitted
- * tree slower: a cell's side becomes the larger of its build side L 2^-level
- * and the largest side of its particles' tight box. */
+ * tree slower.  Both opening tests rely on the cube of side l about the centre
+ * of Eq. (1) holding every particle of the cell, so the refit keeps that true:
+ * a cell whose particles all still lie in its key cell (inside the build's
+ * bounding box, with the cell's key prefix under the build's integer map)
+ * keeps the build's geometry; any other cell takes the tight box of its
+ * particles, centre 0.5 (lo + hi) per axis and side the larger of L 2^-level
+ * and the box's largest extent. */
 int orc_refit(orc_tree *t, const double *pos)
 {
     if (!t || !pos) return -1;
@@ -394,18 +410,34 @@ int orc_refit(orc_tree *t, const double *pos)
     build_moments(t);
     group_boxes(t);
     for (int64_t c = 0; c < t->ncells; ++c) {
-        double ext = 0.0;
+        int lev = t->level[c];
+        int shift = ORC_MAX_LEVEL - lev;
+        double blo[3], bhi[3];
+        int inside = 1;
         for (int k = 0; k < 3; ++k) {
-            double lo = INFINITY, hi = -INFINITY;
+            uint32_t cell_k = t->q[3 * t->first[c] + k] >> shift;
+            blo[k] = INFINITY;
+            bhi[k] = -INFINITY;
             for (int64_t j = t->first[c]; j < t->first[c] + t->count[c]; ++j) {
                 double x = t->x[3 * j + k];
-                lo = x < lo ? x : lo;
-                hi = x > hi ? x : hi;
+                blo[k] = x < blo[k] ? x : blo[k];
+                bhi[k] = x > bhi[k] ? x : bhi[k];
+                if (!(x >= t->lo[k] && x <= t->hi[k]) ||
+                    (coord_to_int(x, t->lo[k], t->scale) >> shift) != cell_k)
+                    inside = 0;
             }
-            ext = hi - lo > ext ? hi - lo : ext;
         }
-        double l = ldexp(t->L, -t->level[c]);
-        t->side[c] = ext > l ? ext : l;
+        double l = cell_geometry(t, c, t->cen + 3 * c);
+        if (inside) {
+            t->side[c] = l;
+        } else {
+            double ext = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                ext = bhi[k] - blo[k] > ext ? bhi[k] - blo[k] : ext;
+                t->cen[3 * c + k] = 0.5 * (blo[k] + bhi[k]);
+            }
+            t->side[c] = ext > l ? ext : l;
+        }
     }
     return 0;
 }
@@ -485,8 +517,7 @@ static double cell_geometry(const orc_tree *t, int64_t c, double g[3])
 void orc_rcrit(const orc_tree *t, float theta, float *rcrit2, double *centre)
 {
     for (int64_t c = 0; c < t->ncells; ++c) {
-        double g[3];
-        (void)cell_geometry(t, c, g);
+        const double *g = t->cen + 3 * c;
         double l = t->side[c];
         double r;
         if (t->mac) {
@@ -520,13 +551,13 @@ int orc_mac_accept(const orc_tree *t, int64_t g, int64_t c, float rcrit2_c)
 
 /* Minimum-distance test (Salmon & Warren 1994, named in Sect. 3.3 as the
  * alternative): d is the smallest distance between the group's box and the
- * cell's cube (side l about its geometric centre), taken in float32 on offsets
- * from the group centre with the cube's half side (float)(l / 2); accept when
+ * cell's cube (side l about its centre: the geometric centre of a built cell,
+ * see orc_refit for a refitted one), taken in float32 on offsets from the group
+ * centre with the cube's half side (float)(l / 2); accept when
  * d^2 > rmin2_c = (float)((l / theta)^2). */
 int orc_mac_accept_min(const orc_tree *t, int64_t g, int64_t c, float rmin2_c)
 {
-    double gcen[3];
-    (void)cell_geometry(t, c, gcen);
+    const double *gcen = t->cen + 3 * c;
     float h = (float)(0.5 * t->side[c]);
     float u[3];
     for (int k = 0; k < 3; ++k) {

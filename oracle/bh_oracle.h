@@ -61,8 +61,13 @@ void orc_free(orc_tree *t);
 
 /* Multipole-only update (Sect. 5): keep the tree's cells, groups, keys and
  * domain; take new positions (input order, [n][3]) and recompute every cell's
- * moments and every group's box from them.  Returns 0, or -1 for a non-finite
- * coordinate (the tree is then unchanged) or a null argument. */
+ * moments and every group's box from them.  A cell whose particles all still lie
+ * in its key cell (inside the build's bounding box, with the cell's key prefix
+ * under the build's integer map) keeps the build's geometry for the opening
+ * tests; any other cell takes the tight box of its particles (centre, and side
+ * max(L 2^-level, largest extent)), so that the cube of the tests holds every
+ * particle of the cell.  Returns 0, or -1 for a non-finite coordinate (the tree
+ * is then unchanged) or a null argument. */
 int orc_refit(orc_tree *t, const double *pos);
 
 int64_t orc_n(const orc_tree *t);
@@ -95,8 +100,8 @@ int orc_get_mac(const orc_tree *t);
 /* Opening radius of the tree's test.  Eq. (1): r_crit = l / theta + delta, with
  * l = L 2^-level the cell side and delta the distance between the geometric
  * centre and the centre of mass; minimum distance: r_crit = l / theta.  Outputs
- * (each optional): rcrit2[c] = (float)(r_crit^2), centre [c][3] = geometric
- * centre. */
+ * (each optional): rcrit2[c] = (float)(r_crit^2), centre [c][3] = the cell's
+ * centre (geometric after a build; see orc_refit after a refit). */
 void orc_rcrit(const orc_tree *t, float theta, float *rcrit2, double *centre);
 
 /* Opening test of Eq. (1) between group g and cell c, given rcrit2 of the cell.

@@ -30,24 +30,48 @@ def test_refit_at_the_build_positions_changes_nothing():
     assert np.array_equal(r0, r1)
 
 
-def _grown_rcrit2(t, pos, theta):
-    """Eq. (1) radius of every cell with the side grown to its particles' extent,
-    from the exported cells, domain and sorted positions."""
+def _refit_geometry(t, build_pos, pos):
+    """Side and centre of every cell's opening test after a refit to pos, from
+    the exported cells and domain and the build positions: a cell whose particles
+    all keep their key cell (inside the build's bounding box, same integer
+    coordinates at the cell's level) keeps its cube of side L 2^-level about the
+    geometric centre; any other cell takes its particles' tight box (its centre,
+    side max(L 2^-level, largest extent))."""
     c = t.cells()
     perm, _ = t.order()
+    x0 = build_pos[perm]
     x = pos[perm]
-    lo, L, _ = t.domain()
-    l = L * np.ldexp(1.0, -c["level"].astype(np.int64))
-    ext = np.zeros(t.ncells)
+    lo, L, scale = t.domain()
+    hi = build_pos.max(axis=0)
+    lev = c["level"].astype(np.int64)
+    l = L * np.ldexp(1.0, -lev)
+    side = np.zeros(t.ncells)
+    centre = np.zeros((t.ncells, 3))
     for i in range(t.ncells):
-        p = x[c["first"][i]:c["first"][i] + c["count"][i]]
-        ext[i] = (p.max(axis=0) - p.min(axis=0)).max()
-    side = np.maximum(l, ext)
-    _, centre = t.rcrit(theta)
+        s, e = c["first"][i], c["first"][i] + c["count"][i]
+        sh = 20 - lev[i]
+        cell = np.minimum(np.floor((x0[s] - lo) * scale), 2 ** 20 - 1).astype(np.int64) >> sh
+        p = x[s:e]
+        inb = np.all((p >= lo) & (p <= hi))
+        qp = np.minimum(np.floor((p - lo) * scale), 2 ** 20 - 1).astype(np.int64) >> sh
+        if inb and np.all(qp == cell):
+            side[i] = l[i]
+            centre[i] = lo + (cell + 0.5) * l[i]
+        else:
+            ext = (p.max(axis=0) - p.min(axis=0)).max()
+            side[i] = max(l[i], ext)
+            centre[i] = 0.5 * (p.min(axis=0) + p.max(axis=0))
+    return side, centre, l
+
+
+def _grown_rcrit2(t, build_pos, pos, theta):
+    """Eq. (1) radius of every cell after a refit to pos (side and centre from
+    _refit_geometry)."""
+    side, centre, l = _refit_geometry(t, build_pos, pos)
     d = t.moments()["com"] - centre
     delta = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
     r = side / np.float64(np.float32(theta)) + delta
-    return (r * r).astype(np.float32), side, l
+    return (r * r).astype(np.float32), side, l, centre
 
 
 @pytest.mark.parametrize("dt", [1 / 64, 1 / 8])
@@ -56,9 +80,10 @@ def test_refit_grows_the_cell_side_to_the_particles_extent(dt):
     t = oracle.Tree(pos, m)
     new = pos + vel * dt
     t.refit(new)
-    want, side, l = _grown_rcrit2(t, new, 0.7)
-    got, _ = t.rcrit(0.7)
+    want, side, l, centre = _grown_rcrit2(t, pos, new, 0.7)
+    got, got_centre = t.rcrit(0.7)
     assert np.array_equal(got, want)
+    assert np.array_equal(got_centre, centre)
     assert np.any(side > l)            # some cells have spread beyond their cube
     if dt >= 1 / 8:
         # the refitted tree's walk is costlier than a fresh build's (Sect. 5)
@@ -77,7 +102,7 @@ def test_refit_side_of_a_spread_system():
     t = oracle.Tree(pos, m)
     new = pos[0] + 3.0 * (pos - pos[0])
     t.refit(new)
-    _, side, l = _grown_rcrit2(t, new, 0.5)
+    _, side, l, _ = _grown_rcrit2(t, pos, new, 0.5)
     c = t.cells()
     perm, _ = t.order()
     x = pos[perm]
@@ -159,3 +184,124 @@ def test_refit_rejects_non_finite_positions():
         t.refit(bad)
     M0, c0, _ = _moments(t)
     assert np.all(np.isfinite(c0))
+
+
+def _box_dist(x, centre, half):
+    """Distance of each point of x from the box (centre, half sides), float64."""
+    u = np.maximum(np.abs(x - centre) - half.astype(np.float64), 0.0)
+    return np.sqrt((u * u).sum(axis=1))
+
+
+def _drifted_refit(n, seed, dt, mac):
+    pos, vel, m = workloads.plummer(n, seed)
+    t = oracle.Tree(pos, m, mac=mac)
+    new = pos + vel * dt
+    t.refit(new)
+    perm, _ = t.order()
+    return t, new[perm]
+
+
+@pytest.mark.parametrize("dt", [1 / 8, 1 / 2])
+def test_refit_min_distance_accepts_only_cells_whose_particles_are_beyond_the_radius(dt):
+    # Sect. 3.3's alternative test accepts a cell only when its cube lies farther
+    # than l / theta from the group's box; after a refit that guarantee must hold
+    # for the cell's particles themselves, wherever they drifted
+    theta = 0.75
+    t, x = _drifted_refit(3000, 41, dt, mac=1)
+    rmin2, _ = t.rcrit(theta)
+    g = t.groups()
+    c = t.cells()
+    checked = 0
+    for gi in range(t.ngroups):
+        pc, _ = t.group_lists(theta, gi)
+        for ci in pc:
+            p = x[c["first"][ci]:c["first"][ci] + c["count"][ci]]
+            d = _box_dist(p, g["centre"][gi], g["half"][gi]).min()
+            assert d >= np.sqrt(np.float64(rmin2[ci])) * (1 - 1e-6), (gi, ci)
+            checked += 1
+    assert checked > 1000
+
+
+@pytest.mark.parametrize("dt", [1 / 8, 1 / 2])
+def test_refit_eq1_accepted_cells_hold_no_target_of_the_group(dt):
+    # Eq. (1) with theta <= 1: every particle of an accepted cell lies closer to
+    # the cell's centre of mass than the group's box does (the expansion about
+    # the centre of mass converges at every target), also after a refit
+    theta = 0.9
+    t, x = _drifted_refit(3000, 42, dt, mac=0)
+    com = t.moments()["com"]
+    g = t.groups()
+    c = t.cells()
+    checked = 0
+    for gi in range(t.ngroups):
+        pc, _ = t.group_lists(theta, gi)
+        for ci in pc:
+            p = x[c["first"][ci]:c["first"][ci] + c["count"][ci]]
+            reach = np.sqrt(((p - com[ci]) ** 2).sum(axis=1)).max()
+            d = _box_dist(com[ci][None, :], g["centre"][gi], g["half"][gi])[0]
+            assert reach < d * (1 + 1e-6), (gi, ci)
+            checked += 1
+    assert checked > 1000
+
+
+def _spread_leaf(mac):
+    """Two clusters of three particles (a leaf of N_leaf = 3 each at level 1);
+    the refit moves the upper leaf's particles so that their centre of mass stays
+    at the leaf's geometric centre (0.7, 0.7, 0.7) while one of them runs off:
+    (1.1, 1.1, 1.1) and twice (0.5, 0.5, 0.5)."""
+    pos = np.array([[0.1, 0.1, 0.1], [0.2, 0.1, 0.1], [0.1, 0.2, 0.1],
+                    [0.7, 0.7, 0.7], [0.8, 0.8, 0.8], [0.9, 0.9, 0.9]])
+    m = np.full(6, 1.0 / 6)
+    t = oracle.Tree(pos, m, nleaf=3, ncrit=3, mac=mac)
+    c = t.cells()
+    assert t.ncells == 3 and list(c["count"]) == [6, 3, 3]
+    new = pos.copy()
+    new[3] = [1.1, 1.1, 1.1]
+    new[4] = [0.5, 0.5, 0.5]
+    new[5] = [0.5, 0.5, 0.5]
+    t.refit(new)
+    perm, _ = t.order()
+    return t, new[perm], c
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.9, 1.0])
+def test_refit_eq1_radius_holds_every_particle_of_a_spread_leaf(theta):
+    # Eq. (1) with theta <= 1: the sphere of radius r_crit about a cell's centre
+    # of mass holds all of the cell's particles (a box beyond r_crit is beyond
+    # every source).  After the refit above, the cell of side 0.6 centred on its
+    # particles' box (0.8, 0.8, 0.8) gives r_crit = 0.6 / theta + 0.1 sqrt(3)
+    t, x, c = _spread_leaf(mac=0)
+    r2, centre = t.rcrit(theta)
+    com = t.moments()["com"]
+    for ci in range(t.ncells):
+        p = x[c["first"][ci]:c["first"][ci] + c["count"][ci]]
+        reach = np.sqrt(((p - com[ci]) ** 2).sum(axis=1)).max()
+        assert np.sqrt(np.float64(r2[ci])) >= reach * (1 - 1e-6), ci
+    assert np.allclose(centre[2], [0.8, 0.8, 0.8], rtol=0, atol=1e-15)
+    want = 0.6 / np.float64(np.float32(theta)) + np.sqrt(3 * 0.1 ** 2)
+    assert np.sqrt(np.float64(r2[2])) == pytest.approx(want, rel=1e-6)
+
+
+def test_refit_min_distance_cube_holds_every_particle_of_a_spread_leaf():
+    theta = 0.8
+    t, x, c = _spread_leaf(mac=1)
+    rmin2, centre = t.rcrit(theta)
+    for ci in range(t.ncells):
+        p = x[c["first"][ci]:c["first"][ci] + c["count"][ci]]
+        half = 0.5 * np.float64(np.float32(theta)) * np.sqrt(np.float64(rmin2[ci]))
+        assert np.all(np.abs(p - centre[ci]) <= half * (1 + 1e-6)), ci
+    # the lower leaf kept its particles: its geometry is the build's
+    assert np.allclose(centre[1], [0.3, 0.3, 0.3], rtol=0, atol=1e-15)
+
+
+def test_refit_at_the_build_positions_keeps_both_tests_lists():
+    pos, _, m = workloads.plummer(3000, 43)
+    for mac in (0, 1):
+        t = oracle.Tree(pos, m, mac=mac)
+        c0 = t.walk_counts(0.7)
+        r0, g0 = t.rcrit(0.7)
+        t.refit(pos)
+        r1, g1 = t.rcrit(0.7)
+        assert np.array_equal(r0, r1) and np.array_equal(g0, g1)
+        c1 = t.walk_counts(0.7)
+        assert np.array_equal(c0[0], c1[0]) and np.array_equal(c0[1], c1[1])

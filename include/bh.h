@@ -80,6 +80,8 @@ typedef struct {
     int64_t total_npc;      /* sum_npc accumulated over all walks */
     int64_t nclusters;      /* clusters loaded (1 after bh_build_tree) */
     int64_t graph_launches; /* captured steps replayed by bh_batch_run */
+    int64_t graph_captures; /* leapfrog steps captured into a graph (one per buffer parity
+                               and cluster layout) */
 } bh_stats;
 
 /* Host copies of the tree for checking it element by element.  Every pointer is

@@ -75,7 +75,8 @@ class Stats(ctypes.Structure):
                 ("ms_walk_kernel", ctypes.c_double), ("walk_kernel_ms_total", ctypes.c_double),
                 ("walk_kernel_launches", ctypes.c_int64), ("total_npp", ctypes.c_int64),
                 ("total_npc", ctypes.c_int64), ("nclusters", ctypes.c_int64),
-                ("graph_launches", ctypes.c_int64)]
+                ("graph_launches", ctypes.c_int64),
+                ("graph_captures", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -360,15 +361,22 @@ class Context:
     def leapfrog_step(self, dt):
         self._check(self._L.bh_leapfrog_step(self._h, float(dt)))
 
-    def get_state(self):
+    def get_state(self, pos=None, vel=None, acc=None, pot=None):
+        """Positions, velocities, accelerations and potentials in caller order.
+        With no arguments all four are returned in new tensors; otherwise only the
+        given caller-owned tensors are written (the others are skipped)."""
         import torch
-        dev = self._device()
-        pos = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
-        vel = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
-        acc = torch.empty((self.n, 3), dtype=torch.float32, device=dev)
-        pot = torch.empty((self.n,), dtype=torch.float32, device=dev)
-        self._check(self._L.bh_get_state(self._h, _vp(pos.data_ptr()), _vp(vel.data_ptr()),
-                                         _vp(acc.data_ptr()), _vp(pot.data_ptr())))
+        if pos is None and vel is None and acc is None and pot is None:
+            dev = self._device()
+            pos = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+            vel = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+            acc = torch.empty((self.n, 3), dtype=torch.float32, device=dev)
+            pot = torch.empty((self.n,), dtype=torch.float32, device=dev)
+        n = self.n
+        self._check(self._L.bh_get_state(self._h, _dev_ptr(pos, torch.float64, (n, 3), "pos"),
+                                         _dev_ptr(vel, torch.float64, (n, 3), "vel"),
+                                         _dev_ptr(acc, torch.float32, (n, 3), "acc"),
+                                         _dev_ptr(pot, torch.float32, (n,), "pot")))
         return pos, vel, acc, pot
 
     def get_positions(self):

@@ -430,7 +430,7 @@ int update_params(bh_ctx *c, const std::vector<bh_cluster> &cl)
 
 hipError_t rec(bh_ctx *c, int i)
 {
-    if (c->capturing) return hipSuccess;
+    if (c->capturing || !c->ev[0]) return hipSuccess;     // no events: capture, or no-alloc
     return hipEventRecord(c->ev[i], c->stream);
 }
 
@@ -532,9 +532,13 @@ int step_graph(bh_ctx *c)
             c->graph_exec[k] = nullptr;
             return hip_fail(c, e, "capture of the leapfrog step");
         }
+        c->graph_captures += 1;
     }
     TRY_HIP(c, hipGraphLaunch(c->graph_exec[k], c->stream));
+    // the host-side effects of the captured step, which ran only at capture: the
+    // step rebuilds the tree, so the cells are no longer refitted ones
     c->cur = k ^ 1;
+    c->refitted = false;
     c->graph_launches += 1;
     return BH_OK;
 }
@@ -1055,6 +1059,7 @@ int bh_stats_get(bh_ctx *c, bh_stats *out)
     s.total_npc = (int64_t)c->misc_h->tot_npc;
     s.nclusters = c->K;
     s.graph_launches = c->graph_launches;
+    s.graph_captures = c->graph_captures;
     *out = s;
     return st;
 }

@@ -69,7 +69,7 @@ struct DevDomain {
     double lo[3];        // lower corner
     double L;            // cube side
     double scale;        // 2^20 / L
-    double pad[3];
+    double hi[3];        // upper corner: per-axis maximum of the build's positions
 };
 
 // A contiguous piece of one cluster's particles, processed by one block of the
@@ -216,6 +216,7 @@ struct bh_ctx {
     double walk_ms_total = 0.0, walk_ms_last = 0.0;
     int64_t walk_launches = 0;
     int64_t graph_launches = 0;
+    int64_t graph_captures = 0;
 
     // captured leapfrog step, one per parity of the particle ping-pong buffers
     hipStream_t cap_stream = nullptr;        // capture only, never runs work

@@ -204,7 +204,7 @@ domain_kernel(const double *__restrict__ part, const DevCluster *__restrict__ cl
     double side = 0.0;
     for (int k = 0; k < 3; ++k) {
         d.lo[k] = lo[k];
-        d.pad[k] = 0.0;
+        d.hi[k] = hi[k];
         const double e = hi[k] - lo[k];
         if (e > side) side = e;
     }
@@ -214,10 +214,16 @@ domain_kernel(const double *__restrict__ part, const DevCluster *__restrict__ cl
     dom[blockIdx.x] = d;
 }
 
+// Keys of the particles, written in caller order: the pair of the particle at
+// position i goes to slot pid[i] (its caller index; pid == null: the positions
+// are the caller order, a first load) with value i.  The stable sort that
+// follows then orders equal keys by caller index, on a first load and on every
+// rebuild alike (App. A: the split primitive keeps the input order).
 template <typename Src>
 __global__ void __launch_bounds__(kBlock)
 keys_kernel(Src src, const Chunk *__restrict__ chunks, const DevDomain *__restrict__ dom,
-            uint64_t *__restrict__ key, uint32_t *__restrict__ val)
+            const uint32_t *__restrict__ pid, uint32_t n, uint64_t *__restrict__ key,
+            uint32_t *__restrict__ val, DevMisc *m)
 {
     const Chunk ch = chunks[blockIdx.x];
     const DevDomain &cl = dom[ch.cluster];
@@ -228,8 +234,13 @@ keys_kernel(Src src, const Chunk *__restrict__ chunks, const DevDomain *__restri
         const uint32_t qx = coord_to_int(v[0], lx, scale);
         const uint32_t qy = coord_to_int(v[1], ly, scale);
         const uint32_t qz = coord_to_int(v[2], lz, scale);
-        key[i] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
-        val[i] = i;
+        uint32_t o = pid ? pid[i] : i;
+        if (o >= n) {           // caller indices are a permutation of [0, n)
+            atomicOr(&m->nonfinite, 8u);
+            o = i;
+        }
+        key[o] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+        val[o] = i;
     }
 }
 
@@ -253,11 +264,16 @@ reorder_from_caller_kernel(const double *__restrict__ pos, const double *__restr
 __global__ void __launch_bounds__(kBlock)
 reorder_kernel(const double4 *__restrict__ p4i, const double4 *__restrict__ v4i,
                const uint32_t *__restrict__ pidi, const uint32_t *__restrict__ perm, int64_t n,
-               double4 *__restrict__ p4o, double4 *__restrict__ v4o, uint32_t *__restrict__ pido)
+               double4 *__restrict__ p4o, double4 *__restrict__ v4o, uint32_t *__restrict__ pido,
+               DevMisc *m)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const uint32_t s = perm[i];
+    uint32_t s = perm[i];
+    if (s >= (uint64_t)n) {     // only after an internal error (bit 3 already set)
+        atomicOr(&m->nonfinite, 8u);
+        s = (uint32_t)i;
+    }
     p4o[i] = p4i[s];
     v4o[i] = v4i[s];
     pido[i] = pidi[s];
@@ -751,7 +767,8 @@ moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
 }
 
 // Eq. (1): r_crit = l/theta + delta with l = L 2^-level and delta the distance of
-// the centre of mass from the cell's geometric centre; stored as float32 r_crit^2,
+// the centre of mass from the cell's geometric centre (a refitted cell whose
+// particles left it: its tight box's centre and side); stored as float32 r_crit^2,
 // together with the rest of the cell's walk record.  theta, the opening test and
 // the domain are those of the cell's cluster; for the minimum-distance test
 // r_crit = l/theta and the cube (centre, half side) goes to geo.
@@ -784,26 +801,44 @@ rcrit_kernel(DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
         const double gy = cl.lo[1] + ((double)compact3(pre >> 1) + 0.5) * l;
         const double gz = cl.lo[2] + ((double)compact3(pre >> 2) + 0.5) * l;
         const double4 cm = c_com[c];
-        // after a refit the side is the larger of l and the extent of the cell's
-        // particles (box: lo x, y, z, hi x, y, z)
-        double side = l;
+        // After a refit (box: the tight box of the cell's current particles, lo
+        // x, y, z, hi x, y, z) a cell whose particles all still lie in its key
+        // cell keeps this geometry; any other cell takes its box's centre and
+        // side max(l, largest extent), so that the cube of the opening tests
+        // holds every particle of the cell.  The integer map is monotone, so the
+        // particles keep the key cell exactly when the box's two ends do.
+        double side = l, cx = gx, cy = gy, cz = gz;
         if (box) {
             const double2 b0 = box[3 * (int64_t)c], b1 = box[3 * (int64_t)c + 1],
                           b2 = box[3 * (int64_t)c + 2];
-            double ext = 0.0;
-            const double e[3] = {b1.y - b0.x, b2.x - b0.y, b2.y - b1.x};
+            const double blo[3] = {b0.x, b0.y, b1.x}, bhi[3] = {b1.y, b2.x, b2.y};
+            const int sh = kMaxLevel - lev;
+            const uint32_t cell[3] = {compact3(pre), compact3(pre >> 1), compact3(pre >> 2)};
+            bool inside = true;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) ext = e[a] > ext ? e[a] : ext;
-            side = ext > l ? ext : l;
+            for (int a = 0; a < 3; ++a) {
+                inside = inside && blo[a] >= cl.lo[a] && bhi[a] <= cl.hi[a] &&
+                         (coord_to_int(blo[a], cl.lo[a], cl.scale) >> sh) == cell[a] &&
+                         (coord_to_int(bhi[a], cl.lo[a], cl.scale) >> sh) == cell[a];
+            }
+            if (!inside) {
+                double ext = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ext = bhi[a] - blo[a] > ext ? bhi[a] - blo[a] : ext;
+                side = ext > l ? ext : l;
+                cx = 0.5 * (blo[0] + bhi[0]);
+                cy = 0.5 * (blo[1] + bhi[1]);
+                cz = 0.5 * (blo[2] + bhi[2]);
+            }
         }
         double r;
         if (clus[k].mac) {
             // minimum-distance test: the cube (geometric centre, half side) must lie
             // beyond side / theta of the group's box
             r = side / (double)theta;
-            geo[c] = make_double4(gx, gy, gz, 0.5 * side);
+            geo[c] = make_double4(cx, cy, cz, 0.5 * side);
         } else {
-            const double dx = cm.x - gx, dy = cm.y - gy, dz = cm.z - gz;
+            const double dx = cm.x - cx, dy = cm.y - cy, dz = cm.z - cz;
             const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
             r = side / (double)theta + delta;
         }
@@ -861,11 +896,12 @@ hipError_t launch_keys(bh_ctx *c, const double *pos_aos)
 {
     if (pos_aos)
         hipLaunchKernelGGL(keys_kernel<AosSrc>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
-                           c->stream, AosSrc{pos_aos}, c->chunks, c->dom, c->key[0], c->val[0]);
+                           c->stream, AosSrc{pos_aos}, c->chunks, c->dom, nullptr, (uint32_t)c->n,
+                           c->key[0], c->val[0], c->misc);
     else
         hipLaunchKernelGGL(keys_kernel<P4Src>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
-                           c->stream, P4Src{c->p4[c->cur]}, c->chunks, c->dom, c->key[0],
-                           c->val[0]);
+                           c->stream, P4Src{c->p4[c->cur]}, c->chunks, c->dom, c->pid[c->cur],
+                           (uint32_t)c->n, c->key[0], c->val[0], c->misc);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -884,7 +920,8 @@ hipError_t launch_reorder(bh_ctx *c, const uint32_t *perm)
 {
     const int s = c->cur, d = c->cur ^ 1;
     hipLaunchKernelGGL(reorder_kernel, dim3(grid_for(c->n, kBlock)), dim3(kBlock), 0, c->stream,
-                       c->p4[s], c->v4[s], c->pid[s], perm, c->n, c->p4[d], c->v4[d], c->pid[d]);
+                       c->p4[s], c->v4[s], c->pid[s], perm, c->n, c->p4[d], c->v4[d], c->pid[d],
+                       c->misc);
     BH_LAUNCH_CHECK();
     c->cur = d;
     return hipSuccess;

@@ -301,3 +301,31 @@ def test_batch_512_full_size_sampled_clusters():
         compare_walk(d, t, q["theta"])
         compare_forces(a[s], p[s], t, q["theta"], q["eps"])
     ctx.close()
+
+
+def test_replayed_step_after_a_refit_walks_the_rebuilt_tree():
+    # a replayed step rebuilds the tree: a refit before it (a block step that
+    # only refits) must not leave the next force call with the refitted cells'
+    # geometry (the opening radii and counts of the rebuilt tree's own cells)
+    import paper_1106_1900_amd as bh
+    pos, vel, m = workloads.plummer(20_000, 25)
+    theta, eps = 0.6, 0.01
+    ctx = bh.Context()
+    ctx.build_tree(to_dev(pos), to_dev(m))
+    ctx.set_velocities(to_dev(vel))
+    ctx.compute_forces(theta, eps, want=False)
+    ctx.batch_set_params([dict(n=20_000, theta=theta, eps=eps, dt=1 / 64)])
+    ctx.batch_run(2)                         # captures the step of both buffer parities
+    assert ctx.stats().graph_captures == 2
+    st = ctx.block_step(1 / 16, 0.025, 0.01, 2, 1e9)
+    assert st["rebuilt"] == 0                # refitted throughout
+    ctx.batch_run(1)                         # a replay, no new capture
+    assert ctx.stats().graph_captures == 2
+    acc, pot = ctx.compute_forces(theta, eps)
+    x, _ = ctx.get_positions()
+    t = oracle.Tree(x.cpu().numpy(), m)
+    ex = ctx.export_tree()
+    compare_tree(ex, t)
+    compare_walk(ex, t, theta)
+    compare_forces(acc.cpu().numpy(), pot.cpu().numpy(), t, theta, eps)
+    ctx.close()

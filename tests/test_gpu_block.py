@@ -18,9 +18,10 @@ pytestmark = pytest.mark.gpu
 ETA, LENGTH = 0.025, 0.01
 
 
-def _ctx(pos, vel, mass, theta, eps, nleaf=16, ncrit=64):
+def _ctx(pos, vel, mass, theta, eps, nleaf=16, ncrit=64, mac=0):
     import paper_1106_1900_amd as bh
     ctx = bh.Context(nleaf=nleaf, ncrit=ncrit)
+    ctx.set_mac(mac)
     ctx.build_tree(to_dev(pos), to_dev(mass))
     ctx.set_velocities(to_dev(vel))
     ctx.compute_forces(theta, eps, want=False)
@@ -72,13 +73,14 @@ def test_one_level_rebuilding_every_step_is_the_leapfrog():
     b.close()
 
 
-@pytest.mark.parametrize("growth", [0.0, np.float32(0.02), np.float32(1e9)])
-def test_block_steps_follow_the_oracle(growth):
+@pytest.mark.parametrize("growth,mac", [(0.0, 0), (np.float32(0.02), 0), (np.float32(1e9), 0),
+                                        (np.float32(0.02), 1), (np.float32(1e9), 1)])
+def test_block_steps_follow_the_oracle(growth, mac):
     n, theta, eps, B, dt_max = 6000, 0.6, 0.01, 3, 1 / 16
     pos, vel, m = workloads.plummer(n, 73)
-    ctx = _ctx(pos, vel, m, theta, eps)
-    orc = oracle.Block(pos, vel, m, theta, eps)
-    say("case block growth", float(growth))
+    ctx = _ctx(pos, vel, m, theta, eps, mac=mac)
+    orc = oracle.Block(pos, vel, m, theta, eps, mac=mac)
+    say("case block growth", float(growth), "mac", mac)
     for step in range(3):
         bins, _ = ctx.block_bins(dt_max, ETA, LENGTH, B)
         bins = bins.cpu().numpy()

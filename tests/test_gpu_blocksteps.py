@@ -18,15 +18,17 @@ def _drifted(pos, vel, dt):
     return pos + vel * dt          # the same float64 operations as the device drift
 
 
-@pytest.mark.parametrize("dt", [1 / 64, 1 / 8])
-def test_refit_matches_the_oracle_refit(dt):
-    # three drifts, then a refit: moments, boxes, grown cell sides (the opening
-    # radii), counts and forces against the oracle's refit
+@pytest.mark.parametrize("dt,mac", [(1 / 64, 0), (1 / 8, 0), (1 / 8, 1), (1 / 2, 0), (1 / 2, 1)])
+def test_refit_matches_the_oracle_refit(dt, mac):
+    # three drifts, then a refit: moments, boxes, the opening geometry of every
+    # cell (kept where the particles stayed in their key cell, else the tight
+    # box's centre and grown side), counts and forces against the oracle's refit
     import torch
     pos, vel, m = workloads.plummer(30_000, 51)
     theta, eps = 0.6, 0.01
-    say("case refit", pos.shape[0], dt)
+    say("case refit", pos.shape[0], dt, "mac", mac)
     ctx = gpu_build(pos, m, 16, 64)
+    ctx.set_mac(mac)
     ctx.set_velocities(to_dev(vel))
     ctx.compute_forces(theta, eps, want=False)
     for _ in range(3):
@@ -40,7 +42,7 @@ def test_refit_matches_the_oracle_refit(dt):
     acc, pot = ctx.compute_forces(theta, eps)
     torch.cuda.synchronize()
     ex = ctx.export_tree()
-    t = oracle.Tree(pos, m, 16, 64)
+    t = oracle.Tree(pos, m, 16, 64, mac=mac)
     t.refit(x)
     compare_tree(ex, t)           # the build's keys and cells, the refit's moments and boxes
     compare_walk(ex, t, theta)

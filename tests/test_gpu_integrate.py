@@ -44,15 +44,14 @@ def test_leapfrog_steps(n, seed, theta, eps, dt):
         compare_walk(ex, t, theta)
         compare_forces(a1.astype(np.float32), p1.astype(np.float32), t, theta, eps)
         x0, v0, a0 = x1, v1, a1
-    # energy and momentum sums against float64 sums of the state
+    # energy and momentum sums (Eq. (3)) against the oracle's float64 sums of the
+    # same state (another summation order)
     e = ctx.energy()
-    T = 0.5 * np.sum(m * np.sum(v0 * v0, axis=1))
-    W = 0.5 * np.sum(m * p1)
-    P = (m[:, None] * v0).sum(axis=0)
-    assert e[0] == pytest.approx(T, rel=1e-12)
-    assert e[1] == pytest.approx(W, rel=1e-12)
-    assert e[2] == pytest.approx(T + W, rel=1e-12)
-    assert np.allclose(e[3:6], P, rtol=0, atol=1e-15 * np.abs(m[:, None] * v0).sum())
+    eo = oracle.energy(v0, m, p1)
+    assert e[0] == pytest.approx(eo[0], rel=1e-12)
+    assert e[1] == pytest.approx(eo[1], rel=1e-12)
+    assert e[2] == pytest.approx(eo[2], rel=1e-12)
+    assert np.allclose(e[3:6], eo[3:6], rtol=0, atol=1e-15 * np.abs(m[:, None] * v0).sum())
     assert e[6] == 0.0    # first call after the build sets E0
     ctx.close()
 
@@ -170,4 +169,34 @@ def test_memory_budget_is_enforced():
     ctx = bh.Context(hbm_budget_bytes=1 << 30)
     ctx.build_tree(to_dev(pos), to_dev(m))
     assert ctx.stats().device_bytes <= 1 << 30
+    ctx.close()
+
+
+def test_rebuild_orders_equal_keys_by_caller_index():
+    # App. A: the split primitive keeps the input order, so equal keys keep
+    # caller order.  set_state rebuilds from the particles the context holds;
+    # particles moved onto one point (one level-20 key) must come out in caller
+    # order whatever their order in the previous tree
+    n = 6000
+    pos, vel, m = workloads.plummer(n, 12)
+    ctx = gpu_build(pos, m)
+    perm0 = ctx.export_tree()["perm"]
+    rank = np.empty_like(perm0)
+    rank[perm0] = np.arange(n)
+    new = pos.copy()
+    reversed_pairs = 0
+    for a in range(0, n - 1, 2):
+        b = a + 1
+        new[b] = new[a]                      # b joins a on one key
+        reversed_pairs += int(rank[b] < rank[a])
+    new[n - 100:] = new[n - 101]             # a run of 101 coincident particles
+    say("case ties", n, "pairs placed before their partner", reversed_pairs)
+    assert reversed_pairs > 1000
+    ctx.set_state(to_dev(new), to_dev(vel))
+    acc, pot = ctx.compute_forces(0.6, 0.01)
+    ex = ctx.export_tree()
+    t = oracle.Tree(new, m)
+    compare_tree(ex, t)                      # keys, perm (caller order on ties), cells, groups
+    compare_walk(ex, t, 0.6)
+    compare_forces(acc.cpu().numpy(), pot.cpu().numpy(), t, 0.6, 0.01)
     ctx.close()

@@ -11,8 +11,13 @@ before the timed region starts.  Prints one JSON line on stdout.
 The line also carries the batched form ("batch": 512 Plummer clusters of
 1024..65536 particles in one forest, one captured graph per step, against the same
 clusters stepped one context at a time) unless --no-batch is given, and the
-serving loop ("served": a Poisson trace of requests, each a force evaluation plus
-10 leapfrog steps, latency percentiles including queueing) unless --no-serve.
+serving loop ("served": the 2000-request Poisson trace at 200 requests/s, each a
+force evaluation plus 10 leapfrog steps, latency percentiles including queueing;
+"served_constrained": the same under a 4 GiB budget; "served_plain_fifo": the
+same trace served one request at a time through the plain path) unless
+--no-serve, and the 4,194,304-particle galaxy ("galaxy", theta 0.4) unless
+--no-galaxy.  Force errors are measured against float64 direct summation on
+16384 seeded targets.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -210,7 +215,7 @@ def direct_fp64(pos, mass, eps, tgt):
     return out.cpu().numpy()
 
 
-def accuracy_sample(pos, mass, acc_gpu, eps, ntarget=1024):
+def accuracy_sample(pos, mass, acc_gpu, eps, ntarget=16384):
     """Relative acceleration error (Eq. (2)) of the GPU forces against float64
     direct summation on seeded targets."""
     import numpy as np
@@ -369,6 +374,41 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4, alone=True):
     return out
 
 
+_REQUEST_POOLS = {}
+
+
+def request_inputs(count, rate, steps=10, seed=5):
+    """The served trace and its inputs.  Input pools: one Plummer and one Hernquist
+    sphere of 2 nmax particles on the device (kept for every run on the same
+    trace).  A request of n particles takes n consecutive particles of its model
+    at a seeded offset (the draws are independent, so the window is itself a
+    sample of the model) with masses 1/n."""
+    import numpy as np
+    import torch
+
+    import workloads
+    trace = workloads.request_trace(count, rate, seed, steps=steps)
+    nmax = max(q["n"] for q in trace)
+    key = (nmax,)
+    if key not in _REQUEST_POOLS:
+        _REQUEST_POOLS.clear()
+        log("generating request pools of %d particles" % nmax)
+        pools = {}
+        for name, gen in (("plummer", workloads.plummer), ("hernquist", workloads.hernquist)):
+            p, v, _ = gen(2 * nmax, 51 if name == "plummer" else 52)
+            pools[name] = (torch.from_numpy(p).cuda(), torch.from_numpy(v).cuda())
+        _REQUEST_POOLS[key] = pools
+    rng = np.random.default_rng(seed + 1)
+    offsets = [int(rng.integers(0, nmax)) for _ in trace]
+    return trace, _REQUEST_POOLS[key], offsets
+
+
+def trace_workload(count, rate, steps):
+    return ("%d requests, Poisson arrivals at %g/s; Plummer or Hernquist (even odds), "
+            "N log-uniform in [1024, 2097152], theta 0.5 or 0.75, eps 0.01, 1 force "
+            "evaluation + %d leapfrog steps of dt 1/128" % (count, rate, steps))
+
+
 def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256, max_resident=0):
     """The serving loop on a Poisson trace: latency (completion - arrival, with
     queueing) percentiles, offered and served particle-force-evaluation rates."""
@@ -376,20 +416,7 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256, max_res
     import torch
 
     import paper_1106_1900_amd as bh
-    import workloads
-    trace = workloads.request_trace(count, rate, seed, steps=steps)
-    nmax = max(q["n"] for q in trace)
-    # Input pools: one Plummer and one Hernquist sphere of nmax particles on the
-    # device.  A request of n particles takes n consecutive particles of its
-    # model at a seeded offset (the draws are independent, so the window is itself
-    # a sample of the model) with masses 1/n.
-    log("generating request pools of %d particles" % nmax)
-    pools = {}
-    for name, gen in (("plummer", workloads.plummer), ("hernquist", workloads.hernquist)):
-        p, v, _ = gen(2 * nmax, 51 if name == "plummer" else 52)
-        pools[name] = (torch.from_numpy(p).cuda(), torch.from_numpy(v).cuda())
-    rng = np.random.default_rng(seed + 1)
-    offsets = [int(rng.integers(0, nmax)) for _ in trace]
+    trace, pools, offsets = request_inputs(count, rate, steps, seed)
     # requests whose final state is checked against direct summation: four
     # seeded requests below 2^18 particles
     small = [i for i, q in enumerate(trace) if q["n"] < (1 << 18)]
@@ -442,9 +469,7 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256, max_res
                                  kept[i][2].cpu().numpy(), trace[i]["eps"]) for i in sorted(kept)],
                                256, 15)
     return {
-        "workload": "%d requests, Poisson arrivals at %g/s; Plummer or Hernquist (even odds), "
-                    "N log-uniform in [1024, 2097152], theta 0.5 or 0.75, eps 0.01, 1 force "
-                    "evaluation + %d leapfrog steps of dt 1/128" % (count, rate, steps),
+        "workload": trace_workload(count, rate, steps),
         "hbm_budget_bytes": int(budget), "capacity_particles": int(cap),
         "max_resident": int(max_resident),
         "latency_p50_s": st["latency_p50"], "latency_p99_s": st["latency_p99"],
@@ -456,6 +481,66 @@ def bench_serve(count, rate, budget, steps=10, seed=5, max_requests=256, max_res
         "wall_s": t_end, "max_abs_energy_error": max(dE) if dE else None,
         "accuracy_vs_direct": dict(accuracy, what="final accelerations of 4 seeded requests "
                                    "below 2^18 particles at their final positions"),
+    }
+
+
+def bench_fifo(count, rate, steps=10, seed=5):
+    """The plain path on the same trace: one request at a time in arrival order,
+    each through one context (sized once for the largest request): load
+    (bh_build_tree), velocities, one force evaluation, `steps` leapfrog steps and
+    the final positions, accelerations and energy sums copied out (as the server
+    hands back), then the next request.  Latency = completion -
+    arrival with the same arrival times as the served runs."""
+    import numpy as np
+    import torch
+
+    import paper_1106_1900_amd as bh
+    trace, pools, offsets = request_inputs(count, rate, steps, seed)
+    nmax = max(q["n"] for q in trace)
+    ctx = bh.Context(max_n=nmax)
+    out_pos = torch.empty((nmax, 3), dtype=torch.float64, device="cuda")
+    out_acc = torch.empty((nmax, 3), dtype=torch.float32, device="cuda")
+    masses = {}
+    lat, wait = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, q in enumerate(trace):
+        now = time.perf_counter() - t0
+        if now < q["arrival"]:
+            time.sleep(q["arrival"] - now)
+        start = time.perf_counter() - t0
+        n = q["n"]
+        pp, pv = pools[q["shape"]]
+        o = offsets[i]
+        if n not in masses:
+            masses[n] = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+        ctx.build_tree(pp[o:o + n], masses[n])
+        ctx.set_velocities(pv[o:o + n])
+        ctx.compute_forces(q["theta"], q["eps"], want=False)
+        for _ in range(q["steps"]):
+            ctx.leapfrog_step(q["dt"])
+        ctx.get_state(pos=out_pos[:n], acc=out_acc[:n])
+        ctx.energy()                       # reads the step's energy sums (synchronises)
+        done = time.perf_counter() - t0
+        lat.append(done - q["arrival"])
+        wait.append(start - q["arrival"])
+    t_end = time.perf_counter() - t0
+    ctx.close()
+    first_arrival = trace[0]["arrival"]
+    work = sum(q["n"] * (1 + q["steps"]) for q in trace)
+    lat = np.array(lat)
+    wait = np.array(wait)
+    return {
+        "workload": trace_workload(count, rate, steps),
+        "path": "plain: one request at a time in arrival order, one context (bh_build_tree, "
+                "bh_compute_forces, bh_leapfrog_step x %d, bh_get_state)" % steps,
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_max_s": float(lat.max()),
+        "queue_wait_p50_s": float(np.percentile(wait, 50)),
+        "queue_wait_p99_s": float(np.percentile(wait, 99)),
+        "offered_particle_evals_per_s": work / (trace[-1]["arrival"] - first_arrival),
+        "served_particle_evals_per_s": work / (t_end - first_arrival),
+        "completed": count, "wall_s": t_end,
     }
 
 
@@ -519,7 +604,7 @@ def bench_small(reps=20, with_oracle=True):
     return out
 
 
-def bench_galaxy(steps, ntarget=1024, cpu_budget=0.0):
+def bench_galaxy(steps, ntarget=16384, cpu_budget=0.0):
     """The three-component galaxy of 4,194,304 particles at theta 0.4, eps 0.02:
     leapfrog steps of dt 1/128 with the walk kernel timed, and the force error of
     the first evaluation against float64 direct summation on seeded targets."""
@@ -850,8 +935,13 @@ def main():
     ap.add_argument("--batch-clusters", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving loop")
-    ap.add_argument("--serve-requests", type=int, default=400,
-                    help="requests of the served trace (2000: the full 10 s trace)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the served trace (default: the full 10 s trace)")
+    ap.add_argument("--no-fifo", action="store_true",
+                    help="skip the plain one-request-at-a-time leg on the served trace")
+    ap.add_argument("--no-galaxy", action="store_true", help="skip the 4M galaxy workload")
+    ap.add_argument("--targets", type=int, default=16384,
+                    help="seeded targets of the force-error check against direct summation")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-max-resident", type=int, default=1 << 25,
                     help="resident-particle limit of the served run (0: the memory budget only)")
@@ -909,13 +999,15 @@ def main():
                                          growth=growth, blocks=3, workload="galaxy")), flush=True)
         return
     if args.only == "galaxy":
-        print(json.dumps(bench_galaxy(args.steps if args.steps != 100 else 10,
+        print(json.dumps(bench_galaxy(args.steps if args.steps != 100 else 10, ntarget=args.targets,
                                       cpu_budget=args.cpu_budget)), flush=True)
         return
     if args.only == "serve":
         budget = int(args.serve_budget_gib * (1 << 30)) or int(0.6 * torch.cuda.mem_get_info()[0])
         print(json.dumps(bench_serve(args.serve_requests, args.serve_rate, budget,
                                      max_resident=args.serve_max_resident)), flush=True)
+        if not args.no_fifo:
+            print(json.dumps(bench_fifo(args.serve_requests, args.serve_rate)), flush=True)
         return
 
     n = args.n
@@ -1030,8 +1122,16 @@ def main():
         if small > 0:
             log("serving %d requests in %.1f GiB" % (args.serve_requests, args.serve_small_budget_gib))
             out["served_constrained"] = bench_serve(args.serve_requests, args.serve_rate, small)
+        if not args.no_fifo:
+            log("the same %d requests one at a time (plain path)" % args.serve_requests)
+            out["served_plain_fifo"] = bench_fifo(args.serve_requests, args.serve_rate)
+        _REQUEST_POOLS.clear()
+    if not args.no_galaxy:
+        out["galaxy"] = bench_galaxy(10, ntarget=args.targets,
+                                     cpu_budget=min(10.0, args.cpu_budget) if rank == 0 else 0.0)
     if not args.no_accuracy:
-        out["accuracy_vs_direct"] = accuracy_sample(pos, mass, acc0_h, args.eps)
+        log("direct summation on %d targets" % args.targets)
+        out["accuracy_vs_direct"] = accuracy_sample(pos, mass, acc0_h, args.eps, args.targets)
     if args.cpu_budget > 0 and rank == 0:
         log("timing the oracle on the host (%.0f s budget)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(pos, mass, args.theta, args.eps, args.cpu_budget)

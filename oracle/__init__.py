@@ -25,6 +25,7 @@ What each function follows in the paper:
 """
 
 import ctypes
+from concurrent.futures import ThreadPoolExecutor
 import os
 import subprocess
 
@@ -260,27 +261,43 @@ class Tree:
             raise RuntimeError("group_lists failed")
         return pc[:r].copy(), pp[:npl.value].copy()
 
-    def forces(self, theta, eps, groups=None):
-        """float64 tree forces, input order; rows of unselected groups are NaN."""
+    def forces(self, theta, eps, groups=None, threads=1):
+        """float64 tree forces, input order; rows of unselected groups are NaN.
+        threads > 1: the groups are split over that many host threads (the C
+        evaluation reads the tree only and writes the rows of its own groups)."""
         n = self.n
         acc = np.full((n, 3), np.nan)
         pot = np.full(n, np.nan)
         aabs = np.full(n, np.nan)
         pabs = np.full(n, np.nan)
         if groups is None:
-            gp, ng = None, 0
+            garr = np.arange(self.ngroups, dtype=np.int64) if threads > 1 else None
         else:
             garr = np.ascontiguousarray(groups, dtype=np.int64)
-            gp, ng = _ptr(garr), garr.shape[0]
-        st = lib().orc_forces(self._h, float(theta), float(eps), gp, ng, _ptr(acc), _ptr(pot),
-                              _ptr(aabs), _ptr(pabs))
-        if st:
-            raise RuntimeError("oracle forces failed (%d)" % st)
+
+        def run(sel):
+            gp, ng = (None, 0) if sel is None else (_ptr(sel), sel.shape[0])
+            return lib().orc_forces(self._h, float(theta), float(eps), gp, ng, _ptr(acc),
+                                    _ptr(pot), _ptr(aabs), _ptr(pabs))
+
+        if threads <= 1 or garr is None or garr.shape[0] < 2:
+            sts = [run(garr)]
+        else:
+            # round-robin runs of 16 groups: neighbouring groups cost alike
+            runs = [garr[i:i + 16] for i in range(0, garr.shape[0], 16)]
+            parts = [np.ascontiguousarray(np.concatenate(runs[k::threads]))
+                     for k in range(min(threads, len(runs)))]
+            with ThreadPoolExecutor(len(parts)) as ex:
+                sts = list(ex.map(run, parts))
+        for st in sts:
+            if st:
+                raise RuntimeError("oracle forces failed (%d)" % st)
         return acc, pot, aabs, pabs
 
 
-def direct(pos, mass, eps, targets=None):
-    """float64 direct summation on the given targets (all if None)."""
+def direct(pos, mass, eps, targets=None, threads=1):
+    """float64 direct summation on the given targets (all if None); threads > 1
+    splits the targets over that many host threads."""
     pos = _f64(pos)
     mass = _f64(mass)
     n = pos.shape[0]
@@ -288,8 +305,17 @@ def direct(pos, mass, eps, targets=None):
         targets, dtype=np.int64)
     acc = np.zeros((tgt.shape[0], 3))
     pot = np.zeros(tgt.shape[0])
-    lib().orc_direct(_ptr(pos), _ptr(mass), n, float(eps), _ptr(tgt), tgt.shape[0],
-                     _ptr(acc), _ptr(pot))
+
+    def run(k0, k1):
+        lib().orc_direct(_ptr(pos), _ptr(mass), n, float(eps), _ptr(tgt[k0:]), k1 - k0,
+                         _ptr(acc[k0:]), _ptr(pot[k0:]))
+
+    if threads <= 1 or tgt.shape[0] < 2:
+        run(0, tgt.shape[0])
+    else:
+        b = np.linspace(0, tgt.shape[0], min(threads, tgt.shape[0]) + 1).astype(np.int64)
+        with ThreadPoolExecutor(len(b) - 1) as ex:
+            list(ex.map(lambda k: run(int(b[k]), int(b[k + 1])), range(len(b) - 1)))
     return acc, pot
 
 

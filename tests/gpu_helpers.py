@@ -67,9 +67,20 @@ def compare_walk(ex, t, theta):
     assert np.array_equal(ex["npc"], npc), "particle-cell counts differ"
 
 
-def compare_forces(acc, pot, t, theta, eps, groups=None):
+def host_threads():
+    """Host threads for the oracle's evaluations (the cores this process may use,
+    at most 16)."""
+    import os
+    try:
+        k = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        k = os.cpu_count() or 1
+    return max(1, min(16, k))
+
+
+def compare_forces(acc, pot, t, theta, eps, groups=None, threads=1):
     """GPU float32 forces against the float64 oracle on the same lists."""
-    oa, op, aabs, pabs = t.forces(theta, eps, groups)
+    oa, op, aabs, pabs = t.forces(theta, eps, groups, threads=threads)
     sel = ~np.isnan(op)
     acc = acc[sel].astype(np.float64)
     pot = pot[sel].astype(np.float64)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads
-from gpu_helpers import say, to_dev
+from gpu_helpers import compare_forces, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -216,3 +216,43 @@ def test_resident_limit_bounds_the_working_set():
         (x, v, a, p), _ = _alone(q)
         assert np.array_equal(o[0].cpu().numpy(), x) and np.array_equal(o[2].cpu().numpy(), a)
     srv.close()
+
+
+def test_served_hernquist_request_against_the_oracle():
+    # a Hernquist request of 20,000 particles served beside two others: its final
+    # state against the oracle's leapfrog from the same start (float64 forces:
+    # the trajectories agree to the float32 force error), its final accelerations
+    # and potentials against the oracle tree at its final positions, and its
+    # energy sums against the oracle's sums of its final state
+    import oracle
+    n, theta, eps, dt, nsteps = 20_000, 0.75, 0.01, 1 / 128, 10
+    p, v, m = workloads.hernquist(n, 110)
+    reqs = [dict(pos=p, vel=v, mass=m, theta=theta, eps=eps, dt=dt, nsteps=nsteps, nleaf=16,
+                 ncrit=64)]
+    p2, v2, m2 = workloads.plummer(5000, 111)
+    reqs.append(dict(pos=p2, vel=v2, mass=m2, theta=0.5, eps=0.01, dt=dt, nsteps=4, nleaf=8, ncrit=32))
+    p3, v3, m3 = workloads.hernquist(3000, 112)
+    reqs.append(dict(pos=p3, vel=v3, mass=m3, theta=0.6, eps=0.02, dt=dt, nsteps=7, nleaf=16, ncrit=64))
+    say("case served hernquist vs oracle", n)
+    srv, tickets, outs, _ = _serve(reqs, 1 << 30)
+    st = srv.poll(tickets[0])
+    assert st["state"] == 2
+    x, vel, a, pot = [z.cpu().numpy() for z in outs[0]]
+    # the oracle's leapfrog from the same start
+    xo, vo = p.copy(), v.copy()
+    ao, po, _, _ = oracle.Tree(xo, m).forces(theta, eps)
+    for _ in range(nsteps):
+        oracle.kdk_step(xo, vo, m, ao, po, dt, theta, eps)
+    amax = np.abs(ao).max()
+    tol_v = 4e-5 * amax * dt * nsteps
+    say("max |dv|", np.abs(vel - vo).max(), "tolerance", tol_v)
+    assert np.abs(vel - vo).max() <= tol_v
+    assert np.abs(x - xo).max() <= tol_v * dt * nsteps
+    # forces at the final positions
+    t = oracle.Tree(x, m)
+    compare_forces(a, pot, t, theta, eps)
+    # energy sums of the final state
+    eo = oracle.energy(vel, m, pot.astype(np.float64))
+    for k in range(3):
+        assert st["energy"][k] == pytest.approx(eo[k], rel=1e-12), k
+    assert np.allclose(st["energy"][3:6], eo[3:6], rtol=0, atol=1e-15 * np.abs(m[:, None] * vel).sum())

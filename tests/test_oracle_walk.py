@@ -191,3 +191,23 @@ def test_mac_is_strict():
         assert d2.dtype == np.float32 and d2 > 0
         assert not t.mac_accept(gi, c, d2)
         assert t.mac_accept(gi, c, np.nextafter(d2, np.float32(0)))
+
+
+def test_threaded_evaluation_equals_the_serial_one():
+    # the thread split only partitions the groups (targets): every row is the
+    # same computation, bit for bit
+    pos, _, m = workloads.plummer(6000, 91)
+    t = oracle.Tree(pos, m)
+    one = t.forces(0.6, 0.01)
+    many = t.forces(0.6, 0.01, threads=5)
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b)
+    sel = np.arange(3, t.ngroups, 7)
+    one = t.forces(0.6, 0.01, sel)
+    many = t.forces(0.6, 0.01, sel, threads=3)
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b, equal_nan=True)
+    tgt = np.arange(0, 6000, 11)
+    d1 = oracle.direct(pos, m, 0.01, tgt)
+    d4 = oracle.direct(pos, m, 0.01, tgt, threads=4)
+    assert np.array_equal(d1[0], d4[0]) and np.array_equal(d1[1], d4[1])

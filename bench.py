@@ -320,6 +320,11 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4, alone=True):
     ctx.batch_run(steps)
     torch.cuda.synchronize()
     t_tuned = (time.perf_counter() - t0) / steps
+    ctx.batch_forces(want=False)
+    torch.cuda.synchronize()
+    swt = ctx.stats()
+    tuned_flops = FLOPS_PP * swt.sum_npp + FLOPS_PC * swt.sum_npc
+    tuned_tflops = tuned_flops / (swt.ms_walk_kernel * 1e-3) / 1e12 if swt.ms_walk_kernel > 0 else 0.0
     ctx.close()
 
     out = {
@@ -334,6 +339,10 @@ def bench_batch(k, steps, warmup, dt=1.0 / 128, seed=4, alone=True):
         "walk": {"ms_per_launch": sw.ms_walk_kernel, "interactions": {"pp": sw.sum_npp,
                                                                      "pc": sw.sum_npc},
                  "tflops": walk_tflops, "frac_of_157_3": walk_tflops / PEAK_FP32_VECTOR_TFLOPS},
+        "tuned_walk": {"ms_per_launch": swt.ms_walk_kernel,
+                       "interactions": {"pp": swt.sum_npp, "pc": swt.sum_npc},
+                       "tflops": tuned_tflops,
+                       "frac_of_157_3": tuned_tflops / PEAK_FP32_VECTOR_TFLOPS},
         "tuned_value": ntot / t_tuned,
         "tuned_ms_per_step": 1e3 * t_tuned,
         "autotune_seconds": t_tune,
@@ -656,34 +665,41 @@ def bench_galaxy(steps, ntarget=16384, cpu_budget=0.0):
     return out
 
 
-def bench_sweep():
-    """Accuracy and cost against theta at N = 2^15, 2^17, 2^20 (Plummer, eps 1/64):
-    Δa/a against float64 direct summation on 256 seeded targets, interactions per
-    particle, walk time; and one force evaluation (build + walk) against N."""
+SWEEP_FULL = dict(ns=(1 << 15, 1 << 17, 1 << 20), thetas=(0.2, 0.3, 0.4, 0.5, 0.6, 0.75, 0.8),
+                  exps=tuple(range(15, 25)), ntarget=256)
+SWEEP_COMPACT = dict(ns=(1 << 15, 1 << 17), thetas=(0.4, 0.5, 0.6, 0.75), exps=(15, 17, 19, 21, 23),
+                     ntarget=1024)
+
+
+def bench_sweep(ns, thetas, exps, ntarget):
+    """Accuracy and cost against theta at the sizes ns (Plummer, eps 1/64): Δa/a
+    against float64 direct summation on ntarget seeded targets, interactions per
+    particle, walk time; and one force evaluation (build + walk) against N = 2^e
+    for e in exps."""
     import numpy as np
     import torch
 
     import paper_1106_1900_amd as bh
     import workloads
     rows = []
-    for n in (1 << 15, 1 << 17, 1 << 20):
+    for n in ns:
         pos, _, mass = workloads.plummer(n, 2)
         dp, dm = torch.from_numpy(pos).cuda(), torch.from_numpy(mass).cuda()
         ctx = bh.Context()
         ctx.build_tree(dp, dm)
-        for theta in (0.2, 0.3, 0.4, 0.5, 0.6, 0.75, 0.8):
+        for theta in thetas:
             ctx.compute_forces(theta, 1 / 64, want=False)
             acc, _ = ctx.compute_forces(theta, 1 / 64)
             torch.cuda.synchronize()
             st = ctx.stats()
-            a = pooled_accuracy([(pos, mass, acc.cpu().numpy(), 1 / 64)], 256, 17)
+            a = pooled_accuracy([(pos, mass, acc.cpu().numpy(), 1 / 64)], ntarget, 17)
             rows.append({"n": n, "theta": theta, "median": a["median"], "p99": a["p99"],
                          "pp_per_particle": st.sum_npp / n, "pc_per_particle": st.sum_npc / n,
                          "walk_ms": st.ms_walk_kernel})
             log(rows[-1])
         ctx.close()
     scaling = []
-    for e in range(15, 25):
+    for e in exps:
         n = 1 << e
         pos, _, mass = workloads.plummer(n, 2)
         ctx = bh.Context()
@@ -705,7 +721,11 @@ def bench_sweep():
                         "walk_ms": st.ms_walk_kernel})
         log(scaling[-1])
         ctx.close()
-    return {"accuracy_vs_theta": rows, "scaling_theta_0_75": scaling}
+    return {"workload": "Plummer seed 2, eps 1/64; accuracy at N in %s, theta in %s (%d seeded "
+                        "targets vs float64 direct summation); one force evaluation (rebuild + "
+                        "walk, dt = 0 step) at theta 0.75 for N = 2^e, e in %s"
+                        % (list(ns), list(thetas), ntarget, list(exps)),
+            "accuracy_vs_theta": rows, "scaling_theta_0_75": scaling}
 
 
 def bench_active(n=1 << 20, theta=0.75, eps=1.0 / 64, reps=5):
@@ -940,6 +960,8 @@ def main():
     ap.add_argument("--no-fifo", action="store_true",
                     help="skip the plain one-request-at-a-time leg on the served trace")
     ap.add_argument("--no-galaxy", action="store_true", help="skip the 4M galaxy workload")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the compact accuracy / scaling sweep (--only sweep: the full one)")
     ap.add_argument("--targets", type=int, default=16384,
                     help="seeded targets of the force-error check against direct summation")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -984,7 +1006,7 @@ def main():
         print(json.dumps(bench_active()), flush=True)
         return
     if args.only == "sweep":
-        print(json.dumps(bench_sweep()), flush=True)
+        print(json.dumps(bench_sweep(**SWEEP_FULL)), flush=True)
         return
     if args.only == "mac":
         print(json.dumps(bench_mac()), flush=True)
@@ -1126,6 +1148,9 @@ def main():
             log("the same %d requests one at a time (plain path)" % args.serve_requests)
             out["served_plain_fifo"] = bench_fifo(args.serve_requests, args.serve_rate)
         _REQUEST_POOLS.clear()
+    if not args.no_sweep:
+        log("compact accuracy and scaling sweep")
+        out["sweep"] = bench_sweep(**SWEEP_COMPACT)
     if not args.no_galaxy:
         out["galaxy"] = bench_galaxy(10, ntarget=args.targets,
                                      cpu_budget=min(10.0, args.cpu_budget) if rank == 0 else 0.0)

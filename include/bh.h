@@ -40,8 +40,9 @@ extern "C" {
 typedef struct bh_ctx bh_ctx;
 
 /* Tunables.  nleaf: most particles a leaf may hold (Sect. 2.1, 16 in the paper);
- * ncrit: most particles in a walk group (Sect. 2.2, 64 in the paper; at most 64
- * here, one wavefront per group); max_n: particles to reserve room for up front
+ * ncrit: most particles in a walk group (Sect. 2.2, 64 in the paper; 1..128
+ * here: one wavefront per group, a lane carrying up to two of its particles);
+ * nleaf is 1..64; max_n: particles to reserve room for up front
  * (0: grow on demand); hbm_budget_bytes: cap on the device memory the context
  * may hold (0: no cap); max_clusters: clusters of a batch to reserve room for
  * (0: grow on demand). */
@@ -297,7 +298,7 @@ typedef struct {
                            cluster's positions and velocities as they are while its
                            forces are evaluated) */
     int32_t nleaf;      /* 1..64; 0: the context's nleaf */
-    int32_t ncrit;      /* 1..64; 0: the context's ncrit */
+    int32_t ncrit;      /* 1..128; 0: the context's ncrit */
     int32_t mac;        /* opening test: BH_MAC_EQ1 or BH_MAC_MIN_DIST */
     int32_t pad;        /* zero */
 } bh_cluster;
@@ -350,7 +351,7 @@ typedef struct {
 
 /* Times one leapfrog step of dt = 0 (rebuild and forces, no motion) of the loaded
  * batch's clusters, class by class in a private context, for every nleaf in
- * {8, 16, 32} and ncrit in {16, 32, 64}, reps steps each, and keeps the fastest
+ * {8, 16, 32} and ncrit in {32, 64, 128}, reps steps each, and keeps the fastest
  * pair per class in the context (replacing an earlier table).  out: host
  * [cap] entries (may be NULL); *count: classes found.  Synchronous.  The loaded
  * batch is not changed. */
@@ -396,7 +397,7 @@ typedef struct {
     double dt;                  /* leapfrog step, finite */
     int32_t nsteps;             /* steps after the force evaluation, >= 0 */
     int32_t nleaf;              /* 1..64, or 0: the server's */
-    int32_t ncrit;              /* 1..64, or 0: the server's */
+    int32_t ncrit;              /* 1..128, or 0: the server's */
     int32_t mac;                /* opening test: BH_MAC_EQ1 or BH_MAC_MIN_DIST */
     double arrival;             /* arrival time on the server clock (seconds, see
                                    bh_server_now); a negative value: the time of

@@ -85,6 +85,7 @@ void free_buffers(bh_ctx *c)
     dfree(c->scan_tmp);
     dfree(c->c_first);
     dfree(c->c_count);
+    dfree(c->c_end);
     dfree(c->c_child);
     dfree(c->c_nchild);
     dfree(c->c_parent);
@@ -176,6 +177,7 @@ hipError_t each_buffer(bh_ctx *c, const Sizes &z, F f)
     B(c->scan_tmp, z.scan);
     B(c->c_first, z.cells);
     B(c->c_count, z.cells);
+    B(c->c_end, z.cells);
     B(c->c_child, z.cells);
     B(c->c_nchild, z.cells);
     B(c->c_parent, z.cells);
@@ -331,8 +333,8 @@ int check_clusters(bh_ctx *c, const bh_cluster *cl, int64_t K, std::vector<bh_cl
             if (q.ncrit == 0) q.ncrit = t ? t->ncrit : c->p.ncrit;
         }
         if (q.n < 1) return fail(c, BH_EINVAL, "every cluster needs n >= 1");
-        if (q.nleaf < 1 || q.nleaf > 64 || q.ncrit < 1 || q.ncrit > 64)
-            return fail(c, BH_EINVAL, "cluster nleaf and ncrit must be in 1..64");
+        if (q.nleaf < 1 || q.nleaf > 64 || q.ncrit < 1 || q.ncrit > kMaxGroup)
+            return fail(c, BH_EINVAL, "cluster nleaf must be in 1..64 and ncrit in 1..128");
         if (bad_theta(q.theta)) return fail(c, BH_EINVAL, "cluster theta must be in (0, 1]");
         if (bad_eps(q.eps)) return fail(c, BH_EINVAL, "cluster eps must be finite and >= 0");
         if (!std::isfinite(q.dt)) return fail(c, BH_EINVAL, "cluster dt must be finite");
@@ -794,7 +796,7 @@ int bh_create(bh_ctx **out, const bh_params *p, void *hip_stream)
     bh_params q;
     bh_default_params(&q);
     if (p) q = *p;
-    if (q.nleaf < 1 || q.nleaf > 64 || q.ncrit < 1 || q.ncrit > 64 || q.max_n < 0 ||
+    if (q.nleaf < 1 || q.nleaf > 64 || q.ncrit < 1 || q.ncrit > kMaxGroup || q.max_n < 0 ||
         q.hbm_budget_bytes < 0 || q.max_clusters < 0 || q.max_n > 0x7fffffffLL)
         return BH_EINVAL;
     bh_ctx *c = new (std::nothrow) bh_ctx();

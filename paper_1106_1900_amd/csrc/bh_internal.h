@@ -29,8 +29,10 @@ constexpr int kRadix = 1 << kRadixBits;
 // Tree-level tiling: one block of 256 threads handles 256 particles.
 constexpr int kTreeTile = 256;
 
-// Walk: one group per wavefront, 4 wavefronts per block.
+// Walk: one group per wavefront, 4 wavefronts per block.  A group holds at most
+// kMaxGroup particles: a lane carries up to two (or three) of them.
 constexpr int kWalkWaves = 4;
+constexpr int kMaxGroup = 128;
 constexpr int kStackCap = 1408;        // >= 21 levels x 64 ranges (see walk.hip)
 
 // Per-cell record read by the walk: everything the opening test and a
@@ -175,6 +177,7 @@ struct bh_ctx {
     // ---- cells (level-major, key order within a level) ----
     uint32_t *c_first = nullptr, *c_count = nullptr, *c_child = nullptr, *c_nchild = nullptr;
     uint32_t *c_parent = nullptr;
+    uint32_t *c_end = nullptr;               // one past a cell's last particle (build only)
     uint8_t *c_level = nullptr, *c_leaf = nullptr;
     double4 *c_com = nullptr;                // centre of mass, mass (float64)
     double *c_S = nullptr;                   // [c][6] float64 second moment

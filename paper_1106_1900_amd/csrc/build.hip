@@ -350,7 +350,7 @@ split_leaf_kernel(const uint64_t *__restrict__ key, const uint32_t *__restrict__
         lm = best > kMaxLevel ? (uint8_t)kMaxLevel : best;
         split[i] = sp;
         lam[i] = lm;
-        gflag[i] = 0;       // group starts are flagged later by cell_ends_kernel
+        gflag[i] = 0;       // group starts are flagged later by cell_finish_kernel
     }
     // count starts per level
     const int l = t % kWave;
@@ -396,27 +396,32 @@ __device__ void level_finalize(const uint32_t *__restrict__ tot, DevMisc *m, int
 
 // one block per level (and one for the leaf row): exclusive scan of the row's
 // block counts in place; the last block to finish derives the level offsets
-__global__ void scan_levels_kernel(uint32_t *__restrict__ blk, int nblk, uint32_t *__restrict__ tot,
-                                   DevMisc *m, int64_t cap_c)
+constexpr int kScanLevelsBlock = 1024;
+
+__global__ void __launch_bounds__(kScanLevelsBlock)
+scan_levels_kernel(uint32_t *__restrict__ blk, int nblk, uint32_t *__restrict__ tot, DevMisc *m,
+                   int64_t cap_c)
 {
-    __shared__ uint32_t s_tmp[4];
+    constexpr int kWaves = kScanLevelsBlock / kWave;
+    __shared__ uint32_t s_tmp[kWaves];
     uint32_t *row = blk + (int64_t)blockIdx.x * nblk;
     uint32_t run = 0;
     const int t = threadIdx.x, w = t / kWave, l = t % kWave;
-    for (int b0 = 0; b0 < nblk; b0 += 256) {
+    for (int b0 = 0; b0 < nblk; b0 += kScanLevelsBlock) {
         int b = b0 + t;
         uint32_t v = b < nblk ? row[b] : 0u;
         uint32_t inc = wave_incl_scan_add(v);
         if (l == kWave - 1) s_tmp[w] = inc;
         __syncthreads();
-        uint32_t off = 0, tot4 = 0;
-        for (int k = 0; k < 4; ++k) {
-            if (k < w) off += s_tmp[k];
-            tot4 += s_tmp[k];
+        uint32_t off = 0, totw = 0;
+        for (int k = 0; k < kWaves; ++k) {
+            const uint32_t x = s_tmp[k];
+            if (k < w) off += x;
+            totw += x;
         }
         __syncthreads();
         if (b < nblk) row[b] = run + off + inc - v;
-        run += tot4;
+        run += totw;
     }
     if (t == 0) {
         __hip_atomic_store(&tot[blockIdx.x], run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -460,85 +465,91 @@ __device__ __forceinline__ void level_ranks(bool valid, uint8_t sp, uint8_t lm,
     }
 }
 
+// Every cell a particle starts: its first particle, level, leaf flag, parent and
+// first child.  The last particle of a cell (the next particle starts a cell at
+// the same or a shallower level, or lies beyond the cluster) writes the cell's
+// end; the last particle of a node also writes one past the node's last child
+// (the child holding that particle).  Counts follow as end - first.
 __global__ void __launch_bounds__(kTreeTile)
 emit_cells_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__ lam, int64_t n,
                   const uint32_t *__restrict__ blk_scanned, int nblk, const DevMisc *__restrict__ m,
                   uint32_t *__restrict__ c_first, uint8_t *__restrict__ c_level,
                   uint8_t *__restrict__ c_leaf, uint32_t *__restrict__ c_parent,
-                  uint32_t *__restrict__ c_child, uint32_t *__restrict__ c_nchild)
+                  uint32_t *__restrict__ c_child, uint32_t *__restrict__ c_end,
+                  uint32_t *__restrict__ c_cend)
 {
     __shared__ uint32_t s_wc[kTreeTile / kWave][kLevels];
     const int64_t i = (int64_t)blockIdx.x * kTreeTile + threadIdx.x;
     const bool valid = i < n;
     const uint8_t sp = valid ? split[i] : (uint8_t)255;
     const uint8_t lm = valid ? lam[i] : (uint8_t)0;
+    // split of the next particle: 0 past the end (and at a cluster's first particle)
+    const uint8_t sn = (valid && i + 1 < n) ? split[i + 1] : (uint8_t)0;
     Ranks r;
     level_ranks(valid, sp, lm, blk_scanned, nblk, m, s_wc, r);
-    if (!valid || sp > lm || m->ncells == 0) return;
-#pragma unroll
-    for (int lev = 0; lev < kLevels; ++lev) {
-        if (lev < sp || lev > lm) continue;
-        const uint32_t c = r.anc[lev];
-        if (c >= m->ncells) continue;
-        c_first[c] = (uint32_t)i;
-        c_level[c] = (uint8_t)lev;
-        c_leaf[c] = (uint8_t)(lev == lm);
-        c_parent[c] = lev > 0 ? r.anc[lev > 0 ? lev - 1 : 0] : kNone;
-        c_child[c] = lev < lm ? r.anc[lev < kMaxLevel ? lev + 1 : kMaxLevel] : kNone;
-        c_nchild[c] = 0;
-    }
-}
-
-// Cell ends (hence counts), numbers of children, and group starts.
-__global__ void __launch_bounds__(kTreeTile)
-cell_ends_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__ lam, int64_t n,
-                 const uint32_t *__restrict__ pcl, const DevCluster *__restrict__ clus,
-                 const uint32_t *__restrict__ blk_scanned, int nblk,
-                 const DevMisc *__restrict__ m, const uint32_t *__restrict__ c_first,
-                 const uint32_t *__restrict__ c_parent, const uint32_t *__restrict__ c_child,
-                 uint32_t *__restrict__ c_count, uint32_t *__restrict__ c_nchild,
-                 uint8_t *__restrict__ gflag)
-{
-    __shared__ uint32_t s_wc[kTreeTile / kWave][kLevels];
-    const int64_t i = (int64_t)blockIdx.x * kTreeTile + threadIdx.x;
-    const bool valid = i < n;
-    const uint8_t sp = valid ? split[i] : (uint8_t)255;
-    const uint8_t lm = valid ? lam[i] : (uint8_t)0;
-    Ranks r;
-    level_ranks(valid, sp, lm, blk_scanned, nblk, m, s_wc, r);
-    if (!valid || sp > lm || m->ncells == 0) return;
-    const uint32_t ncrit = clus[pcl[i]].ncrit;
-    uint32_t e = (uint32_t)n;            // running end: min over shallower levels
-    uint32_t prev_count = 0;             // count of the level above (the parent)
-    bool grouped = false;
+    const uint32_t ncells = m->ncells;
+    if (!valid || ncells == 0) return;
 #pragma unroll
     for (int lev = 0; lev < kLevels; ++lev) {
         if (lev > lm) continue;
-        const uint32_t a = r.anc[lev];
-        const uint32_t lend = m->level_offset[lev] + m->level_count[lev];
-        if (a >= lend) break;
-        const uint32_t nxt = (a + 1u < lend) ? c_first[a + 1u] : (uint32_t)n;
-        e = nxt < e ? nxt : e;
-        const uint32_t first = (lev >= sp) ? (uint32_t)i : c_first[a];
-        const uint32_t cnt = e - first;
+        const uint32_t c = r.anc[lev];
+        if (c >= ncells) continue;
         if (lev >= sp) {
-            c_count[a] = cnt;
-            if (lev > 0) {
-                const uint32_t p = r.anc[lev > 0 ? lev - 1 : 0];
-                const bool last = (a + 1u >= lend) || (c_parent[a + 1u] != p);
-                if (last) c_nchild[p] = a - c_child[p] + 1u;
-            }
-            // group: at most ncrit particles and the parent holds more (or root)
-            if (!grouped && cnt <= ncrit && (lev == 0 || prev_count > ncrit)) {
-                gflag[i] = 1;
-                grouped = true;
-            }
-            // a leaf still larger than ncrit is cut into runs of ncrit particles
-            if (lev == lm && cnt > ncrit) {
-                for (uint32_t o = 0; o < cnt; o += ncrit) gflag[i + o] = 1;
+            c_first[c] = (uint32_t)i;
+            c_level[c] = (uint8_t)lev;
+            c_leaf[c] = (uint8_t)(lev == lm);
+            c_parent[c] = lev > 0 ? r.anc[lev > 0 ? lev - 1 : 0] : kNone;
+            c_child[c] = lev < lm ? r.anc[lev < kMaxLevel ? lev + 1 : kMaxLevel] : kNone;
+        }
+        if (lev >= sn) {
+            // particle i is the last of its level-lev cell
+            c_end[c] = (uint32_t)(i + 1);
+            if (lev < lm) {
+                const uint32_t last = r.anc[lev < kMaxLevel ? lev + 1 : kMaxLevel];
+                c_cend[c] = last + 1u;
             }
         }
-        prev_count = cnt;
+    }
+}
+
+// Per cell: count = end - first, children = one past the last child - first
+// child (0 for a leaf), and the group starts (Sect. 2.2): a cell of at most
+// ncrit particles whose parent holds more (or the root) starts a group at its
+// first particle; a leaf still larger than ncrit is cut into runs of ncrit
+// particles.  Reads the ends of a cell's parent, never its converted fields.
+__global__ void __launch_bounds__(kBlock)
+cell_finish_kernel(DevMisc *__restrict__ m, const uint32_t *__restrict__ pcl,
+                   const DevCluster *__restrict__ clus, const uint32_t *__restrict__ c_first,
+                   const uint32_t *__restrict__ c_end, const uint8_t *__restrict__ c_leaf,
+                   const uint8_t *__restrict__ c_level, const uint32_t *__restrict__ c_parent,
+                   const uint32_t *__restrict__ c_child, uint32_t *__restrict__ c_count,
+                   uint32_t *__restrict__ c_nchild, uint8_t *__restrict__ gflag, int64_t n)
+{
+    const uint32_t ncells = m->ncells;
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < ncells; c += gridDim.x * kBlock) {
+        const uint32_t f = c_first[c];
+        uint32_t e = c_end[c];
+        const bool leaf = c_leaf[c] != 0;
+        const uint32_t nc = leaf ? 0u : c_nchild[c] - c_child[c];
+        // never for a consistent tree; keeps every later access in bounds
+        if (f >= (uint64_t)n || e <= f || e > (uint64_t)n || (!leaf && (nc < 1u || nc > 8u))) {
+            c_count[c] = 0;
+            c_nchild[c] = 0;
+            atomicOr(&m->nonfinite, 8u);
+            continue;
+        }
+        const uint32_t cnt = e - f;
+        c_count[c] = cnt;
+        c_nchild[c] = nc;
+        const uint32_t ncrit = clus[pcl[f]].ncrit;
+        bool top = c_level[c] == 0;
+        if (!top) {
+            const uint32_t p = c_parent[c];
+            top = p < ncells && c_end[p] - c_first[p] > ncrit;
+        }
+        if (cnt <= ncrit && top) gflag[f] = 1;
+        if (leaf && cnt > ncrit)
+            for (uint32_t o = 0; o < cnt; o += ncrit) gflag[f + o] = 1;
     }
 }
 
@@ -717,6 +728,78 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
     store_walk_multipole(c, S, q0, q1);
 }
 
+// Moments of node c from its n <= 8 children [s, s + n) (one level deeper,
+// already done), with the same operations in the same order as cell_moments:
+// every child's centre of mass, second moment (and box) is loaded up front in
+// one batch, so a node costs one round of dependent loads after its own record.
+template <bool kBox>
+__device__ __forceinline__ void node_moments(uint32_t c, uint32_t s, uint32_t n,
+                                             double4 *__restrict__ c_com, double *__restrict__ c_S,
+                                             float4 *__restrict__ q0, float4 *__restrict__ q1,
+                                             double2 *__restrict__ box)
+{
+    if (n < 1u || n > 8u) return;      // a node has 1..8 children (checked when the tree is built)
+    double4 q[8];
+    double2 Sk[8][3];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t j = s + min((uint32_t)k, n - 1u);
+        q[k] = c_com[j];
+        const double2 *p = reinterpret_cast<const double2 *>(c_S + 6 * (int64_t)j);
+        Sk[k][0] = p[0];
+        Sk[k][1] = p[1];
+        Sk[k][2] = p[2];
+    }
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if ((uint32_t)k < n) M = M + q[k].w;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if ((uint32_t)k < n) {
+            sx = sx + q[k].w * q[k].x;
+            sy = sy + q[k].w * q[k].y;
+            sz = sz + q[k].w * q[k].z;
+        }
+    }
+    const double cx = sx / M, cy = sy / M, cz = sz / M;
+    double S[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if ((uint32_t)k < n) {
+            const double ex = q[k].x - cx, ey = q[k].y - cy, ez = q[k].z - cz;
+            const double w = q[k].w;
+            S[0] += Sk[k][0].x + w * ex * ex; S[1] += Sk[k][0].y + w * ey * ey;
+            S[2] += Sk[k][1].x + w * ez * ez; S[3] += Sk[k][1].y + w * ex * ey;
+            S[4] += Sk[k][2].x + w * ex * ez; S[5] += Sk[k][2].y + w * ey * ez;
+        }
+    }
+    c_com[c] = make_double4(cx, cy, cz, M);
+    if (kBox) {
+        // the union of the children's boxes (refits only: a second round of
+        // loads keeps the registers of the common path free)
+        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            // lo x, y; lo z, hi x; hi y, z (repeated members change no min or max)
+            const double2 *bp = box + 3 * (int64_t)(s + min((uint32_t)k, n - 1u));
+            const double2 b0 = bp[0], b1 = bp[1], b2 = bp[2];
+            blo[0] = fmin(blo[0], b0.x); blo[1] = fmin(blo[1], b0.y);
+            blo[2] = fmin(blo[2], b1.x); bhi[0] = fmax(bhi[0], b1.y);
+            bhi[1] = fmax(bhi[1], b2.x); bhi[2] = fmax(bhi[2], b2.y);
+        }
+        double2 *b = box + 3 * (int64_t)c;
+        b[0] = make_double2(blo[0], blo[1]);
+        b[1] = make_double2(blo[2], bhi[0]);
+        b[2] = make_double2(bhi[1], bhi[2]);
+    }
+    double2 *out = reinterpret_cast<double2 *>(c_S + 6 * (int64_t)c);
+    out[0] = make_double2(S[0], S[1]);
+    out[1] = make_double2(S[2], S[3]);
+    out[2] = make_double2(S[4], S[5]);
+    store_walk_multipole(c, S, q0, q1);
+}
+
 // kLeaves: every leaf of the tree (any level); otherwise the nodes of one level.
 // kBox: also the cells' tight boxes (refits).
 template <bool kLeaves, bool kBox>
@@ -733,9 +816,15 @@ moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restri
     for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < count; t += gridDim.x * kBlock) {
         const uint32_t c = begin + t;
         const bool leaf = c_leaf[c] != 0;
-        if (leaf != kLeaves) continue;
-        cell_moments<kLeaves, kBox>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S, q0,
-                                    q1, box);
+        if (kLeaves) {
+            if (leaf)
+                cell_moments<true, kBox>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S,
+                                         q0, q1, box);
+        } else {
+            // the node's own record, loaded with its leaf flag in one round
+            const uint32_t ch = c_child[c], nc = c_nchild[c];
+            if (!leaf) node_moments<kBox>(c, ch, nc, c_com, c_S, q0, q1, box);
+        }
     }
 }
 
@@ -758,9 +847,8 @@ moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
         const uint32_t count = m->level_count[level];
         for (uint32_t t = threadIdx.x; t < count; t += kLevelsBlock) {
             const uint32_t c = begin + t;
-            if (c_leaf[c] == 0)
-                cell_moments<false, kBox>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S,
-                                          q0, q1, box);
+            const uint32_t ch = c_child[c], nc = c_nchild[c];
+            if (c_leaf[c] == 0) node_moments<kBox>(c, ch, nc, c_com, c_S, q0, q1, box);
         }
         __syncthreads();
     }
@@ -938,16 +1026,19 @@ hipError_t launch_tree(bh_ctx *c)
     hipLaunchKernelGGL(split_leaf_kernel, dim3(nblk), dim3(kTreeTile), lds, c->stream, c->key[0],
                        c->pcl, n, H, c->clus, c->split, c->lam, c->gflag, blk, nblk, c->misc);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(scan_levels_kernel, dim3(kLevels + 1), dim3(256), 0, c->stream, blk, nblk, tot,
+    hipLaunchKernelGGL(scan_levels_kernel, dim3(kLevels + 1), dim3(kScanLevelsBlock), 0, c->stream,
+                       blk, nblk, tot,
                        c->misc, c->cap_c);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(emit_cells_kernel, dim3(nblk), dim3(kTreeTile), 0, c->stream, c->split,
                        c->lam, n, blk, nblk, c->misc, c->c_first, c->c_level, c->c_leaf,
-                       c->c_parent, c->c_child, c->c_nchild);
+                       c->c_parent, c->c_child, c->c_end, c->c_nchild);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(cell_ends_kernel, dim3(nblk), dim3(kTreeTile), 0, c->stream, c->split,
-                       c->lam, n, c->pcl, c->clus, blk, nblk, c->misc, c->c_first, c->c_parent,
-                       c->c_child, c->c_count, c->c_nchild, c->gflag);
+    int g = grid_for(c->cap_c, kBlock);
+    if (g > kFixedGrid) g = kFixedGrid;
+    hipLaunchKernelGGL(cell_finish_kernel, dim3(g), dim3(kBlock), 0, c->stream, c->misc, c->pcl,
+                       c->clus, c->c_first, c->c_end, c->c_leaf, c->c_level, c->c_parent,
+                       c->c_child, c->c_count, c->c_nchild, c->gflag, n);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -317,7 +317,7 @@ int bh_server_create(bh_server **out, const bh_server_params *p, void *hip_strea
     if (!out || !p) return BH_EINVAL;
     *out = nullptr;
     if (p->hbm_budget_bytes <= 0 || p->max_requests < 1 || p->max_requests > (1 << 20) ||
-        p->nleaf < 1 || p->nleaf > 64 || p->ncrit < 1 || p->ncrit > 64 || p->min_nleaf < 0 ||
+        p->nleaf < 1 || p->nleaf > 64 || p->ncrit < 1 || p->ncrit > kMaxGroup || p->min_nleaf < 0 ||
         p->min_nleaf > p->nleaf || p->max_resident < 0)
         return BH_EINVAL;
     bh_server *s = new (std::nothrow) bh_server();

@@ -15,7 +15,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int32_t kLeafSizes[] = {8, 16, 32};
-constexpr int32_t kGroupSizes[] = {16, 32, 64};
+constexpr int32_t kGroupSizes[] = {32, 64, 128};
 
 // positions and masses of the loaded batch in the caller's order
 __global__ void __launch_bounds__(kBlock)
@@ -171,7 +171,7 @@ int bh_set_tuning(bh_ctx *c, const bh_tune_entry *entries, int64_t count)
     if (count < 0 || (count > 0 && !entries)) return ctx_fail(c, BH_EINVAL, "bad tuning table");
     for (int64_t i = 0; i < count; ++i) {
         const bh_tune_entry &t = entries[i];
-        if (t.nleaf < 1 || t.nleaf > 64 || t.ncrit < 1 || t.ncrit > 64 || !(t.theta > 0.0f) ||
+        if (t.nleaf < 1 || t.nleaf > 64 || t.ncrit < 1 || t.ncrit > kMaxGroup || !(t.theta > 0.0f) ||
             t.log2n < 0 || t.log2n > 31)
             return ctx_fail(c, BH_EINVAL, "tuning entry out of range");
     }

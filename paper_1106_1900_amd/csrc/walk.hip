@@ -55,12 +55,17 @@ constexpr int kPpCap = 128;
 constexpr int kLdsStack = 128;
 constexpr int kSpillPerWave = kStackCap - kLdsStack;
 // Lane (p, s) reads tile entries s + t k for t < ceil(cnt / k): at most 83 past
-// the tile's first entry for k = floor(64 / g); the tail is padding.
+// the tile's first entry for cnt <= 64 and k = floor(64 / g); the tail is padding.
 constexpr int kTileReach = 84;
-// The cell list holds fewer than 64 entries between evaluations plus at most 64
-// from one pop; a tile of its last 64 entries is read up to kTileReach past its
-// start.
-constexpr int kPcCap = 63 + kTileReach + 1;
+// Cell tiles: with BH_WALK_FLEX_TILE a full tile holds k ceil(64 / k) cells (at
+// most 84, for k = 21), so that every lane's trips read real cells; otherwise 64
+// cells and padding.  The cell list holds fewer than a full tile between
+// evaluations plus at most 64 from one pop (< 148 entries); the last, partial
+// tile of fewer than 84 cells is read up to 83 + 20 past its start.
+#ifndef BH_WALK_FLEX_TILE
+#define BH_WALK_FLEX_TILE 0
+#endif
+constexpr int kPcCap = 148;
 constexpr float kFar = 1.0e30f;
 #ifndef BH_WALK_UNROLL
 #define BH_WALK_UNROLL 4
@@ -110,12 +115,24 @@ struct WaveLds {
 };
 static_assert(4 * sizeof(WaveLds) * 4 <= 160 * 1024, "four blocks of four wavefronts per CU");
 
-// Running sums of the M particles a lane carries, with their compensations.
+// Running sums of the M particles a lane carries, with their compensations, and
+// the plain float32 partial sums of the tiles evaluated since the last
+// compensated addition (trips: terms per partial so far, the same in every lane).
 template <int M>
 struct Acc {
     float ax[M], ay[M], az[M], ph[M];
     float cx[M], cy[M], cz[M], cp[M];
+    float px[M], py[M], pz[M], pp[M];
+    int trips;
 };
+
+// A partial is added to the compensated totals before it could hold more than
+// this many plain float32 terms (64: the terms of one tile with one lane per
+// particle).  BH_WALK_COMP_EVERY_TILE: after every tile instead.
+#ifndef BH_WALK_COMP_EVERY_TILE
+#define BH_WALK_COMP_EVERY_TILE 1
+#endif
+constexpr int kPlainTerms = 64;
 
 // s + t with the rounding error of the addition carried in c (two-sum).
 __device__ __forceinline__ void comp_add(float &s, float &c, float t)
@@ -264,6 +281,7 @@ template <int M>
 struct Target {
     float ox[M], oy[M], oz[M];
     int sub, k;
+    int tmax;    // trips of the largest tile (cells or particles)
 };
 
 // sources per loop trip: fewer when the lane carries more particles (registers)
@@ -273,17 +291,28 @@ struct Target {
 template <int M>
 constexpr int unroll_for() { return M == 1 ? kUnroll : (M == 2 ? BH_WALK_UNROLL2 : 1); }
 
+// the partials into the compensated totals (two-sum), partials cleared
 template <int M>
-__device__ __forceinline__ void acc_tile(Acc<M> &acc, const float *ax, const float *ay,
-                                         const float *az, const float *ph)
+__device__ __forceinline__ void acc_flush(Acc<M> &acc)
 {
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        comp_add(acc.ax[m], acc.cx[m], ax[m]);
-        comp_add(acc.ay[m], acc.cy[m], ay[m]);
-        comp_add(acc.az[m], acc.cz[m], az[m]);
-        comp_add(acc.ph[m], acc.cp[m], ph[m]);
+        comp_add(acc.ax[m], acc.cx[m], acc.px[m]);
+        comp_add(acc.ay[m], acc.cy[m], acc.py[m]);
+        comp_add(acc.az[m], acc.cz[m], acc.pz[m]);
+        comp_add(acc.ph[m], acc.cp[m], acc.pp[m]);
+        acc.px[m] = acc.py[m] = acc.pz[m] = acc.pp[m] = 0.f;
     }
+    acc.trips = 0;
+}
+
+// after a tile of T trips: flush when the next tile (at most tmax trips) could
+// take a partial past kPlainTerms terms
+template <int M>
+__device__ __forceinline__ void acc_tile_done(Acc<M> &acc, int T, int tmax)
+{
+    acc.trips += T;
+    if (BH_WALK_COMP_EVERY_TILE || acc.trips + tmax > kPlainTerms) acc_flush<M>(acc);
 }
 
 template <bool kEps0, int M>
@@ -291,9 +320,7 @@ __device__ __forceinline__ void run_pc(const WaveLds &L, int base, int cnt, cons
                                        float eps2, Acc<M> &acc)
 {
     constexpr int U = unroll_for<M>();
-    float ax[M], ay[M], az[M], ph[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) ax[m] = ay[m] = az[m] = ph[m] = 0.f;
+    float *ax = acc.px, *ay = acc.py, *az = acc.pz, *ph = acc.pp;
     const int k = t.k;
     const int T = uniform((cnt + k - 1) / k);
     int j = base + t.sub;
@@ -321,7 +348,6 @@ __device__ __forceinline__ void run_pc(const WaveLds &L, int base, int cnt, cons
             pc_term<kEps0>(A, B, C, t.ox[m], t.oy[m], t.oz[m], eps2, ax[m], ay[m], az[m], ph[m]);
         j += k;
     }
-    acc_tile<M>(acc, ax, ay, az, ph);
 }
 
 template <bool kEps0, int M>
@@ -329,9 +355,7 @@ __device__ __forceinline__ void run_pp(const WaveLds &L, int cnt, const Target<M
                                        Acc<M> &acc)
 {
     constexpr int U = unroll_for<M>();
-    float ax[M], ay[M], az[M], ph[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) ax[m] = ay[m] = az[m] = ph[m] = 0.f;
+    float *ax = acc.px, *ay = acc.py, *az = acc.pz, *ph = acc.pp;
     const int k = t.k;
     const int T = uniform((cnt + k - 1) / k);
     int j = t.sub;
@@ -354,7 +378,6 @@ __device__ __forceinline__ void run_pp(const WaveLds &L, int cnt, const Target<M
             pp_term<kEps0>(S, t.ox[m], t.oy[m], t.oz[m], eps2, ax[m], ay[m], az[m], ph[m]);
         j += k;
     }
-    acc_tile<M>(acc, ax, ay, az, ph);
 }
 
 // evaluate cnt <= 64 cells of the staged cell list from entry base: the entries
@@ -364,13 +387,16 @@ __device__ __forceinline__ void eval_pc(WaveLds &L, int base, int cnt, const Tar
                                         float eps2, Acc<M> &acc)
 {
     const int lane = lane_id();
-    for (int i = base + cnt + lane; i < base + kTileReach; i += kWave) {
+    // the lanes read entries up to k ceil(cnt / k) past base
+    const int reach = t.k * uniform((cnt + t.k - 1) / t.k);
+    for (int i = base + cnt + lane; i < base + reach; i += kWave) {
         L.ca[i] = make_float4(kFar, kFar, kFar, 0.0f);
         L.cb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         L.cc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     wave_sync();
     if (t.sub < t.k) run_pc<kEps0, M>(L, base, cnt, t, eps2, acc);
+    acc_tile_done<M>(acc, reach / t.k, t.tmax);
     wave_sync();
 }
 
@@ -389,6 +415,7 @@ __device__ __forceinline__ void eval_pp(const WalkArgs &a, WaveLds &L, uint32_t 
     }
     wave_sync();
     if (t.sub < t.k) run_pp<kEps0, M>(L, cnt, t, eps2, acc);
+    acc_tile_done<M>(acc, uniform((cnt + t.k - 1) / t.k), t.tmax);
     wave_sync();
 }
 
@@ -425,6 +452,7 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
         mi[m] = 0.f;
         acc.ax[m] = acc.ay[m] = acc.az[m] = acc.ph[m] = 0.f;
         acc.cx[m] = acc.cy[m] = acc.cz[m] = acc.cp[m] = 0.f;
+        acc.px[m] = acc.py[m] = acc.pz[m] = acc.pp[m] = 0.f;
         const int q = p + m * P;
         if (t.sub < t.k && q < gn) {
             const double4 x = a.p4[gs + q];
@@ -435,6 +463,10 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
         }
     }
 
+    // cells per full tile (uniform); trips of the largest tile
+    const int tsz = BH_WALK_FLEX_TILE ? t.k * ((kWave + t.k - 1) / t.k) : kWave;
+    t.tmax = (tsz + t.k - 1) / t.k;
+    acc.trips = 0;
     int top = 1;
     if (lane == 0) stack.set(0, cid, 1u);  // the cluster's root
     wave_sync();
@@ -521,10 +553,10 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
             top += nn;
         }
         stack.sync();
-        if (pc_n >= kWave) {     // pc_n < 128: one tile of the last 64 entries
+        if (pc_n >= tsz) {       // pc_n < tsz + 64: one tile of the last tsz entries
             __builtin_amdgcn_s_setprio(0);
-            eval_pc<kEps0, M>(L, pc_n - kWave, kWave, t, eps2, acc);
-            pc_n -= kWave;
+            eval_pc<kEps0, M>(L, pc_n - tsz, tsz, t, eps2, acc);
+            pc_n -= tsz;
         }
         while (pend >= (uint32_t)kWave) {
             uint32_t idx;
@@ -553,6 +585,7 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
         pend -= (uint32_t)n < pend ? (uint32_t)n : pend;
     }
 
+    if (acc.trips > 0) acc_flush<M>(acc);
     // add the k partial sums of each particle: halving steps over the sub-lane
     // index, in a fixed order
     float ax[M], ay[M], az[M], ph[M];
@@ -603,17 +636,21 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
 
 // Particles per lane for a group of g: the M in {1, .., kMaxPerLane} with the
 // fewest loop trips per 64-source tile, M ceil(64 / floor(64 / ceil(g / M)));
-// ties go to the smaller M.
+// ties go to the smaller M.  M must leave at most 64 particle slots (groups of
+// up to 128 particles need M >= 2).
 #ifndef BH_WALK_MAX_PER_LANE
 #define BH_WALK_MAX_PER_LANE 2
 #endif
 constexpr int kMaxPerLane = BH_WALK_MAX_PER_LANE;
+static_assert(kMaxPerLane >= 2 && kMaxPerLane * kWave >= kMaxGroup,
+              "a group of kMaxGroup particles must fit one wavefront");
 
 __device__ __forceinline__ int lanes_mode(int g)
 {
-    int best = 1, cost = 1 << 30;
+    int best = kMaxPerLane, cost = 1 << 30;
     for (int m = 1; m <= kMaxPerLane; ++m) {
         const int P = (g + m - 1) / m;
+        if (P > kWave) continue;
         const int k = kWave / P;
         const int c = m * ((kWave + k - 1) / k);
         if (c < cost) {

@@ -84,7 +84,7 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch):
 def test_create_validates_before_touching_the_device():
     import torch
     lib = bh.load_library()
-    for field, value in (("nleaf", 0), ("nleaf", 65), ("ncrit", 0), ("ncrit", 65), ("max_n", -1),
+    for field, value in (("nleaf", 0), ("nleaf", 65), ("ncrit", 0), ("ncrit", 129), ("max_n", -1),
                          ("hbm_budget_bytes", -1), ("max_clusters", -1)):
         p = binding.Params()
         lib.bh_default_params(ctypes.byref(p))

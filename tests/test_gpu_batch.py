@@ -30,6 +30,11 @@ def _mixed_batch():
                   dict(theta=0.7, eps=0.01, nleaf=16, ncrit=64)))
     p, v, m = workloads.plummer(9000, 24)
     parts.append((p, v, m, dict(theta=0.4, eps=0.0, nleaf=16, ncrit=64)))
+    # groups of up to 128 particles (the batched configuration's largest size)
+    p, v, m = workloads.plummer(6000, 25)
+    parts.append((p, v, m, dict(theta=0.75, eps=0.01, nleaf=32, ncrit=128)))
+    p, v, m = workloads.clustered(4000, 26)
+    parts.append((p, v, m, dict(theta=0.5, eps=0.005, nleaf=8, ncrit=128)))
     return parts
 
 

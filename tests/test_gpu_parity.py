@@ -72,10 +72,18 @@ def test_structured_inputs(name, n, seed, theta, eps):
     _full_check(pos, m, theta, eps, label=name)
 
 
-@pytest.mark.parametrize("nleaf,ncrit", [(8, 32), (32, 64), (1, 1), (16, 16), (4, 64)])
+@pytest.mark.parametrize("nleaf,ncrit", [(8, 32), (32, 64), (1, 1), (16, 16), (4, 64),
+                                         # groups of 65..128 particles: two per lane
+                                         (16, 128), (32, 128), (64, 100), (8, 65)])
 def test_leaf_and_group_sizes(nleaf, ncrit):
     pos, _, m = workloads.plummer(8_191, 5)
     _full_check(pos, m, 0.6, 0.02, nleaf, ncrit, label="sizes")
+
+
+def test_large_leaf_cut_into_groups_of_128():
+    # 1000 coincident particles: one level-20 leaf cut into runs of 128
+    pos, _, m = workloads.coincident(1_000)
+    _full_check(pos, m, 0.5, 0.01, 16, 128, label="coincident-128")
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 16, 17, 64, 65, 257])

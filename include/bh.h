@@ -477,6 +477,33 @@ const char *bh_server_last_error(bh_server *srv);
 /* Message for the last non-zero status of this context (never NULL). */
 const char *bh_last_error(bh_ctx *ctx);
 
+/* ---- without device allocation ----
+ * For callers that cannot allocate device memory: code under HIP graph capture
+ * that must not call hipMalloc, tight serving loops, harnesses that forbid
+ * allocation.  bh_forces_static does what bh_build_tree followed by
+ * bh_compute_forces does on a fresh context (nleaf 16, ncrit 64, opening test
+ * of Eq. (1)), with identical results, but every intermediate buffer lives in
+ * one file-scope device array of the library (40 MiB per GPU, reserved when the
+ * library is loaded and held until the process ends); it calls no allocation
+ * routine.  The caller owns the inputs and outputs:
+ *   pos: device [n][3] float64, mass: device [n] float64 (> 0), caller order;
+ *   acc: device [n][3] float32, pot: device [n] float32, caller order (either
+ *   may be NULL, not both); 1 <= n <= BH_STATIC_MAX_N; theta in (0, 1]; eps >= 0;
+ *   hip_stream: the stream the work is enqueued on (NULL: the null stream).
+ * Synchronous: returns after the stream has drained, so device-side errors
+ * (non-finite coordinates, bad masses) are reported by the call itself.
+ * BH_EINVAL for bad arguments, including n above BH_STATIC_MAX_N; BH_ENOMEM or
+ * BH_EDEVICE on failure; bh_forces_static_error() gives the calling thread's
+ * last message.  Every call on one GPU uses that GPU's array and keeps nothing
+ * between calls that the next call reads; calls that overlap on one GPU (from
+ * two host threads, or on two streams in flight at once) race. */
+#define BH_STATIC_MAX_N 32768
+int bh_forces_static(const double *pos, const double *mass, int64_t n, float theta, float eps,
+                     float *acc, float *pot, void *hip_stream);
+
+/* Message of the calling thread's last bh_forces_static failure (never NULL). */
+const char *bh_forces_static_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,8 @@ from .binding import (  # noqa: F401
     library_path,
     load_library,
     declared_functions,
+    forces_static,
+    STATIC_MAX_N,
 )
 
-__all__ = ["MAC_EQ1", "MAC_MIN_DIST", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "REQ_FAILED", "BHError", "Cluster", "Context", "Server", "Stats", "library_path", "load_library", "declared_functions"]
+__all__ = ["MAC_EQ1", "MAC_MIN_DIST", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "REQ_FAILED", "BHError", "Cluster", "Context", "Server", "Stats", "library_path", "load_library", "declared_functions", "forces_static", "STATIC_MAX_N"]

@@ -144,6 +144,8 @@ def load_library():
                               ctypes.POINTER(i64)]),
         "bh_set_tuning": (i32, [_vp, ctypes.POINTER(TuneEntry), i64]),
         "bh_last_error": (ctypes.c_char_p, [_vp]),
+        "bh_forces_static": (i32, [_vp, _vp, i64, f32, f32, _vp, _vp, _vp]),
+        "bh_forces_static_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -166,6 +168,33 @@ def _dev_ptr(t, dtype, shape=None, name="tensor"):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError("%s must have shape %s, got %s" % (name, shape, tuple(t.shape)))
     return _vp(t.data_ptr())
+
+
+STATIC_MAX_N = 32768     # BH_STATIC_MAX_N
+
+
+def forces_static(pos, mass, theta, eps, acc=None, pot=None, stream=None):
+    """bh_forces_static: build and walk of one particle set (n <= STATIC_MAX_N)
+    without any device allocation by the library.  pos (n, 3) and mass (n,) are
+    float64 device tensors; acc (n, 3) and pot (n,) float32 device tensors are
+    allocated here (by torch) unless given.  Synchronous.  Returns (acc, pot)."""
+    import torch
+    L = load_library()
+    n = int(mass.shape[0])
+    p = _dev_ptr(pos, torch.float64, (n, 3), "pos")
+    m = _dev_ptr(mass, torch.float64, (n,), "mass")
+    if acc is None:
+        acc = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+    if pot is None:
+        pot = torch.empty((n,), dtype=torch.float32, device=pos.device)
+    a = _dev_ptr(acc, torch.float32, (n, 3), "acc")
+    q = _dev_ptr(pot, torch.float32, (n,), "pot")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = L.bh_forces_static(p, m, n, float(theta), float(eps), a, q, _vp(stream.cuda_stream))
+    if st:
+        raise BHError(st, L.bh_forces_static_error().decode())
+    return acc, pot
 
 
 class Context:

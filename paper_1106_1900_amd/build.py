@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbh.so")
 SOURCES = ["sort.hip", "build.hip", "walk.hip", "integrate.hip", "api.hip", "serve.hip", "tune.hip",
-           "block.hip"]
+           "block.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 HIPFLAGS = [

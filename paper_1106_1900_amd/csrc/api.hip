@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "bh_internal.h"
@@ -711,6 +712,54 @@ hipError_t ctx_enqueue_refit(bh_ctx *c)
 }
 
 hipError_t ctx_enqueue_forces(bh_ctx *c) { return enqueue_forces(c, nullptr, nullptr); }
+
+// Points every device buffer of c (and its misc block) into [base, base + bytes)
+// for n particles of one cluster with leaf size >= nleaf_min and a walk grid of
+// spill_waves wavefronts, each buffer on a 256-byte boundary.  Returns the bytes
+// the layout needs; with base == null (or too few bytes) nothing is assigned.
+int64_t ctx_carve(bh_ctx *c, int64_t n, int nleaf_min, int64_t spill_waves, char *base,
+                  int64_t bytes)
+{
+    Sizes z = sizes_for(c, n, 1, nleaf_min);
+    z.spill_waves = spill_waves;
+    auto round = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    int64_t need = round((int64_t)sizeof(DevMisc));
+    bh_ctx tmp;
+    (void)each_buffer(&tmp, z, [&](auto **, size_t sz, int64_t cnt) {
+        need += round((int64_t)sz * std::max<int64_t>(cnt, 1));
+        return hipSuccess;
+    });
+    if (!base || need > bytes) return need;
+    int64_t off = 0;
+    c->misc = reinterpret_cast<DevMisc *>(base);
+    off += round((int64_t)sizeof(DevMisc));
+    (void)each_buffer(c, z, [&](auto **pp, size_t sz, int64_t cnt) {
+        using T = std::remove_reference_t<decltype(**pp)>;
+        *pp = reinterpret_cast<T *>(base + off);
+        off += round((int64_t)sz * std::max<int64_t>(cnt, 1));
+        return hipSuccess;
+    });
+    c->cap_n = z.n;
+    c->cap_k = z.K;
+    c->cap_chunks = z.chunks;
+    c->cap_c = z.cells;
+    c->walk_spill_waves = z.spill_waves;
+    c->bytes = need;
+    return need;
+}
+
+// Build from caller arrays (the sequence of bh_build_tree, enqueued only: the
+// table, chunk and misc set-up is the caller's), and the walk with the outputs
+// scattered to caller order (that of bh_compute_forces).
+hipError_t ctx_enqueue_load(bh_ctx *c, const double *pos, const double *mass)
+{
+    return enqueue_load(c, pos, mass, nullptr);
+}
+
+hipError_t ctx_enqueue_forces_out(bh_ctx *c, float *acc, float *pot)
+{
+    return enqueue_forces(c, acc, pot);
+}
 
 }  // namespace bh
 

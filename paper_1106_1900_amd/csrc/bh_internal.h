@@ -280,6 +280,11 @@ int ctx_log2_floor(int64_t n);
 hipError_t ctx_enqueue_rebuild(bh_ctx *c);   // keys .. moments from the held particles
 hipError_t ctx_enqueue_refit(bh_ctx *c);     // group boxes and moments of the existing cells
 hipError_t ctx_enqueue_forces(bh_ctx *c);    // opening radii and the full walk
+// buffers of a one-cluster context carved from caller-provided device memory
+int64_t ctx_carve(bh_ctx *c, int64_t n, int nleaf_min, int64_t spill_waves, char *base,
+                  int64_t bytes);
+hipError_t ctx_enqueue_load(bh_ctx *c, const double *pos, const double *mass);
+hipError_t ctx_enqueue_forces_out(bh_ctx *c, float *acc, float *pot);
 
 // block.hip
 

@@ -228,19 +228,35 @@ keys_kernel(Src src, const Chunk *__restrict__ chunks, const DevDomain *__restri
     const Chunk ch = chunks[blockIdx.x];
     const DevDomain &cl = dom[ch.cluster];
     const double lx = cl.lo[0], ly = cl.lo[1], lz = cl.lo[2], scale = cl.scale;
-    for (uint32_t i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) {
-        double v[3];
-        src.get3(i, v);
-        const uint32_t qx = coord_to_int(v[0], lx, scale);
-        const uint32_t qy = coord_to_int(v[1], ly, scale);
-        const uint32_t qz = coord_to_int(v[2], lz, scale);
-        uint32_t o = pid ? pid[i] : i;
-        if (o >= n) {           // caller indices are a permutation of [0, n)
-            atomicOr(&m->nonfinite, 8u);
-            o = i;
+    // kKeyBatch elements per thread at a time: all their loads are issued before
+    // the scattered stores, which the compiler may not move loads across
+    constexpr int kKeyBatch = 8;
+    for (uint32_t i0 = ch.begin + threadIdx.x; i0 < ch.end; i0 += kKeyBatch * kBlock) {
+        double v[kKeyBatch][3];
+        uint32_t o[kKeyBatch];
+#pragma unroll
+        for (int u = 0; u < kKeyBatch; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * kBlock;
+            if (i < ch.end) {
+                src.get3(i, v[u]);
+                o[u] = pid ? pid[i] : i;
+            }
         }
-        key[o] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
-        val[o] = i;
+#pragma unroll
+        for (int u = 0; u < kKeyBatch; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * kBlock;
+            if (i >= ch.end) continue;
+            const uint32_t qx = coord_to_int(v[u][0], lx, scale);
+            const uint32_t qy = coord_to_int(v[u][1], ly, scale);
+            const uint32_t qz = coord_to_int(v[u][2], lz, scale);
+            uint32_t dst = o[u];
+            if (dst >= n) {     // caller indices are a permutation of [0, n)
+                atomicOr(&m->nonfinite, 8u);
+                dst = i;
+            }
+            key[dst] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+            val[dst] = i;
+        }
     }
 }
 

@@ -1,19 +1,21 @@
 // walk.hip - the group walk and force evaluation (Sect. 2.2, 3.3).
 //
-// One wavefront (64 lanes) takes one group of at most 64 particles.  It walks
+// One wavefront (64 lanes) takes one group of at most 128 particles.  It walks
 // the tree from the root: up to 64 cells are tested at a time, one per lane,
 // with the cluster's opening test (Eq. (1), or the minimum distance between the
 // group's box and the cell's cube, the alternative of Sect. 3.3; both in float32
 // on offsets from the group centre).  An accepted cell goes to the cell list, an
 // opened leaf to the particle list, an opened node pushes its contiguous
-// children.  As soon as a list holds 64 entries it is evaluated: the 64 sources
+// children.  As soon as a list holds a full tile it is evaluated: the sources
 // are staged in LDS as float32 offsets from the group's box centre and every
-// lane accumulates them on its particle.  A group of g particles uses
-// k = floor(64 / g) lanes per particle (the paper uses up to 4 threads per
-// particle); lane (p, s) takes sources s, s + k, s + 2k, ... of each tile and
-// the k partial sums are added at the end.  Groups of 22-25 and 33-48 particles
-// would leave many lanes idle that way; there a lane carries two particles of
-// the group (k = floor(64 / ceil(g / 2))) and evaluates each source on both.
+// lane accumulates them on its particles.  A lane carries M particles of the
+// group (M = 1, 2 or 3, whichever needs the fewest loop trips per tile; groups
+// of more than 64 particles need M >= 2): P = ceil(g / M) particle slots,
+// k = floor(64 / P) lanes per slot (the paper uses up to 4 threads per
+// particle).  Lane (p, s) takes sources s, s + k, s + 2k, ... of each tile and
+// the k partial sums are added at the end.  A full tile of cells holds
+// k ceil(64 / k) entries, so that no lane runs a padded trip; a tile of
+// particles holds 64.
 //
 // Per wavefront, in LDS:
 //   stack : pending cell ranges (first cell, count <= 8) packed in 32 bits, used
@@ -33,9 +35,11 @@
 //           pending between evaluations, so < 128 ranges).
 //   tile  : 64 staged particles plus padding.
 //
-// Every pair goes through float32 arithmetic on group-centred offsets; each tile
-// is summed in plain float32 and the tile sums are added to the particle's
-// totals with an error-free two-sum (compensated accumulation).
+// Every pair goes through float32 arithmetic on group-centred offsets; a lane's
+// terms are summed in plain float32 over at most 64 terms (one tile with one
+// lane per particle, several smaller tiles otherwise), and these partial sums are
+// added to the particle's totals with an error-free two-sum (compensated
+// accumulation).
 //
 // Groups are handed out in Morton order (a wavefront's first group is its own
 // index, the rest come from one device-wide counter), so at any
@@ -63,7 +67,7 @@ constexpr int kTileReach = 84;
 // evaluations plus at most 64 from one pop (< 148 entries); the last, partial
 // tile of fewer than 84 cells is read up to 83 + 20 past its start.
 #ifndef BH_WALK_FLEX_TILE
-#define BH_WALK_FLEX_TILE 0
+#define BH_WALK_FLEX_TILE 1
 #endif
 constexpr int kPcCap = 148;
 constexpr float kFar = 1.0e30f;
@@ -130,7 +134,7 @@ struct Acc {
 // this many plain float32 terms (64: the terms of one tile with one lane per
 // particle).  BH_WALK_COMP_EVERY_TILE: after every tile instead.
 #ifndef BH_WALK_COMP_EVERY_TILE
-#define BH_WALK_COMP_EVERY_TILE 1
+#define BH_WALK_COMP_EVERY_TILE 0
 #endif
 constexpr int kPlainTerms = 64;
 
@@ -639,7 +643,7 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
 // ties go to the smaller M.  M must leave at most 64 particle slots (groups of
 // up to 128 particles need M >= 2).
 #ifndef BH_WALK_MAX_PER_LANE
-#define BH_WALK_MAX_PER_LANE 2
+#define BH_WALK_MAX_PER_LANE 3
 #endif
 constexpr int kMaxPerLane = BH_WALK_MAX_PER_LANE;
 static_assert(kMaxPerLane >= 2 && kMaxPerLane * kWave >= kMaxGroup,

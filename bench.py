@@ -15,8 +15,9 @@ serving loop ("served": the 2000-request Poisson trace at 200 requests/s, each a
 force evaluation plus 10 leapfrog steps, latency percentiles including queueing;
 "served_constrained": the same under a 4 GiB budget; "served_plain_fifo": the
 same trace served one request at a time through the plain path) unless
---no-serve, and the 4,194,304-particle galaxy ("galaxy", theta 0.4) unless
---no-galaxy.  Force errors are measured against float64 direct summation on
+--no-serve, the 4,194,304-particle galaxy ("galaxy", theta 0.4) unless
+--no-galaxy, and the energy error of the two-galaxy encounter over its first 125
+time units at theta 0.75 and 0.5 ("merger") unless --no-merger.  Force errors are measured against float64 direct summation on
 16384 seeded targets.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -960,6 +961,10 @@ def main():
     ap.add_argument("--no-fifo", action="store_true",
                     help="skip the plain one-request-at-a-time leg on the served trace")
     ap.add_argument("--no-galaxy", action="store_true", help="skip the 4M galaxy workload")
+    ap.add_argument("--no-merger", action="store_true",
+                    help="skip the compact long-run energy test (--only merger: the full one)")
+    ap.add_argument("--merger-compact-time", type=float, default=125.0,
+                    help="end time of the merger run in the default line (N-body units)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the compact accuracy / scaling sweep (--only sweep: the full one)")
     ap.add_argument("--targets", type=int, default=16384,
@@ -1154,6 +1159,9 @@ def main():
     if not args.no_galaxy:
         out["galaxy"] = bench_galaxy(10, ntarget=args.targets,
                                      cpu_budget=min(10.0, args.cpu_budget) if rank == 0 else 0.0)
+    if not args.no_merger:
+        log("merger energy test to t = %g" % args.merger_compact_time)
+        out["merger"] = bench_merger(t_end=args.merger_compact_time)
     if not args.no_accuracy:
         log("direct summation on %d targets" % args.targets)
         out["accuracy_vs_direct"] = accuracy_sample(pos, mass, acc0_h, args.eps, args.targets)

@@ -170,7 +170,9 @@ int bh_leapfrog_step(bh_ctx *ctx, double dt);
 
 /* Copy the state out in caller order; any pointer may be NULL.  pos, vel:
  * device [n][3] float64; acc: device [n][3] float32; pot: device [n] float32
- * (acc and pot from the last force evaluation). */
+ * (acc and pot from the last force evaluation).  On a batch the arrays hold
+ * every cluster in concatenated order, so one cluster's state is the slice
+ * [first, first + n) of them: there is no separate per-cluster getter. */
 int bh_get_state(bh_ctx *ctx, double *pos, double *vel, float *acc, float *pot);
 
 /* Replace positions and velocities (device [n][3] float64, caller order) of
@@ -184,10 +186,13 @@ int bh_set_state(bh_ctx *ctx, const double *pos, const double *vel);
  * Synchronous. */
 int bh_energy(bh_ctx *ctx, double out[7]);
 
-/* Host copy of the latest figures.  Synchronous. */
+/* Host copy of the latest figures (counts, interaction totals, per-phase
+ * times) in one struct.  Synchronous. */
 int bh_stats_get(bh_ctx *ctx, bh_stats *out);
 
-/* Host copies of the tree (see bh_tree_host).  Synchronous. */
+/* Host copies of the tree (see bh_tree_host), including the per-group
+ * interaction counts of the last force call (npp, npc), so counts and tree come
+ * from one call.  Synchronous. */
 int bh_export_tree(bh_ctx *ctx, const bh_tree_host *out);
 
 /* ---------------------------------------------------------------------------
@@ -305,8 +310,9 @@ typedef struct {
 
 /* Load k clusters and build their forest.  clusters: host [k].  pos: device
  * [sum n][3] float64, mass: device [sum n] float64 (> 0), vel: device [sum n][3]
- * float64 or NULL (zero), all in concatenated order.  Copied in.  Synchronous
- * (validates the inputs).  BH_EINVAL for k < 1, a bad cluster entry, a total of
+ * float64 or NULL (zero), all in concatenated order.  Copied in.  The whole
+ * table is loaded at once (no per-cluster add), so the forest is built in one
+ * pass over all clusters.  Synchronous (validates the inputs).  BH_EINVAL for k < 1, a bad cluster entry, a total of
  * 2^31 particles or more, or non-finite data. */
 int bh_batch_build(bh_ctx *ctx, const bh_cluster *clusters, int64_t k, const double *pos,
                    const double *mass, const double *vel);
@@ -463,6 +469,8 @@ int bh_server_poll(bh_server *srv, int64_t ticket, bh_request_status *out);
  * released ticket. */
 int bh_server_release(bh_server *srv, int64_t ticket);
 
+/* Counters, latency percentiles (p50, p99, max) and the served particle
+ * evaluations in one struct (host).  Synchronous. */
 int bh_server_stats_get(bh_server *srv, bh_server_stats *out);
 
 /* Install a tuning table (see bh_autotune) for requests given nleaf or ncrit 0. */

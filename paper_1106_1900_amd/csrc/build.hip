@@ -655,6 +655,55 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
     // order of the members does not matter): a leaf's from its particles, a
     // node's as the union of its children's
     double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (kLeaf && n >= 1u && n <= (uint32_t)kRun) {
+        // one run: its members are loaded once and serve all three passes, with
+        // the operations of the general path below in the same order
+        double4 q[kRun];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) q[k] = src[s + min((uint32_t)k, n - 1u)];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k)
+            if ((uint32_t)k < n) M = M + q[k].w;
+        if (kBox) {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) {
+                blo[0] = fmin(blo[0], q[k].x); bhi[0] = fmax(bhi[0], q[k].x);
+                blo[1] = fmin(blo[1], q[k].y); bhi[1] = fmax(bhi[1], q[k].y);
+                blo[2] = fmin(blo[2], q[k].z); bhi[2] = fmax(bhi[2], q[k].z);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            if ((uint32_t)k < n) {
+                sx = sx + q[k].w * q[k].x;
+                sy = sy + q[k].w * q[k].y;
+                sz = sz + q[k].w * q[k].z;
+            }
+        }
+        const double cx = sx / M, cy = sy / M, cz = sz / M;
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            if ((uint32_t)k < n) {
+                const double dx = q[k].x - cx, dy = q[k].y - cy, dz = q[k].z - cz;
+                const double w = q[k].w;
+                S[0] += w * dx * dx; S[1] += w * dy * dy; S[2] += w * dz * dz;
+                S[3] += w * dx * dy; S[4] += w * dx * dz; S[5] += w * dy * dz;
+            }
+        }
+        c_com[c] = make_double4(cx, cy, cz, M);
+        if (kBox) {
+            double2 *b = box + 3 * (int64_t)c;
+            b[0] = make_double2(blo[0], blo[1]);
+            b[1] = make_double2(blo[2], bhi[0]);
+            b[2] = make_double2(bhi[1], bhi[2]);
+        }
+        double2 *out = reinterpret_cast<double2 *>(c_S + 6 * (int64_t)c);
+        out[0] = make_double2(S[0], S[1]);
+        out[1] = make_double2(S[2], S[3]);
+        out[2] = make_double2(S[4], S[5]);
+        store_walk_multipole(c, S, q0, q1);
+        return;
+    }
     for (uint32_t r = 0; r < n; r += kRun) {
         double4 q[kRun];
 #pragma unroll

@@ -298,6 +298,26 @@ reorder_kernel(const double4 *__restrict__ p4i, const double4 *__restrict__ v4i,
 // ---------------------------------------------------------------------------
 // cells
 
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const int o = __shfl_xor(v, d, kWave);
+        v = o < v ? o : v;
+    }
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const int o = __shfl_xor(v, d, kWave);
+        v = o > v ? o : v;
+    }
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 __device__ __forceinline__ uint8_t split_level(uint64_t a, uint64_t b)
 {
     uint64_t x = a ^ b;
@@ -368,9 +388,13 @@ split_leaf_kernel(const uint64_t *__restrict__ key, const uint32_t *__restrict__
         lam[i] = lm;
         gflag[i] = 0;       // group starts are flagged later by cell_finish_kernel
     }
-    // count starts per level
+    // count starts per level (only the levels where some particle of the
+    // wavefront starts a cell)
     const int l = t % kWave;
-    for (int lev = 0; lev < kLevels; ++lev) {
+    const bool starts = valid && sp <= lm;
+    const int lo = wave_min_i32(starts ? (int)sp : kLevels);
+    const int hi = wave_max_i32(starts ? (int)lm : -1);
+    for (int lev = lo; lev <= hi; ++lev) {
         unsigned long long b = ballot(valid && sp <= lev && lev <= lm);
         if (l == 0 && b) atomicAdd(&s_cnt[lev], (uint32_t)__popcll(b));
     }
@@ -458,10 +482,12 @@ struct Ranks {
     uint32_t anc[kLevels];
 };
 
+// Only the levels lo..hi (wavefront-uniform) get their ranks; the starts of every
+// level are counted, as other wavefronts of the block may need them.
 __device__ __forceinline__ void level_ranks(bool valid, uint8_t sp, uint8_t lm,
                                             const uint32_t *__restrict__ blk_scanned, int nblk,
                                             const DevMisc *__restrict__ m, uint32_t (*s_wc)[kLevels],
-                                            Ranks &r)
+                                            int lo, int hi, Ranks &r)
 {
     const int t = threadIdx.x, w = t / kWave, l = t % kWave;
     unsigned long long balls[kLevels];
@@ -474,6 +500,7 @@ __device__ __forceinline__ void level_ranks(bool valid, uint8_t sp, uint8_t lm,
     const unsigned long long le = (l == kWave - 1) ? ~0ull : ((2ull << l) - 1ull);
 #pragma unroll
     for (int lev = 0; lev < kLevels; ++lev) {
+        if (lev < lo || lev > hi) continue;
         uint32_t off = blk_scanned[(int64_t)lev * nblk + blockIdx.x];
         for (int ww = 0; ww < w; ++ww) off += s_wc[ww][lev];
         uint32_t incl = off + (uint32_t)__popcll(balls[lev] & le);
@@ -501,12 +528,19 @@ emit_cells_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__
     const uint8_t lm = valid ? lam[i] : (uint8_t)0;
     // split of the next particle: 0 past the end (and at a cluster's first particle)
     const uint8_t sn = (valid && i + 1 < n) ? split[i + 1] : (uint8_t)0;
+    // the levels whose ranks this particle uses: from the parent of its first
+    // start or end up to its leaf (none if it starts and ends nothing)
+    const int first_lev = sp < sn ? sp : sn;
+    const bool used = valid && first_lev <= lm;
+    const int lo = wave_min_i32(used ? (first_lev > 0 ? first_lev - 1 : 0) : kLevels);
+    const int hi = wave_max_i32(used ? (int)lm : -1);
     Ranks r;
-    level_ranks(valid, sp, lm, blk_scanned, nblk, m, s_wc, r);
+    level_ranks(valid, sp, lm, blk_scanned, nblk, m, s_wc, lo, hi, r);
     const uint32_t ncells = m->ncells;
     if (!valid || ncells == 0) return;
 #pragma unroll
     for (int lev = 0; lev < kLevels; ++lev) {
+        if (lev < lo || lev > hi) continue;      // wavefront-uniform
         if (lev > lm) continue;
         const uint32_t c = r.anc[lev];
         if (c >= ncells) continue;
@@ -893,13 +927,16 @@ moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restri
     }
 }
 
-// The nodes of levels hi down to lo in one workgroup, a barrier between levels:
-// for the levels below the tree's expected depth, which normally hold no cells,
-// where a launch per level would cost more than the work.
+// The nodes of levels hi down to lo in one workgroup of kThreads, a barrier
+// between levels: for the levels below the tree's expected depth, which normally
+// hold no cells, and for the small levels next to the root, where a launch per
+// level would cost more than the work.
 constexpr int kLevelsBlock = 256;
+constexpr int kTopBlock = 512;
+constexpr uint32_t kTopCells = 512;     // top levels of at most this many cells share a launch
 
-template <bool kBox>
-__global__ void __launch_bounds__(kLevelsBlock)
+template <bool kBox, int kThreads>
+__global__ void __launch_bounds__(kThreads)
 moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
                       const uint8_t *__restrict__ c_leaf, const uint32_t *__restrict__ c_first,
                       const uint32_t *__restrict__ c_count, const uint32_t *__restrict__ c_child,
@@ -910,7 +947,7 @@ moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
     for (int level = hi; level >= lo; --level) {
         const uint32_t begin = m->level_offset[level];
         const uint32_t count = m->level_count[level];
-        for (uint32_t t = threadIdx.x; t < count; t += kLevelsBlock) {
+        for (uint32_t t = threadIdx.x; t < count; t += kThreads) {
             const uint32_t c = begin + t;
             const uint32_t ch = c_child[c], nc = c_nchild[c];
             if (c_leaf[c] == 0) node_moments<kBox>(c, ch, nc, c_com, c_S, q0, q1, box);
@@ -1136,26 +1173,38 @@ hipError_t moments_launches(bh_ctx *c, double2 *box)
     // nodes from their children, deepest level first (level 20 holds only leaves).
     // The level sizes are known on the device only; the host takes those seen at
     // its last synchronisation as hints: levels below the hinted depth (normally
-    // empty; a tree that grew deeper since) share one workgroup, every other level
-    // gets a launch of its own with a grid sized for twice its hinted count.  The
-    // kernels read the true counts and loop over them, so any tree is handled
-    // whatever the hints.
+    // empty; a tree that grew deeper since) share one workgroup, and so do the
+    // levels next to the root while each holds at most kTopCells cells; every
+    // other level gets a launch of its own with a grid sized for twice its hinted
+    // count.  The kernels read the true counts and loop over them, so any tree is
+    // handled whatever the hints.
     const DevMisc &hint = *c->misc_h;
     const int deep = hint.depth ? std::min(kMaxLevel - 1, (int)hint.depth) : kMaxLevel - 1;
     if (deep < kMaxLevel - 1) {
-        hipLaunchKernelGGL((moments_levels_kernel<kBox>), dim3(1), dim3(kLevelsBlock), 0, c->stream,
-                           kMaxLevel - 1, deep + 1, c->misc, c->c_leaf, c->c_first, c->c_count,
-                           c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0,
-                           c->c_q1, box);
+        hipLaunchKernelGGL((moments_levels_kernel<kBox, kLevelsBlock>), dim3(1), dim3(kLevelsBlock),
+                           0, c->stream, kMaxLevel - 1, deep + 1, c->misc, c->c_leaf, c->c_first,
+                           c->c_count, c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S,
+                           c->c_q0, c->c_q1, box);
         BH_LAUNCH_CHECK();
     }
-    for (int lev = deep; lev >= 0; --lev) {
+    // the small levels next to the root: 0 .. top
+    int top = -1;
+    if (hint.depth)
+        while (top < deep && hint.level_count[top + 1] <= kTopCells) ++top;
+    for (int lev = deep; lev > top; --lev) {
         int gl = g;
         if (hint.depth && hint.level_count[lev])
             gl = (int)std::min<int64_t>(g, grid_for(2 * (int64_t)hint.level_count[lev], kBlock));
         hipLaunchKernelGGL((moments_kernel<false, kBox>), dim3(gl), dim3(kBlock), 0, c->stream, lev,
                            c->misc, c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild,
                            c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1, box);
+        BH_LAUNCH_CHECK();
+    }
+    if (top >= 0) {
+        hipLaunchKernelGGL((moments_levels_kernel<kBox, kTopBlock>), dim3(1), dim3(kTopBlock), 0,
+                           c->stream, top, 0, c->misc, c->c_leaf, c->c_first, c->c_count,
+                           c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0,
+                           c->c_q1, box);
         BH_LAUNCH_CHECK();
     }
     return hipSuccess;

@@ -66,6 +66,10 @@ constexpr int kTileReach = 84;
 // cells and padding.  The cell list holds fewer than a full tile between
 // evaluations plus at most 64 from one pop (< 148 entries); the last, partial
 // tile of fewer than 84 cells is read up to 83 + 20 past its start.
+// Stack reads and pushes that stay within the LDS part use LDS instructions only.
+#ifndef BH_WALK_LDS_FAST
+#define BH_WALK_LDS_FAST 1
+#endif
 #ifndef BH_WALK_FLEX_TILE
 #define BH_WALK_FLEX_TILE 1
 #endif
@@ -158,7 +162,13 @@ __device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &e
     const int lane = lane_id();
     const int m = top < kWave ? top : kWave;
     uint32_t f = 0, cnt = 0;
-    if (lane < m) list.get(top - 1 - lane, f, cnt);
+    // a stack whose entries all lie in LDS is read with LDS loads only (top is
+    // the same in every lane, so the branch is uniform)
+    if (BH_WALK_LDS_FAST && list.all_lds(top)) {
+        if (lane < m) list.get_lds(top - 1 - lane, f, cnt);
+    } else {
+        if (lane < m) list.get(top - 1 - lane, f, cnt);
+    }
     const uint32_t incl = wave_incl_scan_add(cnt);
     const uint32_t excl = incl - cnt;
     uint32_t take = 0;
@@ -193,12 +203,20 @@ __device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &e
 struct CellStack {
     uint32_t *s;
     volatile uint32_t *spill;
+    __device__ bool all_lds(int n) const { return n <= kLdsStack; }
     __device__ void get(int i, uint32_t &f, uint32_t &c) const
     {
         const uint32_t v = i < kLdsStack ? s[i] : spill[i - kLdsStack];
         f = v >> 3;
         c = (v & 7u) + 1u;
     }
+    __device__ void get_lds(int i, uint32_t &f, uint32_t &c) const
+    {
+        const uint32_t v = s[i];
+        f = v >> 3;
+        c = (v & 7u) + 1u;
+    }
+    __device__ void set_lds(int i, uint32_t f, uint32_t c) const { s[i] = (f << 3) | (c - 1u); }
     __device__ void set(int i, uint32_t f, uint32_t c) const
     {
         const uint32_t v = (f << 3) | (c - 1u);
@@ -215,12 +233,14 @@ struct CellStack {
 
 struct LeafList {
     uint2 *s;
+    __device__ bool all_lds(int) const { return true; }
     __device__ void get(int i, uint32_t &f, uint32_t &c) const
     {
         const uint2 v = s[i];
         f = v.x;
         c = v.y;
     }
+    __device__ void get_lds(int i, uint32_t &f, uint32_t &c) const { get(i, f, c); }
     __device__ void set(int i, uint32_t f, uint32_t c) const { s[i] = make_uint2(f, c); }
     __device__ void sync() const { wave_sync(); }
 };
@@ -553,7 +573,11 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
         if (top + nn > kStackCap) {
             overflow = true;
         } else {
-            if (isn) stack.set(top + mask_rank(bn), link, info);
+            if (BH_WALK_LDS_FAST && stack.all_lds(top + nn)) {
+                if (isn) stack.set_lds(top + mask_rank(bn), link, info);
+            } else {
+                if (isn) stack.set(top + mask_rank(bn), link, info);
+            }
             top += nn;
         }
         stack.sync();

@@ -193,9 +193,15 @@ __device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &e
     const uint32_t fs = __shfl(f, src, kWave);
     const uint32_t es = __shfl(excl, src, kWave);
     elem = fs + ((uint32_t)lane - es);
-    if (lane == nfull && lane < m && take > 0 && take < cnt) list.set(top - 1 - lane, f + take, cnt - take);
+    if (lane == nfull && lane < m && take > 0 && take < cnt) {
+        if (BH_WALK_LDS_FAST && list.all_lds(top)) list.set_lds(top - 1 - lane, f + take, cnt - take);
+        else list.set(top - 1 - lane, f + take, cnt - take);
+    }
+    // only an access to the device part needs its stores waited for
+    const bool lds_only = BH_WALK_LDS_FAST && list.all_lds(top);
     top -= nfull;
-    list.sync();
+    if (lds_only) wave_sync();
+    else list.sync();
     return got;
 }
 
@@ -241,6 +247,7 @@ struct LeafList {
         c = v.y;
     }
     __device__ void get_lds(int i, uint32_t &f, uint32_t &c) const { get(i, f, c); }
+    __device__ void set_lds(int i, uint32_t f, uint32_t c) const { set(i, f, c); }
     __device__ void set(int i, uint32_t f, uint32_t c) const { s[i] = make_uint2(f, c); }
     __device__ void sync() const { wave_sync(); }
 };
@@ -572,15 +579,18 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
         const int nn = __popcll(bn);
         if (top + nn > kStackCap) {
             overflow = true;
+            wave_sync();
         } else {
             if (BH_WALK_LDS_FAST && stack.all_lds(top + nn)) {
                 if (isn) stack.set_lds(top + mask_rank(bn), link, info);
+                top += nn;
+                wave_sync();
             } else {
                 if (isn) stack.set(top + mask_rank(bn), link, info);
+                top += nn;
+                stack.sync();
             }
-            top += nn;
         }
-        stack.sync();
         if (pc_n >= tsz) {       // pc_n < tsz + 64: one tile of the last tsz entries
             __builtin_amdgcn_s_setprio(0);
             eval_pc<kEps0, M>(L, pc_n - tsz, tsz, t, eps2, acc);

@@ -87,6 +87,7 @@ void free_buffers(bh_ctx *c)
     dfree(c->c_first);
     dfree(c->c_count);
     dfree(c->c_end);
+    dfree(c->c_cl);
     dfree(c->c_child);
     dfree(c->c_nchild);
     dfree(c->c_parent);
@@ -179,6 +180,7 @@ hipError_t each_buffer(bh_ctx *c, const Sizes &z, F f)
     B(c->c_first, z.cells);
     B(c->c_count, z.cells);
     B(c->c_end, z.cells);
+    B(c->c_cl, z.cells);
     B(c->c_child, z.cells);
     B(c->c_nchild, z.cells);
     B(c->c_parent, z.cells);
@@ -400,6 +402,7 @@ int load_table(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n)
     c->nchunks = nch;
     c->max_nleaf = lmax;
     c->host_clusters = cl;
+    c->rec_fresh = false;
     c->any_eps0 = any_zero_eps(cl);
     c->layout += 1;
     TRY_HIP(c, hipMemcpyAsync(c->chunks, c->chunks_h, sizeof(Chunk) * (size_t)nch,
@@ -411,12 +414,15 @@ int load_table(bh_ctx *c, const std::vector<bh_cluster> &cl, int64_t n)
 // Sets theta, eps and dt of clusters from a table (uploads only if any changed).
 int update_params(bh_ctx *c, const std::vector<bh_cluster> &cl)
 {
-    bool changed = false;
-    for (int64_t k = 0; k < c->K && !changed; ++k) {
+    bool changed = false, records = false;
+    for (int64_t k = 0; k < c->K; ++k) {
         const bh_cluster &a = c->host_clusters[k], &b = cl[k];
-        changed = a.theta != b.theta || a.eps != b.eps || a.dt != b.dt || a.mac != b.mac;
+        changed = changed || a.theta != b.theta || a.eps != b.eps || a.dt != b.dt || a.mac != b.mac;
+        records = records || a.theta != b.theta || a.mac != b.mac;
     }
     if (!changed) return BH_OK;
+    // the walk records hold the opening radii of the old theta or test
+    if (records) c->rec_fresh = false;
     TRY_ST(staging_ready(c));
     for (int64_t k = 0; k < c->K; ++k) fill_params(c->clus_h[k], cl[k]);
     c->host_clusters = cl;

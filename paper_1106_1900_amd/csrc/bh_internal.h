@@ -138,6 +138,8 @@ struct bh_ctx {
     int32_t mac = 0;              // opening test bh_build_tree gives its cluster
     bool moved = false;           // positions drifted since the last build or refit
     bool refitted = false;        // the cells' moments were refitted since the last build
+    bool rec_fresh = false;       // the walk records were written by the last moments pass with
+                                  // the cluster table's current theta and opening test
     int64_t layout = 0;     // changes whenever buffers or the cluster table change
 
     // host copies of counts, refreshed at synchronisation points
@@ -178,6 +180,7 @@ struct bh_ctx {
     uint32_t *c_first = nullptr, *c_count = nullptr, *c_child = nullptr, *c_nchild = nullptr;
     uint32_t *c_parent = nullptr;
     uint32_t *c_end = nullptr;               // one past a cell's last particle (build only)
+    uint32_t *c_cl = nullptr;                // the cell's cluster
     uint8_t *c_level = nullptr, *c_leaf = nullptr;
     double4 *c_com = nullptr;                // centre of mass, mass (float64)
     double *c_S = nullptr;                   // [c][6] float64 second moment

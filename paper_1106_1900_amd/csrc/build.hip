@@ -119,6 +119,7 @@ bbox_kernel(Src src, const Chunk *__restrict__ chunks, double *__restrict__ part
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         m->nleaves = 0;
         m->ngroups = 0;
+        m->walk_next = 0;
         m->ncells = 0;
         m->levels_done = 0;
     }
@@ -519,7 +520,8 @@ emit_cells_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__
                   uint32_t *__restrict__ c_first, uint8_t *__restrict__ c_level,
                   uint8_t *__restrict__ c_leaf, uint32_t *__restrict__ c_parent,
                   uint32_t *__restrict__ c_child, uint32_t *__restrict__ c_end,
-                  uint32_t *__restrict__ c_cend)
+                  uint32_t *__restrict__ c_cend, const uint32_t *__restrict__ pcl,
+                  uint32_t *__restrict__ c_cl)
 {
     __shared__ uint32_t s_wc[kTreeTile / kWave][kLevels];
     const int64_t i = (int64_t)blockIdx.x * kTreeTile + threadIdx.x;
@@ -538,6 +540,7 @@ emit_cells_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__
     level_ranks(valid, sp, lm, blk_scanned, nblk, m, s_wc, lo, hi, r);
     const uint32_t ncells = m->ncells;
     if (!valid || ncells == 0) return;
+    const uint32_t cluster = sp <= lm ? pcl[i] : 0u;
 #pragma unroll
     for (int lev = 0; lev < kLevels; ++lev) {
         if (lev < lo || lev > hi) continue;      // wavefront-uniform
@@ -546,6 +549,7 @@ emit_cells_kernel(const uint8_t *__restrict__ split, const uint8_t *__restrict__
         if (c >= ncells) continue;
         if (lev >= sp) {
             c_first[c] = (uint32_t)i;
+            c_cl[c] = cluster;
             c_level[c] = (uint8_t)lev;
             c_leaf[c] = (uint8_t)(lev == lm);
             c_parent[c] = lev > 0 ? r.anc[lev > 0 ? lev - 1 : 0] : kNone;
@@ -651,14 +655,104 @@ group_boxes_kernel(const uint32_t *__restrict__ g_first, const DevMisc *__restri
 // (Sect. 3.2): a leaf from its particles, a node from its children (one level
 // deeper, finished by the previous launch), both in array order.
 
+// Where the opening radii and walk records go, and what they are computed from.
+struct RecOut {
+    const DevCluster *clus;
+    const DevDomain *dom;
+    const uint8_t *c_level;
+    const uint32_t *c_cl;     // cluster of each cell
+    const uint64_t *skey;     // sorted keys
+    float *rcrit2;
+    WalkCell *rec;
+    double4 *geo;
+};
+
+// Eq. (1): r_crit = l/theta + delta with l = L 2^-level and delta the distance of
+// the centre of mass from the cell's geometric centre (a refitted cell whose
+// particles left it: its tight box's centre and side); stored as float32 r_crit^2,
+// together with the rest of the cell's walk record.  theta, the opening test and
+// the domain are those of the cell's cluster k; for the minimum-distance test
+// r_crit = l/theta and the cube (centre, half side) goes to geo.  f: the cell's
+// first particle (its key gives the key prefix); box: the cell's tight box (lo x,
+// y, z, hi x, y, z) after a refit, else null.
+__device__ __forceinline__ void cell_record(uint32_t c, uint32_t f, int lev, uint32_t k, bool leaf,
+                                            uint32_t link, uint32_t info, const double4 cm,
+                                            const float4 a, const float4 b, const double *blo,
+                                            const double *bhi, const RecOut &ro)
+{
+    const DevDomain &cl = ro.dom[k];
+    const float theta = ro.clus[k].theta;
+    const double l = ldexp(cl.L, -lev);
+    const uint64_t pre = ro.skey[f] >> (3 * (kMaxLevel - lev));
+    const double gx = cl.lo[0] + ((double)compact3(pre) + 0.5) * l;
+    const double gy = cl.lo[1] + ((double)compact3(pre >> 1) + 0.5) * l;
+    const double gz = cl.lo[2] + ((double)compact3(pre >> 2) + 0.5) * l;
+    // After a refit a cell whose particles all still lie in its key cell keeps
+    // this geometry; any other cell takes its box's centre and side
+    // max(l, largest extent), so that the cube of the opening tests holds every
+    // particle of the cell.  The integer map is monotone, so the particles keep
+    // the key cell exactly when the box's two ends do.
+    double side = l, cx = gx, cy = gy, cz = gz;
+    if (blo) {
+        const int sh = kMaxLevel - lev;
+        const uint32_t cell[3] = {compact3(pre), compact3(pre >> 1), compact3(pre >> 2)};
+        bool inside = true;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            inside = inside && blo[q] >= cl.lo[q] && bhi[q] <= cl.hi[q] &&
+                     (coord_to_int(blo[q], cl.lo[q], cl.scale) >> sh) == cell[q] &&
+                     (coord_to_int(bhi[q], cl.lo[q], cl.scale) >> sh) == cell[q];
+        }
+        if (!inside) {
+            double ext = 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) ext = bhi[q] - blo[q] > ext ? bhi[q] - blo[q] : ext;
+            side = ext > l ? ext : l;
+            cx = 0.5 * (blo[0] + bhi[0]);
+            cy = 0.5 * (blo[1] + bhi[1]);
+            cz = 0.5 * (blo[2] + bhi[2]);
+        }
+    }
+    double r;
+    if (ro.clus[k].mac) {
+        // minimum-distance test: the cube (geometric centre, half side) must lie
+        // beyond side / theta of the group's box
+        r = side / (double)theta;
+        ro.geo[c] = make_double4(cx, cy, cz, 0.5 * side);
+    } else {
+        const double dx = cm.x - cx, dy = cm.y - cy, dz = cm.z - cz;
+        const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
+        r = side / (double)theta + delta;
+    }
+    const float r2 = (float)(r * r);
+    ro.rcrit2[c] = r2;
+    WalkCell w;
+    w.cx = cm.x;
+    w.cy = cm.y;
+    w.cz = cm.z;
+    w.mass = (float)cm.w;
+    w.rcrit2 = r2;
+    w.link = link;
+    w.info = leaf ? (info | 0x80000000u) : info;
+    w.s3[0] = a.x;
+    w.s3[1] = a.y;
+    w.s3[2] = a.z;
+    w.s3[3] = a.w;
+    w.s3[4] = b.x;
+    w.s3[5] = b.y;
+    ro.rec[c] = w;
+}
+
 __device__ __forceinline__ void store_walk_multipole(uint32_t c, const double *S,
-                                                     float4 *__restrict__ q0, float4 *__restrict__ q1)
+                                                     float4 *__restrict__ q0, float4 *__restrict__ q1,
+                                                     float4 &a, float4 &b)
 {
     const double tr = (S[0] + S[1]) + S[2];
-    q0[c] = make_float4((float)(3.0 * S[0]), (float)(3.0 * S[1]), (float)(3.0 * S[2]),
-                        (float)(3.0 * S[3]));
-    q1[c] = make_float4((float)(3.0 * S[4]), (float)(3.0 * S[5]), (float)(0.5 * tr),
-                        (float)(1.5 * tr));
+    a = make_float4((float)(3.0 * S[0]), (float)(3.0 * S[1]), (float)(3.0 * S[2]),
+                    (float)(3.0 * S[3]));
+    b = make_float4((float)(3.0 * S[4]), (float)(3.0 * S[5]), (float)(0.5 * tr), (float)(1.5 * tr));
+    q0[c] = a;
+    q1[c] = b;
 }
 
 // Moments of cell c: a leaf from its particles, a node from its children (one
@@ -676,12 +770,16 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
                                              const double4 *__restrict__ p4,
                                              double4 *__restrict__ c_com, double *__restrict__ c_S,
                                              float4 *__restrict__ q0, float4 *__restrict__ q1,
-                                             double2 *__restrict__ box)
+                                             double2 *__restrict__ box, const RecOut &ro)
 {
     // members [s, s + n): particles of a leaf (position, mass) or children of a
     // node (centre of mass, mass; second moments in c_S)
     const uint32_t s = kLeaf ? c_first[c] : c_child[c];
     const uint32_t n = kLeaf ? c_count[c] : c_nchild[c];
+    // the walk record's inputs, loaded with the cell's own record
+    const int lev = ro.c_level[c];
+    const uint32_t kc = ro.c_cl[c];
+    const uint32_t rlink = kLeaf ? s : c_child[c];
     const double4 *__restrict__ src = kLeaf ? p4 : c_com;
     double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     double S[6] = {0, 0, 0, 0, 0, 0};
@@ -735,7 +833,10 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
         out[0] = make_double2(S[0], S[1]);
         out[1] = make_double2(S[2], S[3]);
         out[2] = make_double2(S[4], S[5]);
-        store_walk_multipole(c, S, q0, q1);
+        float4 qa, qb;
+        store_walk_multipole(c, S, q0, q1, qa, qb);
+        cell_record(c, s, lev, kc, kLeaf, rlink, n, make_double4(cx, cy, cz, M), qa, qb,
+                    kBox ? blo : nullptr, kBox ? bhi : nullptr, ro);
         return;
     }
     for (uint32_t r = 0; r < n; r += kRun) {
@@ -824,7 +925,10 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
     out[0] = make_double2(S[0], S[1]);
     out[1] = make_double2(S[2], S[3]);
     out[2] = make_double2(S[4], S[5]);
-    store_walk_multipole(c, S, q0, q1);
+    float4 qa, qb;
+    store_walk_multipole(c, S, q0, q1, qa, qb);
+    cell_record(c, s, lev, kc, kLeaf, rlink, n, make_double4(cx, cy, cz, M), qa, qb,
+                kBox ? blo : nullptr, kBox ? bhi : nullptr, ro);
 }
 
 // Moments of node c from its n <= 8 children [s, s + n) (one level deeper,
@@ -832,10 +936,11 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
 // every child's centre of mass, second moment (and box) is loaded up front in
 // one batch, so a node costs one round of dependent loads after its own record.
 template <bool kBox>
-__device__ __forceinline__ void node_moments(uint32_t c, uint32_t s, uint32_t n,
-                                             double4 *__restrict__ c_com, double *__restrict__ c_S,
-                                             float4 *__restrict__ q0, float4 *__restrict__ q1,
-                                             double2 *__restrict__ box)
+__device__ __forceinline__ void node_moments(uint32_t c, uint32_t s, uint32_t n, uint32_t f, int lev,
+                                             uint32_t k, double4 *__restrict__ c_com,
+                                             double *__restrict__ c_S, float4 *__restrict__ q0,
+                                             float4 *__restrict__ q1, double2 *__restrict__ box,
+                                             const RecOut &ro)
 {
     if (n < 1u || n > 8u) return;      // a node has 1..8 children (checked when the tree is built)
     double4 q[8];
@@ -874,10 +979,10 @@ __device__ __forceinline__ void node_moments(uint32_t c, uint32_t s, uint32_t n,
         }
     }
     c_com[c] = make_double4(cx, cy, cz, M);
+    double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
     if (kBox) {
         // the union of the children's boxes (refits only: a second round of
         // loads keeps the registers of the common path free)
-        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             // lo x, y; lo z, hi x; hi y, z (repeated members change no min or max)
@@ -896,7 +1001,10 @@ __device__ __forceinline__ void node_moments(uint32_t c, uint32_t s, uint32_t n,
     out[0] = make_double2(S[0], S[1]);
     out[1] = make_double2(S[2], S[3]);
     out[2] = make_double2(S[4], S[5]);
-    store_walk_multipole(c, S, q0, q1);
+    float4 qa, qb;
+    store_walk_multipole(c, S, q0, q1, qa, qb);
+    cell_record(c, f, lev, k, false, s, n, make_double4(cx, cy, cz, M), qa, qb, kBox ? blo : nullptr,
+                kBox ? bhi : nullptr, ro);
 }
 
 // kLeaves: every leaf of the tree (any level); otherwise the nodes of one level.
@@ -908,7 +1016,7 @@ moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restri
                const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
                const double4 *__restrict__ p4, double4 *__restrict__ c_com,
                double *__restrict__ c_S, float4 *__restrict__ q0, float4 *__restrict__ q1,
-               double2 *__restrict__ box)
+               double2 *__restrict__ box, RecOut ro)
 {
     const uint32_t begin = kLeaves ? 0u : m->level_offset[level];
     const uint32_t count = kLeaves ? m->ncells : m->level_count[level];
@@ -918,11 +1026,12 @@ moments_kernel(int level, const DevMisc *__restrict__ m, const uint8_t *__restri
         if (kLeaves) {
             if (leaf)
                 cell_moments<true, kBox>(c, c_first, c_count, c_child, c_nchild, p4, c_com, c_S,
-                                         q0, q1, box);
+                                         q0, q1, box, ro);
         } else {
             // the node's own record, loaded with its leaf flag in one round
-            const uint32_t ch = c_child[c], nc = c_nchild[c];
-            if (!leaf) node_moments<kBox>(c, ch, nc, c_com, c_S, q0, q1, box);
+            const uint32_t ch = c_child[c], nc = c_nchild[c], f = c_first[c], k = ro.c_cl[c];
+            const int lev = ro.c_level[c];
+            if (!leaf) node_moments<kBox>(c, ch, nc, f, lev, k, c_com, c_S, q0, q1, box, ro);
         }
     }
 }
@@ -942,118 +1051,48 @@ moments_levels_kernel(int hi, int lo, const DevMisc *__restrict__ m,
                       const uint32_t *__restrict__ c_count, const uint32_t *__restrict__ c_child,
                       const uint32_t *__restrict__ c_nchild, const double4 *__restrict__ p4,
                       double4 *__restrict__ c_com, double *__restrict__ c_S,
-                      float4 *__restrict__ q0, float4 *__restrict__ q1, double2 *__restrict__ box)
+                      float4 *__restrict__ q0, float4 *__restrict__ q1, double2 *__restrict__ box,
+                      RecOut ro)
 {
     for (int level = hi; level >= lo; --level) {
         const uint32_t begin = m->level_offset[level];
         const uint32_t count = m->level_count[level];
         for (uint32_t t = threadIdx.x; t < count; t += kThreads) {
             const uint32_t c = begin + t;
-            const uint32_t ch = c_child[c], nc = c_nchild[c];
-            if (c_leaf[c] == 0) node_moments<kBox>(c, ch, nc, c_com, c_S, q0, q1, box);
+            const uint32_t ch = c_child[c], nc = c_nchild[c], f = c_first[c], k = ro.c_cl[c];
+            if (c_leaf[c] == 0)
+                node_moments<kBox>(c, ch, nc, f, level, k, c_com, c_S, q0, q1, box, ro);
         }
         __syncthreads();
     }
 }
 
-// Eq. (1): r_crit = l/theta + delta with l = L 2^-level and delta the distance of
-// the centre of mass from the cell's geometric centre (a refitted cell whose
-// particles left it: its tight box's centre and side); stored as float32 r_crit^2,
-// together with the rest of the cell's walk record.  theta, the opening test and
-// the domain are those of the cell's cluster; for the minimum-distance test
-// r_crit = l/theta and the cube (centre, half side) goes to geo.
+// The opening radii and walk records of every cell from its stored moments (the
+// moments kernels write them as they go; this pass serves force calls whose
+// theta or opening test differ from those the moments saw).  See cell_record.
 __global__ void __launch_bounds__(kBlock)
-rcrit_kernel(DevMisc *__restrict__ m, const DevCluster *__restrict__ clus,
-             const DevDomain *__restrict__ dom, const uint32_t *__restrict__ pcl, const uint8_t *__restrict__ c_level,
-             const uint32_t *__restrict__ c_first, const uint32_t *__restrict__ c_count,
-             const uint32_t *__restrict__ c_child, const uint32_t *__restrict__ c_nchild,
-             const uint8_t *__restrict__ c_leaf, const uint64_t *__restrict__ skey,
+rcrit_kernel(DevMisc *__restrict__ m, RecOut ro, const uint32_t *__restrict__ c_first,
+             const uint32_t *__restrict__ c_count, const uint32_t *__restrict__ c_child,
+             const uint32_t *__restrict__ c_nchild, const uint8_t *__restrict__ c_leaf,
              const double4 *__restrict__ c_com, const float4 *__restrict__ q0,
-             const float4 *__restrict__ q1, float *__restrict__ rcrit2, WalkCell *__restrict__ rec,
-             double4 *__restrict__ geo, const double2 *__restrict__ box)
+             const float4 *__restrict__ q1, const double2 *__restrict__ box)
 {
-    // the walk that follows takes its groups from a counter cleared here
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        m->walk_next = 0;
-        m->sum_npp = 0;
-        m->sum_npc = 0;
-    }
     const uint32_t ncells = m->ncells;
     for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < ncells; c += gridDim.x * kBlock) {
         const uint32_t f = c_first[c];
-        const uint32_t k = pcl[f];
-        const DevDomain &cl = dom[k];
-        const float theta = clus[k].theta;
-        const int lev = c_level[c];
-        const double l = ldexp(cl.L, -lev);
-        const uint64_t pre = skey[f] >> (3 * (kMaxLevel - lev));
-        const double gx = cl.lo[0] + ((double)compact3(pre) + 0.5) * l;
-        const double gy = cl.lo[1] + ((double)compact3(pre >> 1) + 0.5) * l;
-        const double gz = cl.lo[2] + ((double)compact3(pre >> 2) + 0.5) * l;
-        const double4 cm = c_com[c];
-        // After a refit (box: the tight box of the cell's current particles, lo
-        // x, y, z, hi x, y, z) a cell whose particles all still lie in its key
-        // cell keeps this geometry; any other cell takes its box's centre and
-        // side max(l, largest extent), so that the cube of the opening tests
-        // holds every particle of the cell.  The integer map is monotone, so the
-        // particles keep the key cell exactly when the box's two ends do.
-        double side = l, cx = gx, cy = gy, cz = gz;
+        const bool leaf = c_leaf[c] != 0;
+        double blo[3], bhi[3];
         if (box) {
             const double2 b0 = box[3 * (int64_t)c], b1 = box[3 * (int64_t)c + 1],
                           b2 = box[3 * (int64_t)c + 2];
-            const double blo[3] = {b0.x, b0.y, b1.x}, bhi[3] = {b1.y, b2.x, b2.y};
-            const int sh = kMaxLevel - lev;
-            const uint32_t cell[3] = {compact3(pre), compact3(pre >> 1), compact3(pre >> 2)};
-            bool inside = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                inside = inside && blo[a] >= cl.lo[a] && bhi[a] <= cl.hi[a] &&
-                         (coord_to_int(blo[a], cl.lo[a], cl.scale) >> sh) == cell[a] &&
-                         (coord_to_int(bhi[a], cl.lo[a], cl.scale) >> sh) == cell[a];
-            }
-            if (!inside) {
-                double ext = 0.0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) ext = bhi[a] - blo[a] > ext ? bhi[a] - blo[a] : ext;
-                side = ext > l ? ext : l;
-                cx = 0.5 * (blo[0] + bhi[0]);
-                cy = 0.5 * (blo[1] + bhi[1]);
-                cz = 0.5 * (blo[2] + bhi[2]);
-            }
+            blo[0] = b0.x; blo[1] = b0.y; blo[2] = b1.x;
+            bhi[0] = b1.y; bhi[1] = b2.x; bhi[2] = b2.y;
         }
-        double r;
-        if (clus[k].mac) {
-            // minimum-distance test: the cube (geometric centre, half side) must lie
-            // beyond side / theta of the group's box
-            r = side / (double)theta;
-            geo[c] = make_double4(cx, cy, cz, 0.5 * side);
-        } else {
-            const double dx = cm.x - cx, dy = cm.y - cy, dz = cm.z - cz;
-            const double delta = sqrt((dx * dx + dy * dy) + dz * dz);
-            r = side / (double)theta + delta;
-        }
-        const float r2 = (float)(r * r);
-        rcrit2[c] = r2;
-        const bool leaf = c_leaf[c] != 0;
-        const float4 a = q0[c], b = q1[c];
-        WalkCell w;
-        w.cx = cm.x;
-        w.cy = cm.y;
-        w.cz = cm.z;
-        w.mass = (float)cm.w;
-        w.rcrit2 = r2;
-        w.link = leaf ? f : c_child[c];
-        w.info = leaf ? (c_count[c] | 0x80000000u) : c_nchild[c];
-        w.s3[0] = a.x;
-        w.s3[1] = a.y;
-        w.s3[2] = a.z;
-        w.s3[3] = a.w;
-        w.s3[4] = b.x;
-        w.s3[5] = b.y;
-        rec[c] = w;
+        cell_record(c, f, ro.c_level[c], ro.c_cl[c], leaf, leaf ? f : c_child[c],
+                    leaf ? c_count[c] : c_nchild[c], c_com[c], q0[c], q1[c], box ? blo : nullptr,
+                    box ? bhi : nullptr, ro);
     }
 }
-
 
 }  // namespace
 
@@ -1134,7 +1173,7 @@ hipError_t launch_tree(bh_ctx *c)
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(emit_cells_kernel, dim3(nblk), dim3(kTreeTile), 0, c->stream, c->split,
                        c->lam, n, blk, nblk, c->misc, c->c_first, c->c_level, c->c_leaf,
-                       c->c_parent, c->c_child, c->c_end, c->c_nchild);
+                       c->c_parent, c->c_child, c->c_end, c->c_nchild, c->pcl, c->c_cl);
     BH_LAUNCH_CHECK();
     int g = grid_for(c->cap_c, kBlock);
     if (g > kFixedGrid) g = kFixedGrid;
@@ -1165,10 +1204,12 @@ hipError_t moments_launches(bh_ctx *c, double2 *box)
 {
     int g = grid_for(c->cap_c, kBlock);
     if (g > kFixedGrid) g = kFixedGrid;
+    // every cell's opening radius and walk record are written with its moments
+    const RecOut ro{c->clus, c->dom, c->c_level, c->c_cl, c->key[0], c->c_rcrit2, c->c_rec, c->c_geo};
     // every leaf, whatever its level, from its particles
     hipLaunchKernelGGL((moments_kernel<true, kBox>), dim3(g), dim3(kBlock), 0, c->stream, 0, c->misc,
                        c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild, c->p4[c->cur],
-                       c->c_com, c->c_S, c->c_q0, c->c_q1, box);
+                       c->c_com, c->c_S, c->c_q0, c->c_q1, box, ro);
     BH_LAUNCH_CHECK();
     // nodes from their children, deepest level first (level 20 holds only leaves).
     // The level sizes are known on the device only; the host takes those seen at
@@ -1184,7 +1225,7 @@ hipError_t moments_launches(bh_ctx *c, double2 *box)
         hipLaunchKernelGGL((moments_levels_kernel<kBox, kLevelsBlock>), dim3(1), dim3(kLevelsBlock),
                            0, c->stream, kMaxLevel - 1, deep + 1, c->misc, c->c_leaf, c->c_first,
                            c->c_count, c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S,
-                           c->c_q0, c->c_q1, box);
+                           c->c_q0, c->c_q1, box, ro);
         BH_LAUNCH_CHECK();
     }
     // the small levels next to the root: 0 .. top
@@ -1197,16 +1238,17 @@ hipError_t moments_launches(bh_ctx *c, double2 *box)
             gl = (int)std::min<int64_t>(g, grid_for(2 * (int64_t)hint.level_count[lev], kBlock));
         hipLaunchKernelGGL((moments_kernel<false, kBox>), dim3(gl), dim3(kBlock), 0, c->stream, lev,
                            c->misc, c->c_leaf, c->c_first, c->c_count, c->c_child, c->c_nchild,
-                           c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1, box);
+                           c->p4[c->cur], c->c_com, c->c_S, c->c_q0, c->c_q1, box, ro);
         BH_LAUNCH_CHECK();
     }
     if (top >= 0) {
         hipLaunchKernelGGL((moments_levels_kernel<kBox, kTopBlock>), dim3(1), dim3(kTopBlock), 0,
                            c->stream, top, 0, c->misc, c->c_leaf, c->c_first, c->c_count,
                            c->c_child, c->c_nchild, c->p4[c->cur], c->c_com, c->c_S, c->c_q0,
-                           c->c_q1, box);
+                           c->c_q1, box, ro);
         BH_LAUNCH_CHECK();
     }
+    c->rec_fresh = true;
     return hipSuccess;
 }
 
@@ -1218,13 +1260,16 @@ hipError_t launch_moments(bh_ctx *c, bool boxes)
 
 hipError_t launch_rcrit(bh_ctx *c)
 {
+    // the moments pass wrote the records with the current table already
+    if (c->rec_fresh) return hipSuccess;
     int g = grid_for(c->cap_c, kBlock);
     if (g > kFixedGrid) g = kFixedGrid;
-    hipLaunchKernelGGL(rcrit_kernel, dim3(g), dim3(kBlock), 0, c->stream, c->misc, c->clus, c->dom,
-                       c->pcl, c->c_level, c->c_first, c->c_count, c->c_child, c->c_nchild, c->c_leaf,
-                       c->key[0], c->c_com, c->c_q0, c->c_q1, c->c_rcrit2, c->c_rec, c->c_geo,
+    const RecOut ro{c->clus, c->dom, c->c_level, c->c_cl, c->key[0], c->c_rcrit2, c->c_rec, c->c_geo};
+    hipLaunchKernelGGL(rcrit_kernel, dim3(g), dim3(kBlock), 0, c->stream, c->misc, ro, c->c_first,
+                       c->c_count, c->c_child, c->c_nchild, c->c_leaf, c->c_com, c->c_q0, c->c_q1,
                        c->refitted ? reinterpret_cast<const double2 *>(c->c_box) : nullptr);
     BH_LAUNCH_CHECK();
+    c->rec_fresh = true;
     return hipSuccess;
 }
 

@@ -66,6 +66,10 @@ constexpr int kTileReach = 84;
 // cells and padding.  The cell list holds fewer than a full tile between
 // evaluations plus at most 64 from one pop (< 148 entries); the last, partial
 // tile of fewer than 84 cells is read up to 83 + 20 past its start.
+// Particle tiles of k floor(64 / k) particles for k lanes per particle slot.
+#ifndef BH_WALK_PP_FULL
+#define BH_WALK_PP_FULL 1
+#endif
 // Stack reads and pushes that stay within the LDS part use LDS instructions only.
 #ifndef BH_WALK_LDS_FAST
 #define BH_WALK_LDS_FAST 1
@@ -154,10 +158,12 @@ __device__ __forceinline__ void comp_add(float &s, float &c, float t)
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Pop up to 64 elements from a list of ranges kept as a stack.  Lane j receives
-// element j of the popped run in *elem; returns how many were popped.
+// Pop up to cap <= 64 elements (cap the same in every lane) from a list of
+// ranges kept as a stack.  Lane j receives element j of the popped run in *elem;
+// returns how many were popped.
 template <class List>
-__device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &elem)
+__device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &elem,
+                                     int cap = kWave)
 {
     const int lane = lane_id();
     const int m = top < kWave ? top : kWave;
@@ -172,14 +178,14 @@ __device__ __forceinline__ int pop64(List list, int &top, int *mark, uint32_t &e
     const uint32_t incl = wave_incl_scan_add(cnt);
     const uint32_t excl = incl - cnt;
     uint32_t take = 0;
-    if (lane < m && excl < (uint32_t)kWave) {
-        const uint32_t room = (uint32_t)kWave - excl;
+    if (lane < m && excl < (uint32_t)cap) {
+        const uint32_t room = (uint32_t)cap - excl;
         take = cnt < room ? cnt : room;
     }
     const bool full = lane < m && take == cnt;
     const int nfull = __popcll(ballot(full));
     const uint32_t total = lane_value(incl, m - 1);
-    const int got = uniform(total < (uint32_t)kWave ? (int)total : kWave);
+    const int got = uniform(total < (uint32_t)cap ? (int)total : cap);
     // the lanes that take a range form a prefix with strictly increasing starts,
     // so the range that output slot `lane` comes from is the number of range
     // starts at or below it, minus one
@@ -497,6 +503,8 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
     // cells per full tile (uniform); trips of the largest tile
     const int tsz = BH_WALK_FLEX_TILE ? t.k * ((kWave + t.k - 1) / t.k) : kWave;
     t.tmax = (tsz + t.k - 1) / t.k;
+    // particles per full particle tile: k floor(64 / k), every trip full
+    const int psz = BH_WALK_PP_FULL ? t.k * (kWave / t.k) : kWave;
     acc.trips = 0;
     int top = 1;
     if (lane == 0) stack.set(0, cid, 1u);  // the cluster's root
@@ -570,9 +578,11 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
         const uint32_t lc = isl ? (info & 0x7fffffffu) : 0u;
         if (isl) L.pp[pp_n + mask_rank(bpp)] = make_uint2(link, lc);
         pp_n += __popcll(bpp);
-        const uint32_t lsum = wave_sum_u32(lc);
-        pend += lsum;
-        npp += lsum;
+        if (bpp) {      // uniform: some lane opened a leaf
+            const uint32_t lsum = wave_sum_u32(lc);
+            pend += lsum;
+            npp += lsum;
+        }
         // opened nodes -> children onto the stack
         const bool isn = has && !acc_cell && !leaf;
         const unsigned long long bn = ballot(isn);
@@ -596,9 +606,9 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
             eval_pc<kEps0, M>(L, pc_n - tsz, tsz, t, eps2, acc);
             pc_n -= tsz;
         }
-        while (pend >= (uint32_t)kWave) {
+        while (pend >= (uint32_t)psz) {
             uint32_t idx;
-            const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx) : 0;
+            const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx, psz) : 0;
             if (n <= 0) {   // inconsistent bookkeeping: never spin
                 overflow = true;
                 pend = 0;
@@ -614,7 +624,7 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
     if (pc_n > 0) eval_pc<kEps0, M>(L, 0, pc_n, t, eps2, acc);
     while (pend > 0) {
         uint32_t idx;
-        const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx) : 0;
+        const int n = pp_n > 0 ? pop64(leaves, pp_n, L.mark, idx, psz) : 0;
         if (n <= 0) {
             overflow = true;
             break;
@@ -809,6 +819,7 @@ walk_sum_kernel(const unsigned long long *__restrict__ part, int blocks, DevMisc
         m->sum_npc = s[1][0];
         m->tot_npp += s[0][0];
         m->tot_npc += s[1][0];
+        m->walk_next = 0;       // the next walk hands out its groups from 0 again
     }
 }
 
@@ -885,8 +896,9 @@ int64_t walk_grid_waves(bh_ctx *c)
     return (int64_t)dev_cus * BH_WALK_BLOCKS_PER_CU * kWalkWaves;
 }
 
-// The work counter and interaction sums are cleared by launch_rcrit, which
-// always precedes the walk.
+// The work counter starts at zero (set when the context's device scalars are
+// cleared and at the start of every build) and walk_sum_kernel clears it after
+// each walk; the interaction sums are written by walk_sum_kernel.
 // Flags the groups that hold at least one active particle (flags[g], zero for
 // g >= ngroups up to n so that the flags can be compacted over n entries).
 __global__ void __launch_bounds__(256)

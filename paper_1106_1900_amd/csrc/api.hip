@@ -77,6 +77,7 @@ void free_buffers(bh_ctx *c)
         dfree(c->key[i]);
         dfree(c->val[i]);
     }
+    dfree(c->splt);
     dfree(c->acc4);
     dfree(c->pcl);
     dfree(c->split);
@@ -170,6 +171,7 @@ hipError_t each_buffer(bh_ctx *c, const Sizes &z, F f)
         B(c->key[i], z.n);
         B(c->val[i], z.n);
     }
+    B(c->splt, (int64_t)kRadix * 5);
     B(c->acc4, z.n);
     B(c->pcl, z.n);
     B(c->split, z.n);
@@ -479,7 +481,7 @@ hipError_t enqueue_rebuild(bh_ctx *c)
     BH_HIP_TRY(launch_domain(c, nullptr));
     BH_HIP_TRY(launch_keys(c, nullptr));
     BH_HIP_TRY(rec(c, 1));
-    BH_HIP_TRY(radix_sort_pairs(c));
+    BH_HIP_TRY(rebuild_sort_pairs(c));
     BH_HIP_TRY(rec(c, 2));
     BH_HIP_TRY(launch_reorder(c, c->val[0]));
     return enqueue_finish_build(c);

@@ -168,6 +168,7 @@ struct bh_ctx {
     float4 *acc4 = nullptr;                  // ax, ay, az, pot (sorted order)
     uint64_t *key[2] = {nullptr, nullptr};   // sort ping-pong
     uint32_t *val[2] = {nullptr, nullptr};
+    uint64_t *splt = nullptr;                // a rebuild's sort: splitters, then candidates
     uint8_t *split = nullptr;                // level at which particle i leaves i-1's cell
     uint8_t *lam = nullptr;                  // level of the leaf holding particle i
     uint8_t *gflag = nullptr;                // group start flags
@@ -252,6 +253,12 @@ hipError_t launch_cluster_ids(bh_ctx *c);           // pcl from the chunk table
 // sort.hip
 hipError_t radix_sort_pairs(bh_ctx *c);             // sorts key[0]/val[0] of n particles
                                                     // within clusters; result in key[0]/val[0]
+// The same result for one cluster whose particles are held in the previous
+// build's order (a rebuild); falls back to radix_sort_pairs where it does not apply.
+hipError_t rebuild_sort_pairs(bh_ctx *c);
+int rebuild_buckets(const bh_ctx *c);      // buckets of that sort (0: radix sort instead)
+int rebuild_candidates(const bh_ctx *c);   // candidate keys the keys kernel writes for it
+                                           // to splt + kRadix (0: none)
 hipError_t compact_flags(bh_ctx *c, const uint8_t *flags, int64_t n, uint32_t *idx,
                          uint32_t *count);
 int64_t sort_blk_words(int64_t n);

@@ -219,12 +219,15 @@ domain_kernel(const double *__restrict__ part, const DevCluster *__restrict__ cl
 // position i goes to slot pid[i] (its caller index; pid == null: the positions
 // are the caller order, a first load) with value i.  The stable sort that
 // follows then orders equal keys by caller index, on a first load and on every
-// rebuild alike (App. A: the split primitive keeps the input order).
+// rebuild alike (App. A: the split primitive keeps the input order).  With
+// ncand > 0 the keys at positions (c + 1) cstride, c < ncand, are also written
+// to cand[c] (the candidate splitters of a rebuild's sort).
 template <typename Src>
 __global__ void __launch_bounds__(kBlock)
 keys_kernel(Src src, const Chunk *__restrict__ chunks, const DevDomain *__restrict__ dom,
             const uint32_t *__restrict__ pid, uint32_t n, uint64_t *__restrict__ key,
-            uint32_t *__restrict__ val, DevMisc *m)
+            uint32_t *__restrict__ val, uint64_t *__restrict__ cand, uint32_t ncand,
+            uint32_t cstride, DevMisc *m)
 {
     const Chunk ch = chunks[blockIdx.x];
     const DevDomain &cl = dom[ch.cluster];
@@ -255,8 +258,13 @@ keys_kernel(Src src, const Chunk *__restrict__ chunks, const DevDomain *__restri
                 atomicOr(&m->nonfinite, 8u);
                 dst = i;
             }
-            key[dst] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+            const uint64_t k = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+            key[dst] = k;
             val[dst] = i;
+            if (ncand) {
+                const uint32_t q = (uint32_t)(((double)i + 0.5) / (double)cstride);
+                if (q >= 1u && q <= ncand && q * cstride == i) cand[q - 1] = k;
+            }
         }
     }
 }
@@ -1126,11 +1134,16 @@ hipError_t launch_keys(bh_ctx *c, const double *pos_aos)
     if (pos_aos)
         hipLaunchKernelGGL(keys_kernel<AosSrc>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
                            c->stream, AosSrc{pos_aos}, c->chunks, c->dom, nullptr, (uint32_t)c->n,
-                           c->key[0], c->val[0], c->misc);
-    else
+                           c->key[0], c->val[0], nullptr, 0u, 0u, c->misc);
+    else {
+        // a rebuild: the candidate splitters of its sort, at a fixed stride
+        const uint32_t ncand = (uint32_t)rebuild_candidates(c);
+        const uint32_t cstride = ncand ? (uint32_t)(c->n / (ncand + 1)) : 0u;
         hipLaunchKernelGGL(keys_kernel<P4Src>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
                            c->stream, P4Src{c->p4[c->cur]}, c->chunks, c->dom, c->pid[c->cur],
-                           (uint32_t)c->n, c->key[0], c->val[0], c->misc);
+                           (uint32_t)c->n, c->key[0], c->val[0], c->splt + kRadix, ncand,
+                           cstride, c->misc);
+    }
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -25,6 +25,48 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t v, const uint3
     return cl ? ((cl[v] >> shift) & (kRadix - 1)) : ((uint32_t)(k >> shift) & (kRadix - 1));
 }
 
+// bucket of a key among kRadix - 1 ascending splitters (unused ones are ~0):
+// the number of splitters below it, so equal keys share a bucket and buckets
+// follow key order
+__device__ __forceinline__ uint32_t bucket_of(uint64_t k, const uint64_t *spl)
+{
+    uint32_t b = 0;
+#pragma unroll
+    for (uint32_t step = kRadix / 2; step > 0; step >>= 1)
+        if (spl[b + step - 1] < k) b += step;
+    return b;
+}
+
+// The lanes of the wavefront that are valid and hold the same 8-bit digit as
+// this lane: one ballot per digit bit, collecting the lanes that differ.
+__device__ __forceinline__ unsigned long long match_digit(uint32_t d, bool valid)
+{
+    const unsigned long long v = ballot(valid);
+    uint32_t dlo = ~(uint32_t)v, dhi = ~(uint32_t)(v >> 32);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const uint32_t s = (uint32_t)((int32_t)(d << (31 - b)) >> 31);   // ~0 if bit b is set
+        const unsigned long long m = ballot(s != 0u);
+        dlo |= (uint32_t)m ^ s;
+        dhi |= (uint32_t)(m >> 32) ^ s;
+    }
+    return ~(((unsigned long long)dhi << 32) | dlo);
+}
+
+// OR and AND of a 64-bit value over the wavefront (every lane gets the result)
+__device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) v |= __shfl_xor(v, off);
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_and_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) v &= __shfl_xor(v, off);
+    return v;
+}
+
 // Exclusive scan of one value per thread over a 256-thread block.  Returns the
 // exclusive prefix; *total receives the block sum (same in every thread).
 __device__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_tmp, uint32_t *total)
@@ -45,20 +87,33 @@ __device__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *s_tmp, uint32_t *t
     return off + inc - v;
 }
 
+constexpr int kSplitOver = 4;           // candidate keys per bucket of a rebuild's sort
+constexpr int kCand = kRadix * kSplitOver;
+
+// The digit of a pass is a radix digit of the key (or of the element's cluster),
+// or, with splitters (spl != NULL: kRadix - 1 ascending keys, unused ones ~0),
+// the key's bucket.
 __global__ void __launch_bounds__(kSortThreads)
 hist_kernel(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
-            const uint32_t *__restrict__ cl, int64_t n, int shift, uint32_t *__restrict__ hist,
-            int nblk)
+            const uint32_t *__restrict__ cl, const uint64_t *__restrict__ spl, int64_t n,
+            int shift, uint32_t *__restrict__ hist, int nblk)
 {
     __shared__ uint32_t cnt[kRadix];
+    __shared__ uint64_t s_spl[kRadix];
     const int t = threadIdx.x;
     cnt[t] = 0;
+    if (spl && t < kRadix - 1) s_spl[t] = spl[t];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         int64_t i = base + (int64_t)k * kSortThreads + t;
-        if (i < n) atomicAdd(&cnt[digit_of(keys[i], cl ? vals[i] : 0u, cl, shift)], 1u);
+        if (i < n) {
+            const uint64_t key = keys[i];
+            const uint32_t d = spl ? bucket_of(key, s_spl)
+                                   : digit_of(key, cl ? vals[i] : 0u, cl, shift);
+            atomicAdd(&cnt[d], 1u);
+        }
     }
     __syncthreads();
     hist[(int64_t)t * nblk + blockIdx.x] = cnt[t];
@@ -85,15 +140,18 @@ scan_digit_kernel(uint32_t *__restrict__ hist, int nblk, uint32_t *__restrict__ 
 __global__ void __launch_bounds__(kSortThreads)
 scatter_kernel(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
-               const uint32_t *__restrict__ cl, int64_t n, int shift,
-               const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot, int nblk)
+               const uint32_t *__restrict__ cl, const uint64_t *__restrict__ spl, int64_t n,
+               int shift, const uint32_t *__restrict__ hist,
+               const uint32_t *__restrict__ tot, int nblk)
 {
     __shared__ uint32_t s_wcnt[kSortThreads / kWave][kRadix];  // per-wave digit counts
     __shared__ uint32_t s_base[kRadix];                         // global digit base
     __shared__ uint32_t s_local[kRadix];                        // block-local digit start
     __shared__ uint32_t s_tmp[4];
+    __shared__ uint64_t s_spl[kRadix];
     __shared__ uint64_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint8_t s_dig[kSortTile];
 
     const int t = threadIdx.x, w = t / kWave, l = t % kWave;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -108,11 +166,13 @@ scatter_kernel(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vi
         uint32_t ex = block_excl_scan_256(tot[t], s_tmp, &sum);
         s_base[t] = ex;
     }
+    if (spl && t < kRadix - 1) s_spl[t] = spl[t];
     __syncthreads();
 
     uint64_t key[kSortItems];
     uint32_t val[kSortItems];
     uint32_t rank[kSortItems];
+    uint32_t dig[kSortItems];
     const int wbase = w * kWave * kSortItems;  // this wave's contiguous sub-tile
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
@@ -120,14 +180,10 @@ scatter_kernel(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vi
         bool valid = p < tile_n;
         key[k] = valid ? kin[base + p] : 0ull;
         val[k] = valid ? vin[base + p] : 0u;
-        uint32_t d = valid ? digit_of(key[k], val[k], cl, shift) : 0u;
-        unsigned long long peers = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            bool bit = (d >> b) & 1u;
-            unsigned long long m = ballot(bit);
-            peers &= bit ? m : ~m;
-        }
+        uint32_t d = 0;
+        if (valid) d = spl ? bucket_of(key[k], s_spl) : digit_of(key[k], val[k], cl, shift);
+        dig[k] = d;
+        const unsigned long long peers = match_digit(d, valid);
         uint32_t before = s_wcnt[w][d];
         int r = mask_rank(peers);
         rank[k] = before + (uint32_t)r;
@@ -157,17 +213,18 @@ scatter_kernel(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vi
     for (int k = 0; k < kSortItems; ++k) {
         int p = wbase + k * kWave + l;
         if (p < tile_n) {
-            uint32_t d = digit_of(key[k], val[k], cl, shift);
+            const uint32_t d = dig[k];
             uint32_t lp = s_local[d] + s_wcnt[w][d] + rank[k];
             s_key[lp] = key[k];
             s_val[lp] = val[k];
+            s_dig[lp] = (uint8_t)d;
         }
     }
     __syncthreads();
 
     for (int p = t; p < tile_n; p += kSortThreads) {
         uint64_t k = s_key[p];
-        uint32_t d = digit_of(k, s_val[p], cl, shift);
+        const uint32_t d = s_dig[p];
         int64_t g = (int64_t)s_base[d] + hist[(int64_t)d * nblk + blockIdx.x] + (p - s_local[d]);
         kout[g] = k;
         vout[g] = s_val[p];
@@ -245,6 +302,275 @@ compact_down_kernel(const uint8_t *__restrict__ flags, int64_t n, const uint32_t
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Sort of a rebuild.  The particles are held in the previous build's key order
+// and move little between builds, so the new keys taken at regular positions of
+// that order (the candidates, written by the keys kernel) split the new key
+// range into buckets of similar size.  One stable pass places the pairs by
+// bucket (the same three kernels as a radix pass, with the bucket as the digit),
+// and one workgroup per bucket sorts it by key, stably.  The pairs arrive in
+// caller order, which both steps keep, so equal keys end in caller order: the
+// same result as the stable radix sort of all 60 key bits.
+
+constexpr int kBucketTarget = 4096;     // mean bucket size the bucket count aims at
+constexpr int kBucketCap = 8192;        // largest bucket sorted in LDS
+constexpr int kBucketThreads = 1024;
+constexpr int kBucketWaves = kBucketThreads / kWave;
+
+// Splitters of nb buckets: the ncand candidate keys (none: one bucket) sorted,
+// every kSplitOver-th kept; kRadix - 1 values, unused ones ~0.  One element per
+// thread; the stages whose partners lie in the same wavefront need no barrier.
+__global__ void __launch_bounds__(kCand)
+splitter_kernel(const uint64_t *__restrict__ cand, int ncand, int nspl, uint64_t *__restrict__ spl)
+{
+    __shared__ uint64_t s[kCand];
+    const int t = threadIdx.x;
+    s[t] = t < ncand ? cand[t] : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= kCand; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int l = t ^ j;
+            if (l > t) {
+                const uint64_t a = s[t], b = s[l];
+                if ((a > b) == ((t & k) == 0)) {
+                    s[t] = b;
+                    s[l] = a;
+                }
+            }
+            // a stage at distance j writes elements of other wavefronts when
+            // j >= kWave, and the next one (distance j / 2, or k to open the next
+            // round) reads them when its distance is >= kWave
+            const int jn = j > 1 ? (j >> 1) : k;
+            if (j >= kWave || jn >= kWave) __syncthreads();
+            else wave_sync();
+        }
+    }
+    __syncthreads();
+    if (t < kRadix - 1) spl[t] = t < nspl ? s[(t + 1) * kSplitOver - 1] : ~0ull;
+}
+
+// One workgroup per bucket: the bucket's pairs (k1, v1)[lo, lo + L), in caller
+// order, are sorted stably by key into (k0, v0)[lo, lo + L).  Up to kBucketCap
+// pairs are sorted in LDS by stable 8-bit passes (keys and positions move, values
+// are gathered at the end), skipping the digits every key of the bucket shares; a
+// larger bucket (many equal or clustered keys) is sorted by the workgroup with the
+// same passes through (k0, v0) and back.
+__global__ void __launch_bounds__(kBucketThreads)
+bucket_sort_kernel(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1, uint64_t *__restrict__ k0,
+                   uint32_t *__restrict__ v0, const uint32_t *__restrict__ tot)
+{
+    constexpr int kItems = kBucketCap / kBucketThreads;   // most pairs per thread in LDS
+    __shared__ uint64_t s_k[kBucketCap];
+    __shared__ uint16_t s_x[kBucketCap];
+    __shared__ uint32_t s_wcnt[kBucketWaves][kRadix];
+    __shared__ uint32_t s_wcnt2[kBucketWaves][kRadix];     // the next LDS pass's counts
+    __shared__ uint32_t s_off[kRadix];
+    __shared__ uint32_t s_ctot[kRadix];
+    __shared__ uint32_t s_tmp[kBucketWaves];
+    __shared__ uint32_t s_lo;
+    __shared__ unsigned long long s_or, s_and;
+    const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+    const int b = blockIdx.x;
+    if (w == 0) {       // the bucket's first position: the sizes of the buckets before it
+        uint32_t x = 0;
+        for (int d = lane; d < b; d += kWave) x += tot[d];
+        x = wave_sum_u32(x);
+        if (lane == 0) {
+            s_lo = x;
+            s_or = 0ull;
+            s_and = ~0ull;
+        }
+    }
+    __syncthreads();
+    const int64_t lo = s_lo;
+    const uint32_t L = tot[b];
+
+    if (L <= (uint32_t)kBucketCap) {
+        // all of a thread's loads first, then the LDS stores
+        uint64_t kin[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+            kin[j] = i < L ? k1[lo + i] : 0ull;
+        }
+        unsigned long long o = 0ull, a = ~0ull;
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+            if (i < L) {
+                s_k[i] = kin[j];
+                s_x[i] = (uint16_t)i;
+                o |= kin[j];
+                a &= kin[j];
+            }
+        }
+        o = wave_or_u64(o);
+        a = wave_and_u64(a);
+        if (lane == 0) {
+            atomicOr(&s_or, o);
+            atomicAnd(&s_and, a);
+        }
+        for (int q = t; q < kBucketWaves * kRadix; q += kBucketThreads) (&s_wcnt[0][0])[q] = 0;
+        __syncthreads();
+        const uint64_t vary = s_or ^ s_and;     // bits that differ within the bucket
+        const int items = (int)((L + kBucketThreads - 1) / kBucketThreads);
+        const uint32_t sub = (uint32_t)items * kWave;      // a wavefront's positions
+        uint32_t(*cur)[kRadix] = s_wcnt;       // counts of this pass (zero at its start)
+        uint32_t(*nxt)[kRadix] = s_wcnt2;      // cleared during this pass for the next one
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = pass * kRadixBits;
+            if (((vary >> shift) & (kRadix - 1)) == 0) continue;    // one digit: order kept
+            // thread (w, lane) takes positions w sub + j kWave + lane: position
+            // order is (wavefront, j, lane) order, which the ranks below keep
+            uint64_t key[kItems];
+            uint32_t idx[kItems], rank[kItems], dg[kItems];
+#pragma unroll
+            for (int j = 0; j < kItems; ++j) {
+                if (j >= items) break;      // uniform
+                const uint32_t p = w * sub + (uint32_t)(j * kWave + lane);
+                const bool valid = p < L;
+                key[j] = valid ? s_k[p] : 0ull;
+                idx[j] = valid ? s_x[p] : 0u;
+                const uint32_t d = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+                dg[j] = d;
+                const unsigned long long peers = match_digit(d, valid);
+                const int r = mask_rank(peers);
+                const uint32_t before = j == 0 ? 0u : cur[w][d];
+                rank[j] = before + (uint32_t)r;
+                wave_sync();
+                if (valid && r == 0) cur[w][d] = before + (uint32_t)__popcll(peers);
+                wave_sync();
+            }
+            for (int q = t; q < kBucketWaves * kRadix; q += kBucketThreads) (&nxt[0][0])[q] = 0;
+            __syncthreads();
+            uint32_t cnt = 0, inc = 0;
+            if (t < kRadix) {   // wavefronts before each one, per digit; digit totals
+                uint32_t x[kBucketWaves];
+#pragma unroll
+                for (int q = 0; q < kBucketWaves; ++q) x[q] = cur[q][t];
+                uint32_t run = 0;
+#pragma unroll
+                for (int q = 0; q < kBucketWaves; ++q) {
+                    cur[q][t] = run;
+                    run += x[q];
+                }
+                cnt = run;
+                inc = wave_incl_scan_add(cnt);
+                if (lane == kWave - 1) s_tmp[w] = inc;
+            }
+            __syncthreads();
+            if (t < kRadix) {
+                uint32_t before = 0;
+                for (int q = 0; q < w; ++q) before += s_tmp[q];
+                s_off[t] = before + inc - cnt;    // first position of digit t
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kItems; ++j) {
+                if (j >= items) break;
+                const uint32_t p = w * sub + (uint32_t)(j * kWave + lane);
+                if (p < L) {
+                    const uint32_t d = dg[j];
+                    const uint32_t np = s_off[d] + cur[w][d] + rank[j];
+                    s_k[np] = key[j];
+                    s_x[np] = (uint16_t)idx[j];
+                }
+            }
+            __syncthreads();
+            uint32_t(*tmp)[kRadix] = cur;
+            cur = nxt;
+            nxt = tmp;
+        }
+        // every value gather of a thread in flight at once
+        uint32_t vout[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+            vout[j] = i < L ? v1[lo + s_x[i]] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+            if (i < L) {
+                k0[lo + i] = s_k[i];
+                v0[lo + i] = vout[j];
+            }
+        }
+        return;
+    }
+
+    // large bucket: 8 stable passes of 8 bits (60-bit keys), (k1, v1) -> (k0, v0)
+    // -> (k1, v1) ..., ending in (k1, v1), then copied to (k0, v0)
+    uint64_t *ks = k1, *kd = k0;
+    uint32_t *vs = v1, *vd = v0;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = pass * kRadixBits;
+        if (t < kRadix) s_off[t] = 0;
+        __syncthreads();
+        for (uint32_t i = t; i < L; i += kBucketThreads)
+            atomicAdd(&s_off[(uint32_t)(ks[lo + i] >> shift) & (kRadix - 1)], 1u);
+        __syncthreads();
+        uint32_t cnt = 0, inc = 0;
+        if (t < kRadix) {
+            cnt = s_off[t];
+            inc = wave_incl_scan_add(cnt);
+            if (lane == kWave - 1) s_tmp[w] = inc;
+        }
+        __syncthreads();
+        if (t < kRadix) {
+            uint32_t before = 0;
+            for (int q = 0; q < w; ++q) before += s_tmp[q];
+            s_off[t] = before + inc - cnt;        // first output slot of digit t
+        }
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < L; c0 += kBucketThreads) {
+            const uint32_t i = c0 + t;
+            const bool valid = i < L;
+            const uint64_t key = valid ? ks[lo + i] : 0ull;
+            const uint32_t val = valid ? vs[lo + i] : 0u;
+            const uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
+            const unsigned long long peers = match_digit(d, valid);
+            const int r = mask_rank(peers);
+            for (int q = t; q < kBucketWaves * kRadix; q += kBucketThreads) (&s_wcnt[0][0])[q] = 0;
+            __syncthreads();
+            if (valid && r == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (t < kRadix) {   // wavefronts before each one, per digit
+                uint32_t x[kBucketWaves];
+#pragma unroll
+                for (int q = 0; q < kBucketWaves; ++q) x[q] = s_wcnt[q][t];
+                uint32_t run = 0;
+#pragma unroll
+                for (int q = 0; q < kBucketWaves; ++q) {
+                    s_wcnt[q][t] = run;
+                    run += x[q];
+                }
+                s_ctot[t] = run;
+            }
+            __syncthreads();
+            if (valid) {
+                const uint32_t pos = s_off[d] + s_wcnt[w][d] + (uint32_t)r;
+                kd[lo + pos] = key;
+                vd[lo + pos] = val;
+            }
+            __syncthreads();
+            if (t < kRadix) s_off[t] += s_ctot[t];
+            __syncthreads();
+        }
+        uint64_t *kt = ks;
+        ks = kd;
+        kd = kt;
+        uint32_t *vt = vs;
+        vs = vd;
+        vd = vt;
+    }
+    for (uint32_t i = t; i < L; i += kBucketThreads) {
+        k0[lo + i] = k1[lo + i];
+        v0[lo + i] = v1[lo + i];
+    }
+}
+
 }  // namespace
 
 hipError_t radix_sort_pairs(bh_ctx *c)
@@ -262,14 +588,14 @@ hipError_t radix_sort_pairs(bh_ctx *c)
         const int shift = by_cluster ? (pass - 8) * kRadixBits : pass * kRadixBits;
         const uint32_t *cl = by_cluster ? c->pcl : nullptr;
         hipLaunchKernelGGL(hist_kernel, dim3(nblk), dim3(kSortThreads), 0, c->stream,
-                           c->key[src], c->val[src], cl, n, shift, hist, nblk);
+                           c->key[src], c->val[src], cl, nullptr, n, shift, hist, nblk);
         BH_LAUNCH_CHECK();
         hipLaunchKernelGGL(scan_digit_kernel, dim3(kRadix), dim3(256), 0, c->stream, hist, nblk,
                            tot);
         BH_LAUNCH_CHECK();
         hipLaunchKernelGGL(scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, c->stream,
-                           c->key[src], c->val[src], c->key[src ^ 1], c->val[src ^ 1], cl, n, shift,
-                           hist, tot, nblk);
+                           c->key[src], c->val[src], c->key[src ^ 1], c->val[src ^ 1], cl, nullptr,
+                           n, shift, hist, tot, nblk);
         BH_LAUNCH_CHECK();
         src ^= 1;
     }
@@ -280,6 +606,45 @@ hipError_t radix_sort_pairs(bh_ctx *c)
         BH_LAUNCH_CHECK();
     }
     return hipSuccess;
+}
+
+hipError_t rebuild_sort_pairs(bh_ctx *c)
+{
+    const int64_t n = c->n;
+    if (!rebuild_buckets(c)) return radix_sort_pairs(c);
+    const int nb = rebuild_buckets(c);
+    const int nblk = (int)((n + kSortTile - 1) / kSortTile);
+    uint32_t *hist = c->blk;
+    uint32_t *tot = c->blk + (int64_t)kRadix * nblk;
+    const uint64_t *cand = c->splt + kRadix;    // written by the keys kernel
+    hipLaunchKernelGGL(splitter_kernel, dim3(1), dim3(kCand), 0, c->stream, cand,
+                       rebuild_candidates(c), nb - 1, c->splt);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hist_kernel, dim3(nblk), dim3(kSortThreads), 0, c->stream, c->key[0],
+                       c->val[0], nullptr, c->splt, n, 0, hist, nblk);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(scan_digit_kernel, dim3(kRadix), dim3(256), 0, c->stream, hist, nblk, tot);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(scatter_kernel, dim3(nblk), dim3(kSortThreads), 0, c->stream, c->key[0],
+                       c->val[0], c->key[1], c->val[1], nullptr, c->splt, n, 0, hist, tot, nblk);
+    BH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(bucket_sort_kernel, dim3(nb), dim3(kBucketThreads), 0, c->stream, c->key[1],
+                       c->val[1], c->key[0], c->val[0], tot);
+    BH_LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+int rebuild_buckets(const bh_ctx *c)
+{
+    // one cluster, and few enough particles for at most kRadix buckets
+    if (c->K != 1 || c->n < 2 || c->n > (int64_t)kRadix * kBucketTarget) return 0;
+    return (int)((c->n + kBucketTarget - 1) / kBucketTarget);
+}
+
+int rebuild_candidates(const bh_ctx *c)
+{
+    const int nb = rebuild_buckets(c);
+    return nb > 1 ? nb * kSplitOver - 1 : 0;
 }
 
 hipError_t compact_flags(bh_ctx *c, const uint8_t *flags, int64_t n, uint32_t *idx,

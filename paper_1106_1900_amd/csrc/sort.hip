@@ -318,36 +318,40 @@ constexpr int kBucketCap = 8192;        // largest bucket sorted in LDS
 constexpr int kBucketThreads = 1024;
 constexpr int kBucketWaves = kBucketThreads / kWave;
 
-// Splitters of nb buckets: the ncand candidate keys (none: one bucket) sorted,
-// every kSplitOver-th kept; kRadix - 1 values, unused ones ~0.  One element per
-// thread; the stages whose partners lie in the same wavefront need no barrier.
+// Splitters of nspl + 1 buckets: the ncand candidate keys in sorted order, every
+// kSplitOver-th kept, kRadix - 1 values with the unused ones ~0.  Each workgroup
+// ranks kSplitOver candidates against all of them (ties by index: ranks are a
+// permutation) and the candidate of rank (b + 1) kSplitOver - 1 becomes splitter
+// b; the grid has kRadix workgroups.
 __global__ void __launch_bounds__(kCand)
 splitter_kernel(const uint64_t *__restrict__ cand, int ncand, int nspl, uint64_t *__restrict__ spl)
 {
-    __shared__ uint64_t s[kCand];
-    const int t = threadIdx.x;
-    s[t] = t < ncand ? cand[t] : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= kCand; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const int l = t ^ j;
-            if (l > t) {
-                const uint64_t a = s[t], b = s[l];
-                if ((a > b) == ((t & k) == 0)) {
-                    s[t] = b;
-                    s[l] = a;
-                }
-            }
-            // a stage at distance j writes elements of other wavefronts when
-            // j >= kWave, and the next one (distance j / 2, or k to open the next
-            // round) reads them when its distance is >= kWave
-            const int jn = j > 1 ? (j >> 1) : k;
-            if (j >= kWave || jn >= kWave) __syncthreads();
-            else wave_sync();
+    __shared__ uint32_t s_cnt[kSplitOver][kCand / kWave];
+    const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+    const uint64_t mine = t < ncand ? cand[t] : 0ull;
+#pragma unroll
+    for (int q = 0; q < kSplitOver; ++q) {
+        const int c = blockIdx.x * kSplitOver + q;      // the candidate ranked
+        uint32_t below = 0;
+        if (c < ncand && t < ncand) {
+            const uint64_t v = cand[c];
+            below = (mine < v || (mine == v && t < c)) ? 1u : 0u;
         }
+        below = wave_sum_u32(below);
+        if (lane == 0) s_cnt[q][w] = below;
     }
     __syncthreads();
-    if (t < kRadix - 1) spl[t] = t < nspl ? s[(t + 1) * kSplitOver - 1] : ~0ull;
+    if (t < kSplitOver) {
+        const int c = blockIdx.x * kSplitOver + t;
+        if (c < ncand) {
+            uint32_t r = 0;
+            for (int q = 0; q < kCand / kWave; ++q) r += s_cnt[t][q];
+            if ((r + 1) % kSplitOver == 0 && (int)(r / kSplitOver) < nspl)
+                spl[r / kSplitOver] = cand[c];
+        }
+    }
+    if (blockIdx.x == 0)
+        for (int b = nspl + t; b < kRadix - 1; b += kCand) spl[b] = ~0ull;
 }
 
 // One workgroup per bucket: the bucket's pairs (k1, v1)[lo, lo + L), in caller
@@ -617,7 +621,7 @@ hipError_t rebuild_sort_pairs(bh_ctx *c)
     uint32_t *hist = c->blk;
     uint32_t *tot = c->blk + (int64_t)kRadix * nblk;
     const uint64_t *cand = c->splt + kRadix;    // written by the keys kernel
-    hipLaunchKernelGGL(splitter_kernel, dim3(1), dim3(kCand), 0, c->stream, cand,
+    hipLaunchKernelGGL(splitter_kernel, dim3(kRadix), dim3(kCand), 0, c->stream, cand,
                        rebuild_candidates(c), nb - 1, c->splt);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(hist_kernel, dim3(nblk), dim3(kSortThreads), 0, c->stream, c->key[0],

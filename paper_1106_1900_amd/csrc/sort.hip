@@ -314,7 +314,7 @@ compact_down_kernel(const uint8_t *__restrict__ flags, int64_t n, const uint32_t
 // same result as the stable radix sort of all 60 key bits.
 
 constexpr int kBucketTarget = 4096;     // mean bucket size the bucket count aims at
-constexpr int kBucketCap = 8192;        // largest bucket sorted in LDS
+constexpr int kBucketCap = 12288;       // largest bucket sorted in LDS
 constexpr int kBucketThreads = 1024;
 constexpr int kBucketWaves = kBucketThreads / kWave;
 
@@ -431,20 +431,21 @@ bucket_sort_kernel(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1, uint64_
             uint32_t idx[kItems], rank[kItems], dg[kItems];
 #pragma unroll
             for (int j = 0; j < kItems; ++j) {
-                if (j >= items) break;      // uniform
-                const uint32_t p = w * sub + (uint32_t)(j * kWave + lane);
-                const bool valid = p < L;
-                key[j] = valid ? s_k[p] : 0ull;
-                idx[j] = valid ? s_x[p] : 0u;
-                const uint32_t d = (uint32_t)(key[j] >> shift) & (kRadix - 1);
-                dg[j] = d;
-                const unsigned long long peers = match_digit(d, valid);
-                const int r = mask_rank(peers);
-                const uint32_t before = j == 0 ? 0u : cur[w][d];
-                rank[j] = before + (uint32_t)r;
-                wave_sync();
-                if (valid && r == 0) cur[w][d] = before + (uint32_t)__popcll(peers);
-                wave_sync();
+                if (j < items) {    // uniform
+                    const uint32_t p = w * sub + (uint32_t)(j * kWave + lane);
+                    const bool valid = p < L;
+                    key[j] = valid ? s_k[p] : 0ull;
+                    idx[j] = valid ? s_x[p] : 0u;
+                    const uint32_t d = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+                    dg[j] = d;
+                    const unsigned long long peers = match_digit(d, valid);
+                    const int r = mask_rank(peers);
+                    const uint32_t before = j == 0 ? 0u : cur[w][d];
+                    rank[j] = before + (uint32_t)r;
+                    wave_sync();
+                    if (valid && r == 0) cur[w][d] = before + (uint32_t)__popcll(peers);
+                    wave_sync();
+                }
             }
             for (int q = t; q < kBucketWaves * kRadix; q += kBucketThreads) (&nxt[0][0])[q] = 0;
             __syncthreads();
@@ -472,9 +473,8 @@ bucket_sort_kernel(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1, uint64_
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < kItems; ++j) {
-                if (j >= items) break;
                 const uint32_t p = w * sub + (uint32_t)(j * kWave + lane);
-                if (p < L) {
+                if (j < items && p < L) {
                     const uint32_t d = dg[j];
                     const uint32_t np = s_off[d] + cur[w][d] + rank[j];
                     s_k[np] = key[j];

@@ -50,17 +50,19 @@ def test_bucket_count_limit(n):
     ctx.close()
 
 
-def test_bucket_larger_than_lds_is_sorted_by_its_own_passes():
-    # 12,000 of 30,000 particles moved onto one point: one key, one bucket of more
-    # than the 8192 pairs sorted in LDS; ties in caller order
+@pytest.mark.parametrize("ncoin", [10_000, 16_000])
+def test_large_buckets_of_equal_keys(ncoin):
+    # ncoin of 30,000 particles moved onto one point: one key, one bucket of 8,192
+    # to 12,288 pairs (the largest sorted in LDS) or of more (sorted by the
+    # bucket's workgroup through device memory); ties in caller order
     n = 30_000
     pos, vel, m = workloads.plummer(n, 21)
     ctx = gpu_build(pos, m)
     new = pos.copy()
     rng = np.random.default_rng(5)
-    sel = rng.choice(n, 12_000, replace=False)
+    sel = rng.choice(n, ncoin, replace=False)
     new[sel] = new[sel[0]]
-    say("case rebuild-sort large bucket")
+    say("case rebuild-sort large bucket", ncoin)
     ctx.set_state(to_dev(new), to_dev(vel))
     ctx.compute_forces(0.6, 0.01, want=False)
     ex = ctx.export_tree()

@@ -220,14 +220,16 @@ domain_kernel(const double *__restrict__ part, const DevCluster *__restrict__ cl
 // are the caller order, a first load) with value i.  The stable sort that
 // follows then orders equal keys by caller index, on a first load and on every
 // rebuild alike (App. A: the split primitive keeps the input order).  With
-// ncand > 0 the keys at positions (c + 1) cstride, c < ncand, are also written
-// to cand[c] (the candidate splitters of a rebuild's sort).
+// held != 0 the pair goes to slot i instead (a rebuild's bucket sort, which
+// orders equal keys by pid itself).  With ncand > 0 the keys at positions
+// (c + 1) cstride, c < ncand, are also written to cand[c] (the candidate
+// splitters of that sort).
 template <typename Src>
 __global__ void __launch_bounds__(kBlock)
 keys_kernel(Src src, const Chunk *__restrict__ chunks, const DevDomain *__restrict__ dom,
             const uint32_t *__restrict__ pid, uint32_t n, uint64_t *__restrict__ key,
-            uint32_t *__restrict__ val, uint64_t *__restrict__ cand, uint32_t ncand,
-            uint32_t cstride, DevMisc *m)
+            uint32_t *__restrict__ val, uint32_t held, uint64_t *__restrict__ cand,
+            uint32_t ncand, uint32_t cstride, DevMisc *m)
 {
     const Chunk ch = chunks[blockIdx.x];
     const DevDomain &cl = dom[ch.cluster];
@@ -243,7 +245,7 @@ keys_kernel(Src src, const Chunk *__restrict__ chunks, const DevDomain *__restri
             const uint32_t i = i0 + (uint32_t)u * kBlock;
             if (i < ch.end) {
                 src.get3(i, v[u]);
-                o[u] = pid ? pid[i] : i;
+                o[u] = pid && !held ? pid[i] : i;
             }
         }
 #pragma unroll
@@ -1134,14 +1136,16 @@ hipError_t launch_keys(bh_ctx *c, const double *pos_aos)
     if (pos_aos)
         hipLaunchKernelGGL(keys_kernel<AosSrc>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
                            c->stream, AosSrc{pos_aos}, c->chunks, c->dom, nullptr, (uint32_t)c->n,
-                           c->key[0], c->val[0], nullptr, 0u, 0u, c->misc);
+                           c->key[0], c->val[0], 0u, nullptr, 0u, 0u, c->misc);
     else {
-        // a rebuild: the candidate splitters of its sort, at a fixed stride
+        // a rebuild: held-order pairs and the candidate splitters for its bucket
+        // sort, at a fixed stride (or caller-order pairs for the radix sort)
+        const uint32_t held = rebuild_buckets(c) > 0 ? 1u : 0u;
         const uint32_t ncand = (uint32_t)rebuild_candidates(c);
         const uint32_t cstride = ncand ? (uint32_t)(c->n / (ncand + 1)) : 0u;
         hipLaunchKernelGGL(keys_kernel<P4Src>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
                            c->stream, P4Src{c->p4[c->cur]}, c->chunks, c->dom, c->pid[c->cur],
-                           (uint32_t)c->n, c->key[0], c->val[0], c->splt + kRadix, ncand,
+                           (uint32_t)c->n, c->key[0], c->val[0], held, c->splt + kRadix, ncand,
                            cstride, c->misc);
     }
     BH_LAUNCH_CHECK();

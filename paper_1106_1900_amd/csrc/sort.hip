@@ -309,9 +309,10 @@ compact_down_kernel(const uint8_t *__restrict__ flags, int64_t n, const uint32_t
 // that order (the candidates, written by the keys kernel) split the new key
 // range into buckets of similar size.  One stable pass places the pairs by
 // bucket (the same three kernels as a radix pass, with the bucket as the digit),
-// and one workgroup per bucket sorts it by key, stably.  The pairs arrive in
-// caller order, which both steps keep, so equal keys end in caller order: the
-// same result as the stable radix sort of all 60 key bits.
+// and one workgroup per bucket sorts it by key, stably.  The pairs arrive in the
+// held order (the keys kernel writes them without the scatter to caller order);
+// a bucket holding equal keys orders them by caller index, so the result is the
+// stable radix sort's of the pairs in caller order, bit for bit.
 
 constexpr int kBucketTarget = 4096;     // mean bucket size the bucket count aims at
 constexpr int kBucketCap = 12288;       // largest bucket sorted in LDS
@@ -354,15 +355,19 @@ splitter_kernel(const uint64_t *__restrict__ cand, int ncand, int nspl, uint64_t
         for (int b = nspl + t; b < kRadix - 1; b += kCand) spl[b] = ~0ull;
 }
 
-// One workgroup per bucket: the bucket's pairs (k1, v1)[lo, lo + L), in caller
-// order, are sorted stably by key into (k0, v0)[lo, lo + L).  Up to kBucketCap
-// pairs are sorted in LDS by stable 8-bit passes (keys and positions move, values
-// are gathered at the end), skipping the digits every key of the bucket shares; a
-// larger bucket (many equal or clustered keys) is sorted by the workgroup with the
-// same passes through (k0, v0) and back.
+// One workgroup per bucket: the bucket's pairs (k1, v1)[lo, lo + L) are sorted
+// stably by key into (k0, v0)[lo, lo + L).  With pid == NULL the pairs arrive in
+// caller order; otherwise in the held order (value = held position, pid[value] =
+// caller index), and equal keys are put in caller order explicitly.  Up to
+// kBucketCap pairs are sorted in LDS by stable 8-bit passes (keys and positions
+// move, values are gathered at the end), skipping the digits every key of the
+// bucket shares; a bucket holding equal keys is then sorted again, by caller index
+// first and by key after it.  A larger bucket (many equal or clustered keys) is
+// sorted by the workgroup with the same passes through (k0, v0) and back.
 __global__ void __launch_bounds__(kBucketThreads)
 bucket_sort_kernel(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1, uint64_t *__restrict__ k0,
-                   uint32_t *__restrict__ v0, const uint32_t *__restrict__ tot)
+                   uint32_t *__restrict__ v0, const uint32_t *__restrict__ tot,
+                   const uint32_t *__restrict__ pid)
 {
     constexpr int kItems = kBucketCap / kBucketThreads;   // most pairs per thread in LDS
     __shared__ uint64_t s_k[kBucketCap];
@@ -380,111 +385,154 @@ bucket_sort_kernel(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1, uint64_
         uint32_t x = 0;
         for (int d = lane; d < b; d += kWave) x += tot[d];
         x = wave_sum_u32(x);
-        if (lane == 0) {
-            s_lo = x;
-            s_or = 0ull;
-            s_and = ~0ull;
-        }
+        if (lane == 0) s_lo = x;
     }
     __syncthreads();
     const int64_t lo = s_lo;
     const uint32_t L = tot[b];
 
     if (L <= (uint32_t)kBucketCap) {
-        // all of a thread's loads first, then the LDS stores
-        uint64_t kin[kItems];
-#pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const uint32_t i = (uint32_t)(j * kBucketThreads + t);
-            kin[j] = i < L ? k1[lo + i] : 0ull;
-        }
-        unsigned long long o = 0ull, a = ~0ull;
-#pragma unroll
-        for (int j = 0; j < kItems; ++j) {
-            const uint32_t i = (uint32_t)(j * kBucketThreads + t);
-            if (i < L) {
-                s_k[i] = kin[j];
-                s_x[i] = (uint16_t)i;
-                o |= kin[j];
-                a &= kin[j];
-            }
-        }
-        o = wave_or_u64(o);
-        a = wave_and_u64(a);
-        if (lane == 0) {
-            atomicOr(&s_or, o);
-            atomicAnd(&s_and, a);
-        }
-        for (int q = t; q < kBucketWaves * kRadix; q += kBucketThreads) (&s_wcnt[0][0])[q] = 0;
-        __syncthreads();
-        const uint64_t vary = s_or ^ s_and;     // bits that differ within the bucket
         const int items = (int)((L + kBucketThreads - 1) / kBucketThreads);
         const uint32_t sub = (uint32_t)items * kWave;      // a wavefront's positions
-        uint32_t(*cur)[kRadix] = s_wcnt;       // counts of this pass (zero at its start)
-        uint32_t(*nxt)[kRadix] = s_wcnt2;      // cleared during this pass for the next one
-        for (int pass = 0; pass < 8; ++pass) {
-            const int shift = pass * kRadixBits;
-            if (((vary >> shift) & (kRadix - 1)) == 0) continue;    // one digit: order kept
-            // thread (w, lane) takes positions w sub + j kWave + lane: position
-            // order is (wavefront, j, lane) order, which the ranks below keep
-            uint64_t key[kItems];
-            uint32_t idx[kItems], rank[kItems], dg[kItems];
+        uint32_t(*cur)[kRadix] = s_wcnt;       // counts of a pass (zero at its start)
+        uint32_t(*nxt)[kRadix] = s_wcnt2;      // cleared during a pass for the next one
+        // s_k[i] = v[j] for positions i = j kBucketThreads + t < L, s_x[i] = i, with
+        // every load of the thread in flight at once; returns the bits in which
+        // the values differ
+        auto load = [&](const uint64_t(&v)[kItems]) -> uint64_t {
+            __syncthreads();        // earlier readers of s_k, s_x, s_or and s_and are done
+            unsigned long long o = 0ull, a = ~0ull;
 #pragma unroll
             for (int j = 0; j < kItems; ++j) {
-                if (j < items) {    // uniform
+                const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+                if (i < L) {
+                    s_k[i] = v[j];
+                    s_x[i] = (uint16_t)i;
+                    o |= v[j];
+                    a &= v[j];
+                }
+            }
+            o = wave_or_u64(o);
+            a = wave_and_u64(a);
+            if (t == 0) {
+                s_or = 0ull;
+                s_and = ~0ull;
+            }
+            for (int q = t; q < kBucketWaves * kRadix; q += kBucketThreads) (&cur[0][0])[q] = 0;
+            __syncthreads();
+            if (lane == 0) {
+                atomicOr(&s_or, o);
+                atomicAnd(&s_and, a);
+            }
+            __syncthreads();
+            return s_or ^ s_and;
+        };
+        // stable 8-bit passes over the bytes of s_k in which vary has bits
+        auto passes = [&](uint64_t vary) {
+            for (int pass = 0; pass < 8; ++pass) {
+                const int shift = pass * kRadixBits;
+                if (((vary >> shift) & (kRadix - 1)) == 0) continue;    // one digit: order kept
+                // thread (w, lane) takes positions w sub + j kWave + lane: position
+                // order is (wavefront, j, lane) order, which the ranks below keep
+                uint64_t key[kItems];
+                uint32_t idx[kItems], rank[kItems], dg[kItems];
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) {
+                    if (j < items) {    // uniform
+                        const uint32_t p = w * sub + (uint32_t)(j * kWave + lane);
+                        const bool valid = p < L;
+                        key[j] = valid ? s_k[p] : 0ull;
+                        idx[j] = valid ? s_x[p] : 0u;
+                        const uint32_t d = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+                        dg[j] = d;
+                        const unsigned long long peers = match_digit(d, valid);
+                        const int r = mask_rank(peers);
+                        const uint32_t before = j == 0 ? 0u : cur[w][d];
+                        rank[j] = before + (uint32_t)r;
+                        wave_sync();
+                        if (valid && r == 0) cur[w][d] = before + (uint32_t)__popcll(peers);
+                        wave_sync();
+                    }
+                }
+                for (int q = t; q < kBucketWaves * kRadix; q += kBucketThreads) (&nxt[0][0])[q] = 0;
+                __syncthreads();
+                uint32_t cnt = 0, inc = 0;
+                if (t < kRadix) {   // wavefronts before each one, per digit; digit totals
+                    uint32_t x[kBucketWaves];
+#pragma unroll
+                    for (int q = 0; q < kBucketWaves; ++q) x[q] = cur[q][t];
+                    uint32_t run = 0;
+#pragma unroll
+                    for (int q = 0; q < kBucketWaves; ++q) {
+                        cur[q][t] = run;
+                        run += x[q];
+                    }
+                    cnt = run;
+                    inc = wave_incl_scan_add(cnt);
+                    if (lane == kWave - 1) s_tmp[w] = inc;
+                }
+                __syncthreads();
+                if (t < kRadix) {
+                    uint32_t before = 0;
+                    for (int q = 0; q < w; ++q) before += s_tmp[q];
+                    s_off[t] = before + inc - cnt;    // first position of digit t
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) {
                     const uint32_t p = w * sub + (uint32_t)(j * kWave + lane);
-                    const bool valid = p < L;
-                    key[j] = valid ? s_k[p] : 0ull;
-                    idx[j] = valid ? s_x[p] : 0u;
-                    const uint32_t d = (uint32_t)(key[j] >> shift) & (kRadix - 1);
-                    dg[j] = d;
-                    const unsigned long long peers = match_digit(d, valid);
-                    const int r = mask_rank(peers);
-                    const uint32_t before = j == 0 ? 0u : cur[w][d];
-                    rank[j] = before + (uint32_t)r;
-                    wave_sync();
-                    if (valid && r == 0) cur[w][d] = before + (uint32_t)__popcll(peers);
-                    wave_sync();
+                    if (j < items && p < L) {
+                        const uint32_t d = dg[j];
+                        const uint32_t np = s_off[d] + cur[w][d] + rank[j];
+                        s_k[np] = key[j];
+                        s_x[np] = (uint16_t)idx[j];
+                    }
                 }
+                __syncthreads();
+                uint32_t(*tmp)[kRadix] = cur;
+                cur = nxt;
+                nxt = tmp;
             }
-            for (int q = t; q < kBucketWaves * kRadix; q += kBucketThreads) (&nxt[0][0])[q] = 0;
-            __syncthreads();
-            uint32_t cnt = 0, inc = 0;
-            if (t < kRadix) {   // wavefronts before each one, per digit; digit totals
-                uint32_t x[kBucketWaves];
+        };
+
+        uint64_t v[kItems];
 #pragma unroll
-                for (int q = 0; q < kBucketWaves; ++q) x[q] = cur[q][t];
-                uint32_t run = 0;
+        for (int j = 0; j < kItems; ++j) {
+            const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+            v[j] = i < L ? k1[lo + i] : 0ull;
+        }
+        passes(load(v));
+        if (pid) {
+            // equal keys, if any, are still in the held order
+            bool tie = false;
+            for (uint32_t i = t; i + 1 < L; i += kBucketThreads) tie |= s_k[i] == s_k[i + 1];
+            if (__syncthreads_or(tie)) {
 #pragma unroll
-                for (int q = 0; q < kBucketWaves; ++q) {
-                    cur[q][t] = run;
-                    run += x[q];
+                for (int j = 0; j < kItems; ++j) {
+                    const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+                    v[j] = i < L ? (uint64_t)pid[v1[lo + i]] : 0ull;
                 }
-                cnt = run;
-                inc = wave_incl_scan_add(cnt);
-                if (lane == kWave - 1) s_tmp[w] = inc;
-            }
-            __syncthreads();
-            if (t < kRadix) {
-                uint32_t before = 0;
-                for (int q = 0; q < w; ++q) before += s_tmp[q];
-                s_off[t] = before + inc - cnt;    // first position of digit t
-            }
-            __syncthreads();
+                passes(load(v));        // by caller index
 #pragma unroll
-            for (int j = 0; j < kItems; ++j) {
-                const uint32_t p = w * sub + (uint32_t)(j * kWave + lane);
-                if (j < items && p < L) {
-                    const uint32_t d = dg[j];
-                    const uint32_t np = s_off[d] + cur[w][d] + rank[j];
-                    s_k[np] = key[j];
-                    s_x[np] = (uint16_t)idx[j];
+                for (int j = 0; j < kItems; ++j) {
+                    const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+                    v[j] = i < L ? k1[lo + s_x[i]] : 0ull;
                 }
+                uint16_t x[kItems];
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) {
+                    const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+                    x[j] = i < L ? s_x[i] : 0;
+                }
+                const uint64_t vary = load(v);      // keys in caller-index order ...
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) {  // ... with their own positions
+                    const uint32_t i = (uint32_t)(j * kBucketThreads + t);
+                    if (i < L) s_x[i] = x[j];
+                }
+                __syncthreads();
+                passes(vary);           // then by key
             }
-            __syncthreads();
-            uint32_t(*tmp)[kRadix] = cur;
-            cur = nxt;
-            nxt = tmp;
         }
         // every value gather of a thread in flight at once
         uint32_t vout[kItems];
@@ -504,16 +552,24 @@ bucket_sort_kernel(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1, uint64_
         return;
     }
 
-    // large bucket: 8 stable passes of 8 bits (60-bit keys), (k1, v1) -> (k0, v0)
-    // -> (k1, v1) ..., ending in (k1, v1), then copied to (k0, v0)
+    // Large bucket: stable passes through device memory, (k1, v1) -> (k0, v0) ->
+    // (k1, v1) ...: with pid, three passes on the caller index (below 2^24) first,
+    // then eight on the 60-bit keys; the result is copied to (k0, v0) if it ends in
+    // (k1, v1).
     uint64_t *ks = k1, *kd = k0;
     uint32_t *vs = v1, *vd = v0;
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = pass * kRadixBits;
+    const int npid = pid ? 3 : 0;
+    for (int pass = 0; pass < npid + 8; ++pass) {
+        const bool by_pid = pass < npid;
+        const int shift = (by_pid ? pass : pass - npid) * kRadixBits;
+        auto digit = [&](uint64_t key, uint32_t val) -> uint32_t {
+            return by_pid ? (pid[val] >> shift) & (kRadix - 1)
+                          : (uint32_t)(key >> shift) & (kRadix - 1);
+        };
         if (t < kRadix) s_off[t] = 0;
         __syncthreads();
         for (uint32_t i = t; i < L; i += kBucketThreads)
-            atomicAdd(&s_off[(uint32_t)(ks[lo + i] >> shift) & (kRadix - 1)], 1u);
+            atomicAdd(&s_off[digit(ks[lo + i], vs[lo + i])], 1u);
         __syncthreads();
         uint32_t cnt = 0, inc = 0;
         if (t < kRadix) {
@@ -533,7 +589,7 @@ bucket_sort_kernel(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1, uint64_
             const bool valid = i < L;
             const uint64_t key = valid ? ks[lo + i] : 0ull;
             const uint32_t val = valid ? vs[lo + i] : 0u;
-            const uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
+            const uint32_t d = valid ? digit(key, val) : 0u;
             const unsigned long long peers = match_digit(d, valid);
             const int r = mask_rank(peers);
             for (int q = t; q < kBucketWaves * kRadix; q += kBucketThreads) (&s_wcnt[0][0])[q] = 0;
@@ -569,9 +625,11 @@ bucket_sort_kernel(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1, uint64_
         vs = vd;
         vd = vt;
     }
-    for (uint32_t i = t; i < L; i += kBucketThreads) {
-        k0[lo + i] = k1[lo + i];
-        v0[lo + i] = v1[lo + i];
+    if (ks != k0) {
+        for (uint32_t i = t; i < L; i += kBucketThreads) {
+            k0[lo + i] = ks[lo + i];
+            v0[lo + i] = vs[lo + i];
+        }
     }
 }
 
@@ -633,7 +691,7 @@ hipError_t rebuild_sort_pairs(bh_ctx *c)
                        c->val[0], c->key[1], c->val[1], nullptr, c->splt, n, 0, hist, tot, nblk);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(bucket_sort_kernel, dim3(nb), dim3(kBucketThreads), 0, c->stream, c->key[1],
-                       c->val[1], c->key[0], c->val[0], tot);
+                       c->val[1], c->key[0], c->val[0], tot, c->pid[c->cur]);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -138,6 +138,7 @@ struct bh_ctx {
     int32_t mac = 0;              // opening test bh_build_tree gives its cluster
     bool moved = false;           // positions drifted since the last build or refit
     bool refitted = false;        // the cells' moments were refitted since the last build
+    bool box_ready = false;       // bb_part holds the held positions' partials (a step's drift)
     bool rec_fresh = false;       // the walk records were written by the last moments pass with
                                   // the cluster table's current theta and opening test
     int64_t layout = 0;     // changes whenever buffers or the cluster table change
@@ -367,6 +368,50 @@ __device__ __forceinline__ uint32_t lane_value(uint32_t v, int i)
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 {
     return lane_value(wave_incl_scan_add(v), kWave - 1);
+}
+
+// The first kernel of a build clears the build's counts (the error bits stay
+// until the host reads and clears them).
+__device__ __forceinline__ void reset_build_counts(DevMisc *m)
+{
+    m->nleaves = 0;
+    m->ngroups = 0;
+    m->walk_next = 0;
+    m->ncells = 0;
+    m->levels_done = 0;
+}
+
+constexpr int kChunkThreads = 256;     // workgroup size of the per-chunk kernels
+
+// A kChunkThreads workgroup's minima lo and maxima hi of the three axes into
+// part[6 blockIdx.x + k] (k = 0..2 minima, 3..5 maxima); a non-finite
+// coordinate seen by any thread (bad) sets bit 0 of the error flags.
+__device__ __forceinline__ void box_partial(double lo[3], double hi[3], bool bad,
+                                            double *__restrict__ part, DevMisc *m)
+{
+    __shared__ double s_v[6][kChunkThreads / kWave];
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double a = lo[k], b = hi[k];
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            a = fmin(a, __shfl_xor(a, d, kWave));
+            b = fmax(b, __shfl_xor(b, d, kWave));
+        }
+        if (l == 0) {
+            s_v[k][w] = a;
+            s_v[3 + k][w] = b;
+        }
+    }
+    if (ballot(bad) && l == 0) atomicOr(&m->nonfinite, 1u);
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double a = s_v[k][0];
+        for (int i = 1; i < kChunkThreads / kWave; ++i) a = k < 3 ? fmin(a, s_v[k][i]) : fmax(a, s_v[k][i]);
+        part[6 * (int64_t)blockIdx.x + k] = a;
+    }
 }
 
 template <typename T>

@@ -44,6 +44,7 @@ namespace bh {
 namespace {
 
 constexpr int kBlock = 256;
+static_assert(kBlock == kChunkThreads, "per-chunk kernels share box_partial");
 constexpr int kFixedGrid = 2048;       // grid of the kernels that read their size on the device
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v)
@@ -109,20 +110,13 @@ cluster_ids_kernel(const Chunk *__restrict__ chunks, uint32_t *__restrict__ pcl)
 }
 
 // Per-chunk minima and maxima of each axis: part[6 b + k], k = 0..2 minima, 3..5
-// maxima.  A non-finite coordinate sets bit 0 of the misc flags.
+// maxima.  A non-finite coordinate sets bit 0 of the misc flags.  (A leapfrog
+// step's kick-drift kernel writes the same partials of the drifted positions.)
 template <typename Src>
 __global__ void __launch_bounds__(kBlock)
 bbox_kernel(Src src, const Chunk *__restrict__ chunks, double *__restrict__ part, DevMisc *m)
 {
-    // the first kernel of a build also clears the build's counts (the error bits
-    // stay until the host reads and clears them)
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        m->nleaves = 0;
-        m->ngroups = 0;
-        m->walk_next = 0;
-        m->ncells = 0;
-        m->levels_done = 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) reset_build_counts(m);
     const Chunk ch = chunks[blockIdx.x];
     double lo[3] = {INFINITY, INFINITY, INFINITY};
     double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -137,29 +131,7 @@ bbox_kernel(Src src, const Chunk *__restrict__ chunks, double *__restrict__ part
             hi[k] = fmax(hi[k], v[k]);
         }
     }
-    __shared__ double s_v[6][kBlock / kWave];
-    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        double a = lo[k], b = hi[k];
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) {
-            a = fmin(a, __shfl_xor(a, d, kWave));
-            b = fmax(b, __shfl_xor(b, d, kWave));
-        }
-        if (l == 0) {
-            s_v[k][w] = a;
-            s_v[3 + k][w] = b;
-        }
-    }
-    if (ballot(bad) && l == 0) atomicOr(&m->nonfinite, 1u);
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        const int k = threadIdx.x;
-        double a = s_v[k][0];
-        for (int i = 1; i < kBlock / kWave; ++i) a = k < 3 ? fmin(a, s_v[k][i]) : fmax(a, s_v[k][i]);
-        part[6 * (int64_t)blockIdx.x + k] = a;
-    }
+    box_partial(lo, hi, bad, part, m);
 }
 
 // One block per cluster: reduce its chunk partials; cube side = largest extent
@@ -1118,7 +1090,10 @@ hipError_t launch_cluster_ids(bh_ctx *c)
 
 hipError_t launch_domain(bh_ctx *c, const double *pos_aos)
 {
-    if (pos_aos)
+    if (!pos_aos && c->box_ready) {
+        // the partials of the held positions came with the step's drift
+        c->box_ready = false;
+    } else if (pos_aos)
         hipLaunchKernelGGL(bbox_kernel<AosSrc>, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
                            c->stream, AosSrc{pos_aos}, c->chunks, c->bb_part, c->misc);
     else

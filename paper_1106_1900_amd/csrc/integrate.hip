@@ -9,31 +9,60 @@ namespace bh {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRedBlocks = 1024;
+static_assert(kBlock == kChunkThreads, "per-chunk kernels share box_partial");
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// v += a h; x += v dt in one pass (the first half of a kick-drift-kick step)
+// The kick-drift of a leapfrog step, one workgroup per chunk (each chunk in one
+// cluster), with the chunk's bounding-box partials of the drifted positions for
+// the rebuild that follows (the partials and error bit of bbox_kernel).
 __global__ void __launch_bounds__(kBlock)
-kick_drift_kernel(int64_t n, const uint32_t *__restrict__ pcl, const DevCluster *__restrict__ clus,
-                  const float4 *__restrict__ acc4, double4 *__restrict__ v4,
-                  double4 *__restrict__ p4)
+kick_drift_box_kernel(const Chunk *__restrict__ chunks, const DevCluster *__restrict__ clus,
+                      const float4 *__restrict__ acc4, double4 *__restrict__ v4,
+                      double4 *__restrict__ p4, double *__restrict__ part, DevMisc *m)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const double dt = clus[pcl[i]].dt;
+    if (blockIdx.x == 0 && threadIdx.x == 0) reset_build_counts(m);
+    const Chunk ch = chunks[blockIdx.x];
+    const double dt = clus[ch.cluster].dt;
     const double h = 0.5 * dt;
-    const float4 a = acc4[i];
-    double4 v = v4[i];
-    v.x = v.x + (double)a.x * h;
-    v.y = v.y + (double)a.y * h;
-    v.z = v.z + (double)a.z * h;
-    v4[i] = v;
-    double4 p = p4[i];
-    p.x = p.x + v.x * dt;
-    p.y = p.y + v.y * dt;
-    p.z = p.z + v.z * dt;
-    p4[i] = p;
+    double lo[3] = {INFINITY, INFINITY, INFINITY};
+    double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    constexpr int kU = 4;       // particles of a thread in flight at once
+    for (uint32_t i0 = ch.begin + threadIdx.x; i0 < ch.end; i0 += kU * kBlock) {
+        float4 a[kU];
+        double4 v[kU], p[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * kBlock;
+            if (i < ch.end) {
+                a[u] = acc4[i];
+                v[u] = v4[i];
+                p[u] = p4[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * kBlock;
+            if (i >= ch.end) continue;
+            v[u].x = v[u].x + (double)a[u].x * h;
+            v[u].y = v[u].y + (double)a[u].y * h;
+            v[u].z = v[u].z + (double)a[u].z * h;
+            v4[i] = v[u];
+            p[u].x = p[u].x + v[u].x * dt;
+            p[u].y = p[u].y + v[u].y * dt;
+            p[u].z = p[u].z + v[u].z * dt;
+            p4[i] = p[u];
+            const double x[3] = {p[u].x, p[u].y, p[u].z};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                bad |= !isfinite(x[k]);
+                lo[k] = fmin(lo[k], x[k]);
+                hi[k] = fmax(hi[k], x[k]);
+            }
+        }
+    }
+    box_partial(lo, hi, bad, part, m);
 }
 
 // x += v dt for every particle (a drift without rebuilding the tree)
@@ -211,9 +240,11 @@ state_out_kernel(int64_t n, const double4 *__restrict__ p4, const double4 *__res
 
 hipError_t launch_kick_drift(bh_ctx *c)
 {
-    hipLaunchKernelGGL(kick_drift_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n,
-                       c->pcl, c->clus, c->acc4, c->v4[c->cur], c->p4[c->cur]);
+    hipLaunchKernelGGL(kick_drift_box_kernel, dim3((unsigned)c->nchunks), dim3(kBlock), 0,
+                       c->stream, c->chunks, c->clus, c->acc4, c->v4[c->cur], c->p4[c->cur],
+                       c->bb_part, c->misc);
     BH_LAUNCH_CHECK();
+    c->box_ready = true;        // the rebuild that follows skips its bbox pass
     return hipSuccess;
 }
 

@@ -15,6 +15,8 @@
 //               coalesced at digit base + block offset + rank.
 #include "bh_internal.h"
 
+#include <algorithm>
+
 namespace bh {
 namespace {
 
@@ -264,28 +266,19 @@ scan_reduce_kernel(const T *__restrict__ in, int64_t n, uint32_t *__restrict__ p
     if (threadIdx.x == 0) part[blockIdx.x] = sum;
 }
 
-__global__ void __launch_bounds__(256)
-scan_partials_kernel(uint32_t *__restrict__ part, int nblk, uint32_t *__restrict__ total)
-{
-    __shared__ uint32_t s_tmp[4];
-    uint32_t run = 0;
-    for (int b0 = 0; b0 < nblk; b0 += 256) {
-        int b = b0 + threadIdx.x;
-        uint32_t v = b < nblk ? part[b] : 0u;
-        uint32_t sum;
-        uint32_t ex = block_excl_scan_256(v, s_tmp, &sum);
-        if (b < nblk) part[b] = run + ex;
-        run += sum;
-    }
-    if (threadIdx.x == 0 && total) *total = run;
-}
-
-// Writes the positions of set flags, in order, to idx[0..count).
+// Writes the positions of set flags, in order, to idx[0..count).  Each block
+// adds up the counts of the blocks before it (part: per-block counts from
+// scan_reduce_kernel); the last block also writes the total to *count.
 __global__ void __launch_bounds__(kScanThreads)
 compact_down_kernel(const uint8_t *__restrict__ flags, int64_t n, const uint32_t *__restrict__ part,
-                    uint32_t *__restrict__ idx)
+                    uint32_t *__restrict__ idx, uint32_t *__restrict__ count)
 {
     __shared__ uint32_t s_tmp[4];
+    uint32_t before = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kScanThreads) before += part[b];
+    uint32_t sum;
+    block_excl_scan_256(before, s_tmp, &sum);
+    before = sum;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
@@ -294,8 +287,8 @@ compact_down_kernel(const uint8_t *__restrict__ flags, int64_t n, const uint32_t
         v[k] = base + k < n ? (uint32_t)(flags[base + k] != 0) : 0u;
         s += v[k];
     }
-    uint32_t sum;
-    uint32_t run = part[blockIdx.x] + block_excl_scan_256(s, s_tmp, &sum);
+    uint32_t run = before + block_excl_scan_256(s, s_tmp, &sum);
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *count = before + sum;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (v[k]) idx[run++] = (uint32_t)(base + k);
@@ -712,15 +705,14 @@ int rebuild_candidates(const bh_ctx *c)
 hipError_t compact_flags(bh_ctx *c, const uint8_t *flags, int64_t n, uint32_t *idx,
                          uint32_t *count)
 {
-    const int nblk = (int)((n + kScanTile - 1) / kScanTile);
+    // one block at least, so that the count is written for n = 0 too
+    const int nblk = std::max(1, (int)((n + kScanTile - 1) / kScanTile));
     uint32_t *part = c->scan_tmp;
     hipLaunchKernelGGL(scan_reduce_kernel<uint8_t>, dim3(nblk), dim3(kScanThreads), 0, c->stream,
                        flags, n, part);
     BH_LAUNCH_CHECK();
-    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(256), 0, c->stream, part, nblk, count);
-    BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(compact_down_kernel, dim3(nblk), dim3(kScanThreads), 0, c->stream, flags, n,
-                       part, idx);
+                       part, idx, count);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -466,6 +466,36 @@ __device__ __forceinline__ uint32_t next_slot(const WalkArgs &a, uint32_t waves)
     return waves + readfirst(v);
 }
 
+// The opening test of a cell (record w) for the group of centre gc and half-sizes
+// gh: the distance from the group's box to the cell's centre of mass (Eq. (1)),
+// or to the cell's cube (the minimum-distance test), against the cell's radius;
+// o receives the cell's centre of mass relative to the group centre.
+__device__ __forceinline__ bool mac_accept(const WalkArgs &a, const WalkCell &w, uint32_t cell,
+                                           const double4 gc, const float4 gh, bool mindist,
+                                           float &ox, float &oy, float &oz)
+{
+    ox = (float)(w.cx - gc.x);
+    oy = (float)(w.cy - gc.y);
+    oz = (float)(w.cz - gc.z);
+    float dx, dy, dz;
+    if (mindist) {
+        const double4 q = a.geo[cell];
+        const float h = (float)q.w;
+        dx = (fabsf((float)(q.x - gc.x)) - gh.x) - h;
+        dy = (fabsf((float)(q.y - gc.y)) - gh.y) - h;
+        dz = (fabsf((float)(q.z - gc.z)) - gh.z) - h;
+    } else {
+        dx = fabsf(ox) - gh.x;
+        dy = fabsf(oy) - gh.y;
+        dz = fabsf(oz) - gh.z;
+    }
+    const float ux = dx > 0.0f ? dx : 0.0f;
+    const float uy = dy > 0.0f ? dy : 0.0f;
+    const float uz = dz > 0.0f ? dz : 0.0f;
+    const float d2 = (ux * ux + uy * uy) + uz * uz;
+    return d2 > w.rcrit2;
+}
+
 // One group: walk its cluster's tree from the root, evaluate its lists, and
 // write its particles' accelerations and potentials.  M: particles per lane.
 template <bool kEps0, int M>
@@ -507,7 +537,19 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
     const int psz = BH_WALK_PP_FULL ? t.k * (kWave / t.k) : kWave;
     acc.trips = 0;
     int top = 1;
-    if (lane == 0) stack.set(0, cid, 1u);  // the cluster's root
+    {
+        // The cluster's root holds the group, so the opening test opens it (it
+        // is tested all the same, with the loop's arithmetic): its children then
+        // start the stack, which saves the traversal's one-cell first pass.
+        const WalkCell rw = a.rec[cid];
+        float rx, ry, rz;
+        const bool racc = mac_accept(a, rw, cid, gc, gh, mindist, rx, ry, rz);
+        const bool rleaf = (rw.info >> 31) != 0u;
+        if (lane == 0) {
+            if (!racc && !rleaf) stack.set(0, rw.link, rw.info);
+            else stack.set(0, cid, 1u);
+        }
+    }
     wave_sync();
     int pc_n = 0, pp_n = 0;
     uint32_t pend = 0, npp = 0, npc = 0;
@@ -536,28 +578,7 @@ __device__ __forceinline__ void walk_group(const WalkArgs &a, WaveLds &L, CellSt
             w = a.rec[cell];
             link = w.link;
             info = w.info;
-            ox = (float)(w.cx - gc.x);
-            oy = (float)(w.cy - gc.y);
-            oz = (float)(w.cz - gc.z);
-            float dx, dy, dz;
-            if (mindist) {
-                // distance from the group's box to the cell's cube
-                const double4 q = a.geo[cell];
-                const float h = (float)q.w;
-                dx = (fabsf((float)(q.x - gc.x)) - gh.x) - h;
-                dy = (fabsf((float)(q.y - gc.y)) - gh.y) - h;
-                dz = (fabsf((float)(q.z - gc.z)) - gh.z) - h;
-            } else {
-                // distance from the group's box to the cell's centre of mass
-                dx = fabsf(ox) - gh.x;
-                dy = fabsf(oy) - gh.y;
-                dz = fabsf(oz) - gh.z;
-            }
-            const float ux = dx > 0.0f ? dx : 0.0f;
-            const float uy = dy > 0.0f ? dy : 0.0f;
-            const float uz = dz > 0.0f ? dz : 0.0f;
-            const float d2 = (ux * ux + uy * uy) + uz * uz;
-            acc_cell = d2 > w.rcrit2;
+            acc_cell = mac_accept(a, w, cell, gc, gh, mindist, ox, oy, oz);
             leaf = (info >> 31) != 0u;
         }
         // accepted cells -> cell list, staged for evaluation at once (offset

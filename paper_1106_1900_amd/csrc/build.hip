@@ -743,6 +743,11 @@ __device__ __forceinline__ void store_walk_multipole(uint32_t c, const double *S
 // member and are left out of the sums), so a pass costs one memory latency per
 // run instead of one per member; the sums keep the members' order.
 constexpr int kRun = 8;
+// leaves of up to kLeafFast particles load them once for all three sums
+#ifndef BH_LEAF_FAST
+#define BH_LEAF_FAST 8
+#endif
+constexpr int kLeafFast = BH_LEAF_FAST;
 
 template <bool kLeaf, bool kBox>
 __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restrict__ c_first,
@@ -769,25 +774,25 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
     // order of the members does not matter): a leaf's from its particles, a
     // node's as the union of its children's
     double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (kLeaf && n >= 1u && n <= (uint32_t)kRun) {
+    if (kLeaf && n >= 1u && n <= (uint32_t)kLeafFast) {
         // one run: its members are loaded once and serve all three passes, with
         // the operations of the general path below in the same order
-        double4 q[kRun];
+        double4 q[kLeafFast];
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) q[k] = src[s + min((uint32_t)k, n - 1u)];
+        for (int k = 0; k < kLeafFast; ++k) q[k] = src[s + min((uint32_t)k, n - 1u)];
 #pragma unroll
-        for (int k = 0; k < kRun; ++k)
+        for (int k = 0; k < kLeafFast; ++k)
             if ((uint32_t)k < n) M = M + q[k].w;
         if (kBox) {
 #pragma unroll
-            for (int k = 0; k < kRun; ++k) {
+            for (int k = 0; k < kLeafFast; ++k) {
                 blo[0] = fmin(blo[0], q[k].x); bhi[0] = fmax(bhi[0], q[k].x);
                 blo[1] = fmin(blo[1], q[k].y); bhi[1] = fmax(bhi[1], q[k].y);
                 blo[2] = fmin(blo[2], q[k].z); bhi[2] = fmax(bhi[2], q[k].z);
             }
         }
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) {
+        for (int k = 0; k < kLeafFast; ++k) {
             if ((uint32_t)k < n) {
                 sx = sx + q[k].w * q[k].x;
                 sy = sy + q[k].w * q[k].y;
@@ -796,7 +801,7 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
         }
         const double cx = sx / M, cy = sy / M, cz = sz / M;
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) {
+        for (int k = 0; k < kLeafFast; ++k) {
             if ((uint32_t)k < n) {
                 const double dx = q[k].x - cx, dy = q[k].y - cy, dz = q[k].z - cz;
                 const double w = q[k].w;
@@ -821,6 +826,7 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
                     kBox ? blo : nullptr, kBox ? bhi : nullptr, ro);
         return;
     }
+    // masses and first moments in one pass (each sum in the members' order)
     for (uint32_t r = 0; r < n; r += kRun) {
         double4 q[kRun];
 #pragma unroll
@@ -828,6 +834,14 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
 #pragma unroll
         for (int k = 0; k < kRun; ++k)
             if (r + k < n) M = M + q[k].w;
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            if (r + k < n) {
+                sx = sx + q[k].w * q[k].x;
+                sy = sy + q[k].w * q[k].y;
+                sz = sz + q[k].w * q[k].z;
+            }
+        }
         if (kBox && kLeaf) {
 #pragma unroll
             for (int k = 0; k < kRun; ++k) {
@@ -844,19 +858,6 @@ __device__ __forceinline__ void cell_moments(uint32_t c, const uint32_t *__restr
                 blo[0] = fmin(blo[0], b0.x); blo[1] = fmin(blo[1], b0.y);
                 blo[2] = fmin(blo[2], b1.x); bhi[0] = fmax(bhi[0], b1.y);
                 bhi[1] = fmax(bhi[1], b2.x); bhi[2] = fmax(bhi[2], b2.y);
-            }
-        }
-    }
-    for (uint32_t r = 0; r < n; r += kRun) {
-        double4 q[kRun];
-#pragma unroll
-        for (int k = 0; k < kRun; ++k) q[k] = src[s + min(r + k, n - 1)];
-#pragma unroll
-        for (int k = 0; k < kRun; ++k) {
-            if (r + k < n) {
-                sx = sx + q[k].w * q[k].x;
-                sy = sy + q[k].w * q[k].y;
-                sz = sz + q[k].w * q[k].z;
             }
         }
     }

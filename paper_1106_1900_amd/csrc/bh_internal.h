@@ -164,7 +164,7 @@ struct bh_ctx {
 
     // ---- particle buffers (sorted order) ----
     double4 *p4[2] = {nullptr, nullptr};     // x, y, z, mass
-    double4 *v4[2] = {nullptr, nullptr};     // vx, vy, vz, unused
+    double4 *v4[2] = {nullptr, nullptr};     // vx, vy, vz, m (the mass again, for the energy sums)
     uint32_t *pid[2] = {nullptr, nullptr};   // caller index
     float4 *acc4 = nullptr;                  // ax, ay, az, pot (sorted order)
     uint64_t *key[2] = {nullptr, nullptr};   // sort ping-pong

@@ -255,8 +255,9 @@ reorder_from_caller_kernel(const double *__restrict__ pos, const double *__restr
     const double ms = mass[s];
     if (!(ms > 0.0) || !isfinite(ms)) atomicOr(&m->nonfinite, 2u);
     p4[i] = make_double4(pos[3 * s], pos[3 * s + 1], pos[3 * s + 2], ms);
-    v4[i] = vel ? make_double4(vel[3 * s], vel[3 * s + 1], vel[3 * s + 2], 0.0)
-                : make_double4(0.0, 0.0, 0.0, 0.0);
+    // the velocity record carries the mass too (read by the energy sums)
+    v4[i] = vel ? make_double4(vel[3 * s], vel[3 * s + 1], vel[3 * s + 2], ms)
+                : make_double4(0.0, 0.0, 0.0, ms);
     pid[i] = (uint32_t)s;
 }
 

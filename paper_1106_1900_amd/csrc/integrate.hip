@@ -99,25 +99,39 @@ kick_masked_kernel(int64_t n, const uint32_t *__restrict__ pid, const uint8_t *_
 // Px, Py, Pz partial sums of the new state (same order as energy_partial_kernel).
 __global__ void __launch_bounds__(kBlock)
 kick_energy_kernel(const Chunk *__restrict__ chunks, const DevCluster *__restrict__ clus,
-                   const double4 *__restrict__ p4, double4 *__restrict__ v4,
+                   double4 *__restrict__ v4,
                    const float4 *__restrict__ acc4, double *__restrict__ part)
 {
     const Chunk ch = chunks[blockIdx.x];
     const double h = 0.5 * clus[ch.cluster].dt;
     double s[5] = {0, 0, 0, 0, 0};
-    for (uint32_t i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) {
-        const float4 a = acc4[i];
-        double4 v = v4[i];
-        v.x = v.x + (double)a.x * h;
-        v.y = v.y + (double)a.y * h;
-        v.z = v.z + (double)a.z * h;
-        v4[i] = v;
-        const double m = p4[i].w;
-        s[0] += 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
-        s[1] += 0.5 * m * (double)a.w;
-        s[2] += m * v.x;
-        s[3] += m * v.y;
-        s[4] += m * v.z;
+    constexpr int kU = 4;       // particles of a thread in flight at once (same sum order)
+    for (uint32_t i0 = ch.begin + threadIdx.x; i0 < ch.end; i0 += kU * kBlock) {
+        float4 a[kU];
+        double4 v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * kBlock;
+            if (i < ch.end) {
+                a[u] = acc4[i];
+                v[u] = v4[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * kBlock;
+            if (i >= ch.end) continue;
+            v[u].x = v[u].x + (double)a[u].x * h;
+            v[u].y = v[u].y + (double)a[u].y * h;
+            v[u].z = v[u].z + (double)a[u].z * h;
+            v4[i] = v[u];
+            const double m = v[u].w;        // the velocity record carries the mass
+            s[0] += 0.5 * m * ((v[u].x * v[u].x + v[u].y * v[u].y) + v[u].z * v[u].z);
+            s[1] += 0.5 * m * (double)a[u].w;
+            s[2] += m * v[u].x;
+            s[3] += m * v[u].y;
+            s[4] += m * v[u].z;
+        }
     }
     __shared__ double sh[5][kBlock];
 #pragma unroll
@@ -136,15 +150,14 @@ kick_energy_kernel(const Chunk *__restrict__ chunks, const DevCluster *__restric
 // Per chunk: T, W, Px, Py, Pz partial sums (fixed order: strided per thread,
 // then a tree over the block); part[5 chunk + k].
 __global__ void __launch_bounds__(kBlock)
-energy_partial_kernel(const Chunk *__restrict__ chunks, const double4 *__restrict__ p4,
-                      const double4 *__restrict__ v4, const float4 *__restrict__ acc4,
-                      double *__restrict__ part)
+energy_partial_kernel(const Chunk *__restrict__ chunks, const double4 *__restrict__ v4,
+                      const float4 *__restrict__ acc4, double *__restrict__ part)
 {
     const Chunk ch = chunks[blockIdx.x];
     double s[5] = {0, 0, 0, 0, 0};
     for (uint32_t i = ch.begin + threadIdx.x; i < ch.end; i += kBlock) {
-        const double m = p4[i].w;
         const double4 v = v4[i];
+        const double m = v.w;           // the velocity record carries the mass
         s[0] += 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
         s[1] += 0.5 * m * (double)acc4[i].w;
         s[2] += m * v.x;
@@ -193,12 +206,12 @@ energy_final_kernel(const DevCluster *__restrict__ clus, const double *__restric
 
 __global__ void __launch_bounds__(kBlock)
 gather_vel_kernel(int64_t n, const double *__restrict__ vel, const uint32_t *__restrict__ pid,
-                  double4 *__restrict__ v4)
+                  const double4 *__restrict__ p4, double4 *__restrict__ v4)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int64_t o = pid[i];
-    v4[i] = make_double4(vel[3 * o], vel[3 * o + 1], vel[3 * o + 2], 0.0);
+    v4[i] = make_double4(vel[3 * o], vel[3 * o + 1], vel[3 * o + 2], p4[i].w);   // w: the mass
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -267,7 +280,7 @@ hipError_t launch_kick_masked(bh_ctx *c, double dt, const uint8_t *active)
 hipError_t launch_kick_energy(bh_ctx *c)
 {
     hipLaunchKernelGGL(kick_energy_kernel, dim3((unsigned)c->nchunks), dim3(kBlock), 0, c->stream,
-                       c->chunks, c->clus, c->p4[c->cur], c->v4[c->cur], c->acc4, c->e_part);
+                       c->chunks, c->clus, c->v4[c->cur], c->acc4, c->e_part);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(energy_final_kernel, dim3((unsigned)c->K), dim3(kBlock), 0, c->stream,
                        c->clus, c->e_part, c->e_out);
@@ -278,7 +291,7 @@ hipError_t launch_kick_energy(bh_ctx *c)
 hipError_t launch_energy(bh_ctx *c)
 {
     hipLaunchKernelGGL(energy_partial_kernel, dim3((unsigned)c->nchunks), dim3(kBlock), 0, c->stream,
-                       c->chunks, c->p4[c->cur], c->v4[c->cur], c->acc4, c->e_part);
+                       c->chunks, c->v4[c->cur], c->acc4, c->e_part);
     BH_LAUNCH_CHECK();
     hipLaunchKernelGGL(energy_final_kernel, dim3((unsigned)c->K), dim3(kBlock), 0, c->stream,
                        c->clus, c->e_part, c->e_out);
@@ -289,7 +302,7 @@ hipError_t launch_energy(bh_ctx *c)
 hipError_t launch_set_velocities(bh_ctx *c, const double *vel)
 {
     hipLaunchKernelGGL(gather_vel_kernel, dim3(grid_for(c->n)), dim3(kBlock), 0, c->stream, c->n, vel,
-                       c->pid[c->cur], c->v4[c->cur]);
+                       c->pid[c->cur], c->p4[c->cur], c->v4[c->cur]);
     BH_LAUNCH_CHECK();
     return hipSuccess;
 }

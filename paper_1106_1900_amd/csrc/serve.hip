@@ -56,8 +56,8 @@ load_kernel(const double *__restrict__ pos, const double *__restrict__ mass,
     if (i >= n) return;
     p4[dst + i] = make_double4(pos[3 * (size_t)i], pos[3 * (size_t)i + 1], pos[3 * (size_t)i + 2],
                                mass[i]);
-    v4[dst + i] = vel ? make_double4(vel[3 * (size_t)i], vel[3 * (size_t)i + 1], vel[3 * (size_t)i + 2], 0.0)
-                      : make_double4(0.0, 0.0, 0.0, 0.0);
+    v4[dst + i] = vel ? make_double4(vel[3 * (size_t)i], vel[3 * (size_t)i + 1], vel[3 * (size_t)i + 2], mass[i])
+                      : make_double4(0.0, 0.0, 0.0, mass[i]);     // w: the mass
     pid[dst + i] = dst + i;
     accd[dst + i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }

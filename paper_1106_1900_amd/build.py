@@ -28,6 +28,16 @@ HIPFLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 
+# Per-source flags.  The walk is scheduled for instruction-level parallelism: it
+# keeps its 126 VGPRs (four wavefronts per SIMD, no scratch) and walked the
+# 2^20 Plummer sphere 0.4-1.3% faster than with the default strategy (mean walk
+# time of three sets of interleaved A/B runs, 11 pairs); for the other sources the
+# strategy gained nothing and took the leaf-moments kernel from five to four
+# wavefronts per SIMD.
+SOURCE_FLAGS = {
+    "walk.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
+
 
 def hipcc():
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
@@ -49,7 +59,8 @@ def build(verbose=False, extra_flags=(), out=None, objdir=None, srcdir=None):
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [cc, *HIPFLAGS, *extra_flags, "-c", os.path.join(srcdir, src), "-o", obj]
+        cmd = [cc, *HIPFLAGS, *SOURCE_FLAGS.get(src, ()), *extra_flags, "-c", os.path.join(srcdir, src),
+               "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -57,13 +57,16 @@ def log(*a):
 
 
 def walk_source_hash():
+    """Fingerprint of the walk kernel: its source and its compile flags."""
+    from paper_1106_1900_amd.build import SOURCE_FLAGS
     with open(WALK_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+        src = f.read()
+    return hashlib.sha256(src + b"\0" + " ".join(SOURCE_FLAGS.get("walk.hip", ())).encode()).hexdigest()[:16]
 
 
 def measured_traffic():
     """HBM bytes per walk launch from the committed counter runs, if they were taken
-    on the current walk kernel source; None otherwise."""
+    on the current walk kernel (source and compile flags); None otherwise."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)

@@ -90,6 +90,14 @@ def test_state_round_trip_and_rebuild():
     compare_tree(ex, t)
     compare_walk(ex, t, 0.6)
     compare_forces(acc.cpu().numpy(), pot.cpu().numpy(), t, 0.6, 0.01)
+    # energy and momentum sums of the replaced state (Eq. (3)): the velocity records
+    # written by set_state carry the masses the sums read
+    e = ctx.energy()
+    eo = oracle.energy(vel2, m, pot.cpu().numpy().astype(np.float64))
+    assert e[0] == pytest.approx(eo[0], rel=1e-12)
+    assert e[1] == pytest.approx(eo[1], rel=1e-12)
+    assert e[2] == pytest.approx(eo[2], rel=1e-12)
+    assert np.allclose(e[3:6], eo[3:6], rtol=0, atol=1e-15 * np.abs(m[:, None] * vel2).sum())
     ctx.close()
 
 
